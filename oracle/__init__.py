@@ -1,0 +1,269 @@
+"""CPU oracle of the random-walk incomplete LDL^T preconditioner (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may use this package; the product path never imports it.  It shares
+no code with the GPU library: the arithmetic lives in ``srw_oracle.c`` (plain FP64 C,
+one row and one walk at a time) and in ``dense.py`` (numpy closed forms used as pins).
+
+``build_factor`` and ``pcg`` follow Algorithm 1 of the paper: random ordering
+(Section 5.4), walks with rank homes and the exact one-step treatment (Sections 2.2.1
+and 5.2), tallies (Section 3.1), factor entries by eqs. newy / newz / d, the optional
+drop (Section 4), then PCG (Section 6).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "srw_oracle.c")
+_LIB = os.path.join(_HERE, "libsrw_oracle.so")
+
+OK, NOT_CONVERGED, E_ARG, E_NOT_RMATRIX, E_SINGULAR, E_NOMEM = 0, 1, -1, -2, -3, -5
+
+
+def build() -> str:
+    """Compile the oracle with gcc (no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+           "-ffp-contract=off", _SRC, "-o", _LIB, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, u64, i32, dbl = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double
+        L.srwo_philox4x64_10.argtypes = [P, P, P]
+        L.srwo_draw.argtypes = [u64, i64, i64, u64]
+        L.srwo_draw.restype = ctypes.c_uint32
+        L.srwo_rank.argtypes = [i64, u64, P]
+        L.srwo_validate.argtypes = [i64, P, P, P]
+        L.srwo_table.argtypes = [i64, P, P, P, P, P, P, P, P, P, P]
+        L.srwo_walk_rows.argtypes = [i64, P, P, P, P, P, P, P, u64, i64, P, P, P, P, P, P]
+        L.srwo_tally_rows.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.srwo_factor.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, dbl, P, P, P, P]
+        L.srwo_apply.argtypes = [i64, P, P, P, P, P, P, P, P]
+        L.srwo_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, dbl, i32, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ----------------------------------------------------------------------------- RNG
+def philox4x64_10(ctr, key) -> np.ndarray:
+    c = _c(ctr, np.uint64)
+    k = _c(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().srwo_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def draw(seed: int, k: int, w: int, t: int) -> int:
+    return int(lib().srwo_draw(seed, k, w, t))
+
+
+def rank(n: int, seed: int) -> np.ndarray:
+    r = np.zeros(max(n, 1), np.int32)
+    st = lib().srwo_rank(n, seed, _p(r))
+    assert st == OK
+    return r[:n]
+
+
+def validate(A) -> int:
+    return int(lib().srwo_validate(A.n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)),
+                                   _p(_c(A.val, np.float64))))
+
+
+# --------------------------------------------------------------------------- table
+@dataclass
+class Table:
+    nbr: np.ndarray       # int32[nnz - n]
+    thr: np.ndarray       # uint32[nnz - n]
+    mthr: np.ndarray      # uint32[nnz - n]
+    tau: np.ndarray       # float64[n]
+    grounded: np.ndarray  # uint8[n]
+    diag: np.ndarray      # float64[n]
+
+
+def table(A, rk: np.ndarray) -> Table:
+    m = max(A.nnz - A.n, 1)
+    n1 = max(A.n, 1)
+    t = Table(np.zeros(m, np.int32), np.zeros(m, np.uint32), np.zeros(m, np.uint32),
+              np.zeros(n1), np.zeros(n1, np.uint8), np.zeros(n1))
+    lib().srwo_table(A.n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)),
+                     _p(_c(A.val, np.float64)), _p(_c(rk, np.int32)), _p(t.nbr), _p(t.thr),
+                     _p(t.mthr), _p(t.tau), _p(t.grounded), _p(t.diag))
+    return Table(t.nbr[: A.nnz - A.n], t.thr[: A.nnz - A.n], t.mthr[: A.nnz - A.n],
+                 t.tau[: A.n], t.grounded[: A.n], t.diag[: A.n])
+
+
+# --------------------------------------------------------------------------- walks
+@dataclass
+class Walks:
+    rows: np.ndarray      # int64[r]   rows simulated (list order)
+    budget: np.ndarray    # int32[r]   walks simulated per listed row (0 if tau = 0)
+    rec_off: np.ndarray   # int64[r+1] record offsets
+    end: np.ndarray       # int32      end node, -1 = ground
+    visits: np.ndarray    # uint32     stays at the start node, start included
+    length: np.ndarray    # uint32     steps
+
+
+def walk_rows(A, rk, tb: Table, seed: int, rows, budget) -> Walks:
+    rows = _c(rows, np.int64)
+    budget = np.broadcast_to(np.asarray(budget, np.int32), rows.shape).copy()
+    budget[tb.tau[rows] <= 0.0] = 0
+    rec_off = np.zeros(rows.size + 1, np.int64)
+    np.cumsum(budget, out=rec_off[1:])
+    tot = max(int(rec_off[-1]), 1)
+    end = np.zeros(tot, np.int32)
+    vis = np.zeros(tot, np.uint32)
+    ln = np.zeros(tot, np.uint32)
+    st = lib().srwo_walk_rows(A.n, _p(_c(A.rowptr, np.int64)), _p(tb.nbr), _p(tb.thr),
+                              _p(tb.mthr), _p(tb.tau), _p(tb.grounded), _p(_c(rk, np.int32)),
+                              seed, rows.size, _p(rows), _p(budget), _p(rec_off), _p(end),
+                              _p(vis), _p(ln))
+    assert st == OK
+    n = int(rec_off[-1])
+    return Walks(rows, budget, rec_off, end[:n], vis[:n], ln[:n])
+
+
+@dataclass
+class Tallies:
+    walks: np.ndarray     # uint32[r] M'
+    J: np.ndarray         # uint64[r] sum of visits
+    G: np.ndarray         # uint32[r] walks ended at ground
+    steps: np.ndarray     # uint64[r]
+    visits_sq: np.ndarray  # uint64[r]
+    hlen: np.ndarray      # int32[r]  distinct end nodes
+    h_off: np.ndarray     # int64[r]  start of each row's H list (= record offset)
+    h_end: np.ndarray     # int32     end node ids, ascending per row
+    h_cnt: np.ndarray     # uint32    H'_{k,i}
+
+
+def tally(wk: Walks) -> Tallies:
+    r = wk.rows.size
+    count = wk.budget.astype(np.int32)
+    rr = max(r, 1)
+    tot = max(int(wk.rec_off[-1]), 1)
+    t = Tallies(np.zeros(rr, np.uint32), np.zeros(rr, np.uint64), np.zeros(rr, np.uint32),
+                np.zeros(rr, np.uint64), np.zeros(rr, np.uint64), np.zeros(rr, np.int32),
+                wk.rec_off[:-1].copy(), np.zeros(tot, np.int32), np.zeros(tot, np.uint32))
+    end = wk.end if wk.end.size else np.zeros(1, np.int32)
+    vis = wk.visits if wk.visits.size else np.zeros(1, np.uint32)
+    ln = wk.length if wk.length.size else np.zeros(1, np.uint32)
+    lib().srwo_tally_rows(r, _p(count), _p(wk.rec_off), _p(end), _p(vis), _p(ln), _p(t.walks),
+                          _p(t.J), _p(t.G), _p(t.steps), _p(t.visits_sq), _p(t.hlen),
+                          _p(t.h_end), _p(t.h_cnt))
+    return Tallies(t.walks[:r], t.J[:r], t.G[:r], t.steps[:r], t.visits_sq[:r], t.hlen[:r],
+                   t.h_off[:r], t.h_end, t.h_cnt)
+
+
+# -------------------------------------------------------------------------- factor
+@dataclass
+class Factor:
+    n: int
+    rank: np.ndarray      # int32[n]
+    yptr: np.ndarray      # int64[n+1]  rows of Y (node order), strictly lower in rank
+    ycol: np.ndarray      # int32
+    yval: np.ndarray      # float64
+    d: np.ndarray         # float64[n]
+    table: Table | None = None
+    walks: Walks | None = None
+    tallies: Tallies | None = None
+
+    @property
+    def by_rank(self) -> np.ndarray:
+        br = np.empty(self.n, np.int32)
+        br[self.rank] = np.arange(self.n, dtype=np.int32)
+        return br
+
+    def dense_y(self) -> np.ndarray:
+        Y = np.eye(self.n)
+        for k in range(self.n):
+            for q in range(self.yptr[k], self.yptr[k + 1]):
+                Y[k, self.ycol[q]] = self.yval[q]
+        return Y
+
+
+def assemble(A, rk, tb: Table, tl: Tallies, rows: np.ndarray, drop_tol: float) -> Factor:
+    """Factor rows from tallies of the listed rows (all rows when rows = arange(n))."""
+    n = A.n
+    walks = np.zeros(max(n, 1), np.uint32)
+    J = np.zeros(max(n, 1), np.uint64)
+    hlen = np.zeros(max(n, 1), np.int32)
+    h_off = np.zeros(max(n, 1), np.int64)
+    walks[rows] = tl.walks
+    J[rows] = tl.J
+    hlen[rows] = tl.hlen
+    h_off[rows] = tl.h_off
+    yptr = np.zeros(n + 1, np.int64)
+    args = [n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)), _p(_c(A.val, np.float64)),
+            _p(_c(rk, np.int32)), _p(_c(tb.tau if n else np.zeros(1), np.float64)), _p(walks),
+            _p(J), _p(h_off), _p(hlen), _p(tl.h_end), _p(tl.h_cnt), float(drop_tol), _p(yptr)]
+    lib().srwo_factor(*args, None, None, None)
+    nnz = int(yptr[-1])
+    ycol = np.zeros(max(nnz, 1), np.int32)
+    yval = np.zeros(max(nnz, 1))
+    d = np.zeros(max(n, 1))
+    lib().srwo_factor(*args, _p(ycol), _p(yval), _p(d))
+    return Factor(n, np.asarray(rk, np.int32), yptr, ycol[:nnz], yval[:nnz], d[:n], tb)
+
+
+def build_factor(A, walks_per_row, drop_tol: float, seed: int, rk=None) -> Factor:
+    """The whole preconditioning phase of Algorithm 1 on the CPU.  `walks_per_row` is
+    an int (uniform) or an int array over nodes (per-row budgets, each >= 1)."""
+    rk = rank(A.n, seed) if rk is None else np.asarray(rk, np.int32)
+    tb = table(A, rk)
+    rows = np.arange(A.n, dtype=np.int64)
+    wk = walk_rows(A, rk, tb, seed, rows, walks_per_row)
+    tl = tally(wk)
+    F = assemble(A, rk, tb, tl, rows, drop_tol)
+    F.walks, F.tallies = wk, tl
+    return F
+
+
+def apply(F: Factor, r: np.ndarray) -> np.ndarray:
+    z = np.zeros(max(F.n, 1))
+    work = np.zeros(max(F.n, 1))
+    rr = _c(r, np.float64)
+    lib().srwo_apply(F.n, _p(F.yptr), _p(F.ycol if F.ycol.size else np.zeros(1, np.int32)),
+                     _p(F.yval if F.yval.size else np.zeros(1)), _p(F.d), _p(F.by_rank),
+                     _p(rr), _p(z), _p(work))
+    return z[: F.n]
+
+
+def pcg(A, F: Factor | None, b: np.ndarray, tol: float, max_iter: int = 10000):
+    """Returns (status, x, iters, rel_res); F = None runs plain CG."""
+    n = A.n
+    x = np.zeros(max(n, 1))
+    iters = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    bb = _c(b, np.float64)
+    if F is None:
+        y = (None, None, None, None, None)
+    else:
+        y = (_p(F.yptr), _p(F.ycol if F.ycol.size else np.zeros(1, np.int32)),
+             _p(F.yval if F.yval.size else np.zeros(1)), _p(F.d), _p(F.by_rank))
+    st = lib().srwo_pcg(n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)),
+                        _p(_c(A.val, np.float64)), *y, _p(bb), float(tol), int(max_iter),
+                        _p(x), ctypes.byref(iters), ctypes.byref(rel))
+    return int(st), x[:n], int(iters.value), float(rel.value)

@@ -1,0 +1,186 @@
+"""Seeded synthetic R-matrix workloads.
+
+This module only manufactures inputs: symmetric, irreducibly diagonally dominant
+M-matrices ("R-matrices", paper Section 1) in CSR form and right-hand sides.  It
+holds none of the preconditioner's arithmetic, so both the CPU oracle tests and
+the GPU path may use it.
+
+Every generator is deterministic in its seed (numpy ``default_rng``), and the order
+of random draws is fixed: edge conductances in edge order, then the grounded node
+set, then the grounding excess.  Right-hand sides come from an independent stream.
+
+Resistor-network reading (paper Section 2.1): an off-diagonal entry A_kj = -g_kj is
+the conductance between nodes k and j, the diagonal is the sum of incident
+conductances plus a grounding excess e_k >= 0, and a node with e_k > 0 is a path to
+ground (an initial home of the walk game).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class CSR:
+    """Square sparse matrix: int64 rowptr[n+1], int32 col[nnz] (sorted per row,
+    diagonal stored), float64 val[nnz]."""
+
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
+
+    def dense(self) -> np.ndarray:
+        return self.to_scipy().toarray()
+
+
+def assemble(n: int, eu: np.ndarray, ev: np.ndarray, g: np.ndarray, excess: np.ndarray) -> CSR:
+    """Symmetric CSR from an undirected edge list (eu[e], ev[e]) with conductance g[e]
+    and per-node grounding excess; diagonal = incident conductances + excess."""
+    eu = np.asarray(eu, dtype=np.int64)
+    ev = np.asarray(ev, dtype=np.int64)
+    g = np.asarray(g, dtype=np.float64)
+    excess = np.asarray(excess, dtype=np.float64)
+    if eu.size and (np.any(eu == ev) or np.any(g <= 0)):
+        raise ValueError("edges must join distinct nodes with positive conductance")
+    diag = np.bincount(eu, g, minlength=n) + np.bincount(ev, g, minlength=n) + excess
+    rows = np.concatenate([eu, ev, np.arange(n, dtype=np.int64)])
+    cols = np.concatenate([ev, eu, np.arange(n, dtype=np.int64)])
+    vals = np.concatenate([-g, -g, diag])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    if rows.size > 1:
+        dup = (rows[1:] == rows[:-1]) & (cols[1:] == cols[:-1])
+        if np.any(dup):
+            raise ValueError("duplicate edge")
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return CSR(n, rowptr, cols.astype(np.int32), vals.astype(np.float64))
+
+
+def _draw(rng, spec, size):
+    kind, lo, hi = spec
+    if kind == "uniform":
+        return rng.uniform(lo, hi, size)
+    if kind == "loguniform":
+        return np.exp(rng.uniform(np.log(lo), np.log(hi), size))
+    if kind == "const":
+        return np.full(size, float(lo))
+    raise ValueError(kind)
+
+
+def _ground(rng, n, frac, min_count, exc_spec):
+    ng = max(int(round(frac * n)), min_count)
+    ng = min(ng, n)
+    nodes = rng.choice(n, size=ng, replace=False)
+    excess = np.zeros(n)
+    excess[nodes] = _draw(rng, exc_spec, ng)
+    return excess
+
+
+def grid_edges(dims) -> tuple[np.ndarray, np.ndarray]:
+    """Nearest-neighbour edges of a regular grid; node id = x + nx*(y + ny*z).
+    Edges are listed direction by direction (x, then y, then z)."""
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims))
+    ids = np.arange(n, dtype=np.int64).reshape(dims[::-1])  # [z][y][x]
+    us, vs = [], []
+    nd = len(dims)
+    for axis in range(nd):
+        ax = nd - 1 - axis  # numpy axis of this grid direction
+        sl_a = [slice(None)] * nd
+        sl_b = [slice(None)] * nd
+        sl_a[ax] = slice(0, dims[axis] - 1)
+        sl_b[ax] = slice(1, dims[axis])
+        us.append(ids[tuple(sl_a)].ravel())
+        vs.append(ids[tuple(sl_b)].ravel())
+    return np.concatenate(us), np.concatenate(vs)
+
+
+def grid(dims, *, g=("uniform", 0.5, 1.5), ground_frac=0.05, min_ground=1,
+         excess=("uniform", 0.1, 1.0), seed=0) -> CSR:
+    """Resistor grid (2D 5-point or 3D 7-point): conductances drawn per edge,
+    round(ground_frac*n) (at least min_ground) grounded nodes drawn without
+    replacement, each with an excess drawn from `excess`."""
+    rng = np.random.default_rng(seed)
+    eu, ev = grid_edges(dims)
+    n = int(np.prod(dims))
+    gv = _draw(rng, g, eu.size)
+    exc = _ground(rng, n, ground_frac, min_ground, excess)
+    return assemble(n, eu, ev, gv, exc)
+
+
+def laplace3d_dirichlet(m: int) -> CSR:
+    """7-point finite-difference Laplacian on an m^3 interior grid with Dirichlet
+    boundary: diagonal 6, off-diagonal -1 (the paper's m1-m6 family, Section 6)."""
+    eu, ev = grid_edges((m, m, m))
+    n = m ** 3
+    deg = np.bincount(eu, minlength=n) + np.bincount(ev, minlength=n)
+    return assemble(n, eu, ev, np.ones(eu.size), (6 - deg).astype(np.float64))
+
+
+def from_dense(a: np.ndarray) -> CSR:
+    """CSR of a small dense matrix (stored pattern = nonzeros + diagonal)."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    mask = (a != 0) | np.eye(n, dtype=bool)
+    rows, cols = np.nonzero(mask)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return CSR(n, rowptr, cols.astype(np.int32), a[rows, cols].copy())
+
+
+def random_graph(n: int, n_edges: int, *, g=("uniform", 0.1, 10.0), ground_frac=0.05,
+                 min_ground=1, excess=("uniform", 0.1, 1.0), seed=0, connected=True) -> CSR:
+    """Random sparse graph: a random spanning tree (if `connected`) plus extra
+    uniformly random distinct edges; small irregular test inputs."""
+    rng = np.random.default_rng(seed)
+    edges = set()
+    if connected and n > 1:
+        perm = rng.permutation(n)
+        for i in range(1, n):
+            j = perm[rng.integers(0, i)]
+            u, v = int(perm[i]), int(j)
+            edges.add((min(u, v), max(u, v)))
+    target = min(n_edges, n * (n - 1) // 2)
+    while len(edges) < target:
+        u, v = (int(x) for x in rng.integers(0, n, 2))
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    e = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    gv = _draw(rng, g, e.shape[0])
+    exc = _ground(rng, n, ground_frac, min_ground, excess)
+    return assemble(n, e[:, 0], e[:, 1], gv, exc)
+
+
+def rhs(n: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
+    """Right-hand side(s) b ~ N(0, 1), from a stream independent of the matrix."""
+    rng = np.random.default_rng([int(seed), 0x5EED])
+    b = rng.standard_normal((n, nrhs)) if nrhs > 1 else rng.standard_normal(n)
+    return b
+
+
+# --- the named workloads (sizes and distributions of the method's test matrices) ---
+
+def config_grid2d_32(seed: int = 0) -> CSR:
+    """2D 5-point 32x32 resistor grid, g ~ U[0.5, 1.5], 5% grounded (>= 1) with
+    excess ~ U[0.1, 1.0]; n = 1024."""
+    return grid((32, 32), g=("uniform", 0.5, 1.5), ground_frac=0.05,
+                excess=("uniform", 0.1, 1.0), seed=seed)
+
+
+def config_grid3d(m: int = 128, seed: int = 0) -> CSR:
+    """3D 7-point m^3 resistor grid, g log-uniform on [1e-2, 1e2] per edge, 1%
+    grounded with excess ~ U[0.01, 1]; m = 128 gives n = 2,097,152."""
+    return grid((m, m, m), g=("loguniform", 1e-2, 1e2), ground_frac=0.01,
+                excess=("uniform", 0.01, 1.0), seed=seed)

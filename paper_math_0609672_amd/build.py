@@ -1,0 +1,38 @@
+"""Compile libsrw.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libsrw.so")
+SOURCES = ["scan_sort.hip", "build.hip", "solve.hip", "capi.cpp"]
+ARCH = os.environ.get("SRW_OFFLOAD_ARCH", "gfx950")
+
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-ffp-contract=off",
+    # packed FP32 instructions stay off in every kernel
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+]
+
+
+def build(verbose: bool = False) -> str:
+    srcs = []
+    for f in SOURCES:
+        p = os.path.join(CSRC, f)
+        srcs += (["-x", "hip", p] if f.endswith(".cpp") else [p])
+    cmd = ["hipcc"] + FLAGS + srcs + ["-o", LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,1091 @@
+// Preconditioning phase of the hybrid solver (Algorithm 1, "Precondition") on gfx950.
+//
+//   validate      R-matrix check (Section 1) and a path to ground in every connected
+//                 component (Section 2.1), one thread per row + union-find hooking
+//   rank          random ordering (Section 5.4): Philox keys, stable radix sort
+//   table         the walk game of Section 2.1 as 32-bit cumulative thresholds
+//   walk          one lane = one walk; lanes take new walks from a chunk queue as
+//                 theirs end; homes = lower rank or ground (Section 2.2.1); first
+//                 step among higher-ranked neighbours (Section 5.2)
+//   tally         one wave per row: LDS bitonic sort + run-length of end nodes
+//                 (H'_{k,i}), wave sums of stays (J'_k) -- no global atomics
+//   factor        eqs. newy, newz, d and the drop (Sections 3.3, 4, 5.2), FP64
+//   transpose     Y^T by a stable radix sort of the entries on their column
+//   levels        dependency levels of both triangular solves (Kahn frontiers)
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "factor.hpp"
+
+namespace srw {
+
+namespace {
+
+constexpr int BLOCK = 256;
+
+enum : int { ERR_ARG = 1, ERR_NOT_R = 2, ERR_SINGULAR = 4, ERR_LIMIT = 8 };
+
+// ------------------------------------------------------------------- validation
+__global__ void k_check_structure(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
+                                  const int32_t* __restrict__ col, int* err)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && (rowptr[0] != 0 || rowptr[n] != nnz)) atomicOr(err, ERR_ARG);
+    if (k >= n) return;
+    const int64_t r0 = rowptr[k], r1 = rowptr[k + 1];
+    if (r0 < 0 || r1 < r0 || r1 > nnz || r1 - r0 - 1 > (int64_t)DESC_DEG_MASK) {
+        atomicOr(err, ERR_ARG);
+        return;
+    }
+    int ndiag = 0;
+    int32_t prev = -1;
+    for (int64_t p = r0; p < r1; ++p) {
+        const int32_t j = col[p];
+        if (j < 0 || j >= n || j <= prev) {
+            atomicOr(err, ERR_ARG);
+            return;
+        }
+        prev = j;
+        ndiag += (j == k);
+    }
+    if (ndiag != 1) atomicOr(err, ERR_ARG);
+}
+
+// Needs a valid structure.  diag[k] = A_kk, grounded[k] = (e_k > eps a_k) with the
+// excess summed in CSR order.
+__global__ void k_check_values(int64_t n, const int64_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                               uint8_t* __restrict__ grounded, int* err)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t r0 = rowptr[k], r1 = rowptr[k + 1];
+    double a = 0.0;
+    for (int64_t p = r0; p < r1; ++p)
+        if (col[p] == k) a = val[p];
+    int bad = 0;
+    if (!(a > 0.0)) bad = 1;
+    double sum_w = 0.0;
+    for (int64_t p = r0; p < r1 && !bad; ++p) {
+        const int32_t j = col[p];
+        if (j == k) continue;
+        const double v = val[p];
+        if (!(v < 0.0)) {
+            bad = 1;
+            break;
+        }
+        sum_w = sum_w + (-v);
+        int64_t lo = rowptr[j], hi = rowptr[j + 1] - 1, found = -1;
+        while (lo <= hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            const int32_t c = col[mid];
+            if (c == (int32_t)k) {
+                found = mid;
+                break;
+            }
+            if (c < (int32_t)k) lo = mid + 1;
+            else hi = mid - 1;
+        }
+        if (found < 0 || val[found] != v) bad = 1;
+    }
+    if (!bad) {
+        const double e = a - sum_w;
+        if (e < -EXCESS_EPS * a) bad = 1;
+        grounded[k] = (e > EXCESS_EPS * a) ? 1 : 0;
+    } else {
+        grounded[k] = 0;
+    }
+    if (bad) atomicOr(err, ERR_NOT_R);
+}
+
+__device__ __forceinline__ int32_t cc_root(const int32_t* label, int32_t x)
+{
+    for (;;) {
+        const int32_t y = __hip_atomic_load(&label[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (y == x) return x;
+        x = y;
+    }
+}
+
+__global__ void k_cc_init(int64_t n, int32_t* label)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) label[v] = (int32_t)v;
+}
+
+// Hooks the larger of two different roots under the smaller; labels only decrease,
+// so the forest stays acyclic and find terminates.
+__global__ void k_cc_hook(int64_t n, const int64_t* __restrict__ rowptr,
+                          const int32_t* __restrict__ col, int32_t* label, int* changed)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int any = 0;
+    for (int64_t p = rowptr[u]; p < rowptr[u + 1]; ++p) {
+        const int32_t v = col[p];
+        if (v <= u) continue;  // each undirected edge once
+        const int32_t ru = cc_root(label, (int32_t)u), rv = cc_root(label, v);
+        if (ru != rv) {
+            atomicMin(&label[ru > rv ? ru : rv], ru < rv ? ru : rv);
+            any = 1;
+        }
+    }
+    if (any) atomicOr(changed, 1);
+}
+
+__global__ void k_cc_compress(int64_t n, int32_t* label)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) label[v] = cc_root(label, (int32_t)v);
+}
+
+__global__ void k_cc_ground(int64_t n, const int32_t* __restrict__ label,
+                            const uint8_t* __restrict__ grounded, uint8_t* comp)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && grounded[v]) comp[label[v]] = 1;
+}
+
+__global__ void k_cc_check(int64_t n, const int32_t* __restrict__ label,
+                           const uint8_t* __restrict__ comp, int* err)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && label[v] == (int32_t)v && !comp[v]) atomicOr(err, ERR_SINGULAR);
+}
+
+// -------------------------------------------------------------------- ordering
+__global__ void k_rank_keys(int64_t n, uint64_t seed, uint64_t* keys, uint32_t* vals)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const u64x4 b = philox4x64_10(0, 0, (uint64_t)v, STREAM_ORDER, seed, 0);
+    keys[v] = b.x0;
+    vals[v] = (uint32_t)v;
+}
+
+__global__ void k_rank_scatter(int64_t n, const uint32_t* __restrict__ sorted, int32_t* rank,
+                               int32_t* by_rank)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t v = sorted[p];
+    by_rank[p] = (int32_t)v;
+    rank[v] = (int32_t)p;
+}
+
+__global__ void k_rank_given(int64_t n, const int32_t* __restrict__ given, int32_t* rank,
+                             int32_t* by_rank, int32_t* seen, int* err)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t r = given[v];
+    if (r < 0 || r >= n || atomicAdd(&seen[r], 1) != 0) {
+        atomicOr(err, ERR_ARG);
+        return;
+    }
+    rank[v] = r;
+    by_rank[r] = (int32_t)v;
+}
+
+// ----------------------------------------------------------------------- table
+// Node descriptor: x = first off-diagonal entry of the row, y = degree | grounded
+// flag, z = rank, w = index (within the row) of the last higher-ranked neighbour.
+__global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
+                        const int32_t* __restrict__ col, const double* __restrict__ val,
+                        const int32_t* __restrict__ rank, const uint8_t* __restrict__ grounded,
+                        int32_t walks_per_row, const int32_t* __restrict__ budget_in,
+                        uint2* __restrict__ ent, uint32_t* __restrict__ mthr,
+                        uint4* __restrict__ desc, double* __restrict__ tau,
+                        int32_t* __restrict__ budget, int32_t* max_budget)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t r0 = rowptr[v], r1 = rowptr[v + 1];
+    const int32_t rv = rank[v];
+    double a = 0.0, motel = 0.0;
+    for (int64_t p = r0; p < r1; ++p) {
+        const int32_t j = col[p];
+        if (j == v) a = val[p];
+        else if (rank[j] > rv) motel = motel + (-val[p]);
+    }
+    const int64_t start = r0 - v;
+    double c = 0.0, cm = 0.0;
+    uint32_t m = 0, last_motel = 0;
+    for (int64_t p = r0; p < r1; ++p) {
+        const int32_t j = col[p];
+        if (j == v) continue;
+        const double w = -val[p];
+        c = c + w;
+        const bool is_motel = rank[j] > rv;
+        if (is_motel) {
+            cm = cm + w;
+            last_motel = m;
+        }
+        ent[start + m] = make_uint2((uint32_t)j, threshold32(c, a));
+        mthr[start + m] = motel > 0.0 ? threshold32(cm, motel) : 0u;
+        ++m;
+    }
+    const uint32_t flags = grounded[v] ? DESC_GROUNDED : 0u;
+    desc[v] = make_uint4((uint32_t)start, m | flags, (uint32_t)rv, last_motel);
+    tau[v] = motel / a;
+    int32_t b = 0;
+    if (motel > 0.0) {
+        b = budget_in ? budget_in[v] : walks_per_row;
+        if (b < 1) b = 1;
+        atomicMax(max_budget, b);
+    }
+    budget[v] = b;
+}
+
+// ------------------------------------------------------------- walk schedule
+__global__ void k_flag_walking(int64_t n, const int32_t* __restrict__ by_rank,
+                               const int32_t* __restrict__ budget, int32_t* flag)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) flag[p] = budget[by_rank[p]] > 0 ? 1 : 0;
+}
+
+__global__ void k_compact_order(int64_t n, const int32_t* __restrict__ by_rank,
+                                const int32_t* __restrict__ budget,
+                                const int64_t* __restrict__ pos, int32_t* order,
+                                int32_t* chunks)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t v = by_rank[p];
+    const int32_t b = budget[v];
+    if (b > 0) {
+        order[pos[p]] = v;
+        chunks[pos[p]] = (b + SRW_WAVE - 1) / SRW_WAVE;
+    }
+}
+
+__global__ void k_read_last(const int64_t* scan, const int32_t* last_in, int64_t n, int64_t* out)
+{
+    out[0] = n > 0 ? scan[n - 1] + (int64_t)last_in[n - 1] : 0;
+}
+
+// ----------------------------------------------------------------------- walks
+struct WalkArgs {
+    const uint4* desc;
+    const uint2* ent;
+    const uint32_t* mthr;
+    const int32_t* order;
+    const int64_t* chunk_off;
+    const int32_t* budget;
+    const int64_t* rec_off;
+    int64_t norder;
+    uint64_t n_chunks;
+    uint64_t seed;
+    uint64_t max_steps;
+    uint32_t* rec_end;
+    uint32_t* rec_vis;
+    uint32_t* rec_len;
+    unsigned long long* queue;
+    int* err;
+};
+
+// Persistent walk kernel.  Every wave owns up to 64 walks at a time, one per lane.
+// Every R steps the idle lanes of a wave take the next walks of the current chunk
+// (up to 64 walks of one row); an exhausted chunk is replaced by the next one from
+// a global queue ordered by rank (longest walks first).  A lane's draws come from
+// the Philox block of its (row, walk, step div 8), generated when step mod 8 = 0.
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
+{
+    const int lane = __lane_id();
+    const uint64_t lt = lanemask_lt();
+    // wave-uniform chunk state
+    uint32_t c_row = 0, c_next = 0, c_end = 0;
+    bool done = false;
+    // per-lane walk state
+    bool active = false;
+    uint32_t k = 0, w = 0, visits = 0, rank_k = 0, last_motel = 0;
+    uint32_t cs = 0, cd = 0;  // current node: first entry, degree | flags
+    uint64_t t = 0, rec = 0;
+    uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0, q7 = 0;
+
+    for (uint32_t iter = 0;; ++iter) {
+        if ((iter % R) == 0 && !done) {
+            uint64_t idle = ballot(!active);
+            while (idle != 0) {
+                if (c_next >= c_end) {
+                    unsigned long long c = 0;
+                    if (lane == 0) c = atomicAdd(a.queue, 1ull);
+                    c = __shfl(c, 0, 64);
+                    if (c >= a.n_chunks) {
+                        done = true;
+                        break;
+                    }
+                    int64_t lo = 0, hi = a.norder - 1;
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi + 1) >> 1;
+                        if ((unsigned long long)a.chunk_off[mid] <= c) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    c_row = (uint32_t)a.order[lo];
+                    c_next = (uint32_t)(c - (unsigned long long)a.chunk_off[lo]) * SRW_WAVE;
+                    c_end = min(c_next + SRW_WAVE, (uint32_t)a.budget[c_row]);
+                }
+                const uint32_t avail = c_end - c_next;
+                const uint32_t pos = (uint32_t)__popcll(idle & lt);
+                const bool take = ((idle >> lane) & 1ull) && pos < avail;
+                if (take) {
+                    k = c_row;
+                    w = c_next + pos;
+                    t = 0;
+                    visits = 1;
+                    active = true;
+                    const uint4 dk = a.desc[k];
+                    cs = dk.x;
+                    cd = dk.y;
+                    rank_k = dk.z;
+                    last_motel = dk.w;
+                    rec = (uint64_t)a.rec_off[k] + w;
+                }
+                const uint64_t taken = ballot(take);
+                c_next += (uint32_t)__popcll(taken);
+                idle &= ~taken;
+            }
+        }
+        if (ballot(active) == 0) {
+            if (done) break;
+            continue;
+        }
+        if (!active) continue;
+
+        if ((t & 7) == 0) {
+            const u64x4 b = philox4x64_10(t >> 3, w, k, STREAM_WALK, a.seed, 0);
+            q0 = (uint32_t)b.x0; q1 = (uint32_t)(b.x0 >> 32);
+            q2 = (uint32_t)b.x1; q3 = (uint32_t)(b.x1 >> 32);
+            q4 = (uint32_t)b.x2; q5 = (uint32_t)(b.x2 >> 32);
+            q6 = (uint32_t)b.x3; q7 = (uint32_t)(b.x3 >> 32);
+        }
+        const uint32_t u = q0;
+        q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
+
+        const uint32_t deg = cd & DESC_DEG_MASK;
+        uint32_t nxt = 0;
+        bool to_ground = false;
+        if (t == 0) {
+            // first step: among higher-ranked neighbours of k (exact one-step part)
+            uint32_t sel = last_motel;
+            for (uint32_t m = 0; m < deg; ++m)
+                if (u < a.mthr[cs + m]) {
+                    sel = m;
+                    break;
+                }
+            nxt = a.ent[cs + sel].x;
+        } else {
+            bool found = false;
+            uint32_t lastx = 0;
+            for (uint32_t m0 = 0; m0 < deg; m0 += 8) {
+                uint2 e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    e[j] = (m0 + j < deg) ? a.ent[cs + m0 + j] : make_uint2(0u, 0u);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (m0 + j < deg) {
+                        if (!found && u < e[j].y) {
+                            found = true;
+                            nxt = e[j].x;
+                        }
+                        lastx = e[j].x;
+                    }
+                }
+                if (found) break;
+            }
+            if (!found) {
+                if (cd & DESC_GROUNDED) to_ground = true;
+                else nxt = lastx;
+            }
+        }
+        bool fin = false;
+        uint32_t endv = 0;
+        if (to_ground) {
+            fin = true;
+            endv = END_GROUND;
+        } else {
+            const uint4 dn = a.desc[nxt];
+            if (t > 0 && dn.z < rank_k) {
+                fin = true;
+                endv = nxt;
+            } else {
+                visits += (nxt == k);
+                cs = dn.x;
+                cd = dn.y;
+            }
+        }
+        ++t;
+        if (!fin && t >= a.max_steps) {
+            fin = true;
+            endv = END_LIMIT;
+            atomicOr(a.err, ERR_LIMIT);
+        }
+        if (fin) {
+            a.rec_end[rec] = endv;
+            a.rec_vis[rec] = visits;
+            a.rec_len[rec] = (uint32_t)t;
+            active = false;
+        }
+    }
+}
+
+// --------------------------------------------------------------------- tallies
+// One wave per row.  LDS: P sort keys (P = power of two >= budget) + P+1 run heads.
+__global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restrict__ budget,
+                                              const int64_t* __restrict__ rec_off,
+                                              const uint32_t* rec_end,
+                                              const uint32_t* rec_vis,
+                                              const uint32_t* __restrict__ rec_len, int P,
+                                              uint64_t* __restrict__ J, uint32_t* __restrict__ G,
+                                              uint64_t* __restrict__ steps,
+                                              uint64_t* __restrict__ vsq,
+                                              int32_t* __restrict__ hlen, uint32_t* h_end,
+                                              uint32_t* h_cnt)
+{
+    extern __shared__ uint32_t lds[];
+    uint32_t* key = lds;
+    uint32_t* head = lds + P;
+    const int64_t k = blockIdx.x;
+    if (k >= n) return;
+    const int m = budget[k];
+    const int lane = threadIdx.x;
+    if (m == 0) {  // exact row: no walks
+        if (lane == 0) {
+            J[k] = 0;
+            G[k] = 0;
+            steps[k] = 0;
+            vsq[k] = 0;
+            hlen[k] = 0;
+        }
+        return;
+    }
+    const int64_t base = rec_off[k];
+    uint64_t jv = 0, sl = 0, vq = 0;
+    uint32_t g = 0;
+    for (int i = lane; i < P; i += 64) {
+        uint32_t e = END_GROUND;
+        if (i < m) {
+            e = rec_end[base + i];
+            const uint64_t v = rec_vis[base + i];
+            jv += v;
+            vq += v * v;
+            sl += rec_len[base + i];
+            g += (e == END_GROUND);
+        }
+        key[i] = e;
+    }
+    jv = wave_sum(jv);
+    vq = wave_sum(vq);
+    sl = wave_sum(sl);
+    g = wave_sum(g);
+    __syncthreads();
+    // bitonic sort, ascending (ground markers sort last)
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = lane; i < (P >> 1); i += 64) {
+                const int lo = 2 * stride * (i / stride) + (i % stride);
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint32_t x = key[lo], y = key[hi];
+                if ((x > y) == asc) {
+                    key[lo] = y;
+                    key[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // run heads over the m - g walks that ended at a node
+    const int nb = m - (int)g;
+    const uint64_t lt = lanemask_lt();
+    int run = 0;
+    for (int i0 = 0; i0 < nb; i0 += 64) {
+        const int i = i0 + lane;
+        const bool h = i < nb && (i == 0 || key[i] != key[i - 1]);
+        const uint64_t mask = ballot(h);
+        if (h) head[run + __popcll(mask & lt)] = (uint32_t)i;
+        run += __popcll(mask);
+    }
+    if (lane == 0) head[run] = (uint32_t)nb;
+    __syncthreads();
+    for (int j = lane; j < run; j += 64) {
+        h_end[base + j] = key[head[j]];
+        h_cnt[base + j] = head[j + 1] - head[j];
+    }
+    if (lane == 0) {
+        J[k] = jv;
+        G[k] = g;
+        steps[k] = sl;
+        vsq[k] = vq;
+        hlen[k] = run;
+    }
+}
+
+// ---------------------------------------------------------------------- factor
+// Row k: merge of the lower-ranked neighbours (CSR order) and the end nodes of
+// its walks (ascending), evaluated in FP64 exactly as written, no contraction:
+//   Y_ki = -((w_ki / a) + (tau * (H / M))),  D_k = a / (1 + tau * ((J / M) - 1)).
+template <typename T, bool FILL>
+__global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
+                         const int32_t* __restrict__ col, const double* __restrict__ val,
+                         const int32_t* __restrict__ rank, const double* __restrict__ tau,
+                         const int32_t* __restrict__ budget, const uint64_t* __restrict__ J,
+                         const int64_t* __restrict__ h_off, const int32_t* __restrict__ hlen,
+                         const uint32_t* __restrict__ h_end, const uint32_t* __restrict__ h_cnt,
+                         double drop_tol, int32_t* __restrict__ ynnz,
+                         const int64_t* __restrict__ yptr, int32_t* __restrict__ ycol,
+                         T* __restrict__ yval, T* __restrict__ dout)
+{
+#pragma clang fp contract(off)
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t r0 = rowptr[k], r1 = rowptr[k + 1];
+    const int32_t rk = rank[k];
+    double a = 0.0;
+    for (int64_t p = r0; p < r1; ++p)
+        if (col[p] == k) a = val[p];
+    const double tk = tau[k];
+    const uint32_t M = (uint32_t)budget[k];
+    const int32_t H = M ? hlen[k] : 0;
+    const int64_t hb = M ? h_off[k] : 0;
+    int64_t p = r0;
+    int32_t h = 0;
+    int64_t kept = 0;
+    const int64_t out0 = FILL ? yptr[k] : 0;
+    for (;;) {
+        while (p < r1 && (col[p] == k || rank[col[p]] > rk)) ++p;
+        const uint32_t ci = p < r1 ? (uint32_t)col[p] : 0xFFFFFFFFu;
+        const uint32_t ch = h < H ? h_end[hb + h] : 0xFFFFFFFFu;
+        if (ci == 0xFFFFFFFFu && ch == 0xFFFFFFFFu) break;
+        const uint32_t i = ci < ch ? ci : ch;
+        double w = 0.0;
+        uint32_t cnt = 0;
+        if (ci == i) {
+            w = -val[p];
+            ++p;
+        }
+        if (ch == i) {
+            cnt = h_cnt[hb + h];
+            ++h;
+        }
+        const double hfrac = M > 0 ? (double)cnt / (double)M : 0.0;
+        const double y = -((w / a) + (tk * hfrac));
+        if (!(fabs(y) < drop_tol)) {
+            if (FILL) {
+                ycol[out0 + kept] = (int32_t)i;
+                yval[out0 + kept] = (T)y;
+            }
+            ++kept;
+        }
+    }
+    if (FILL) {
+        double dk = a;
+        if (M > 0) {
+            const double mbar = (double)J[k] / (double)M;
+            dk = a / (1.0 + tk * (mbar - 1.0));
+        }
+        dout[k] = (T)dk;
+    } else {
+        ynnz[k] = (int32_t)kept;
+    }
+}
+
+// ------------------------------------------------------------------- transpose
+__global__ void k_entry_rows(int64_t n, const int64_t* __restrict__ yptr, uint32_t* rowid,
+                             uint32_t* idx)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    for (int64_t q = yptr[k]; q < yptr[k + 1]; ++q) {
+        rowid[q] = (uint32_t)k;
+        idx[q] = (uint32_t)q;
+    }
+}
+
+__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ ycol, int32_t* cnt)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) atomicAdd(&cnt[ycol[q]], 1);
+}
+
+template <typename T>
+__global__ void k_transpose_fill(int64_t nnz, const uint32_t* __restrict__ sorted_idx,
+                                 const uint32_t* __restrict__ rowid, const T* __restrict__ yval,
+                                 int32_t* __restrict__ ytcol, T* __restrict__ ytval)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nnz) return;
+    const uint32_t q = sorted_idx[j];
+    ytcol[j] = (int32_t)rowid[q];
+    ytval[j] = yval[q];
+}
+
+__global__ void k_set_last(int64_t* ptr, int64_t n, int64_t v) { ptr[n] = v; }
+
+// ---------------------------------------------------------------------- levels
+__global__ void k_indeg(int64_t n, const int64_t* __restrict__ ptr, int32_t* indeg)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) indeg[v] = (int32_t)(ptr[v + 1] - ptr[v]);
+}
+
+__global__ void k_frontier0(int64_t n, const int32_t* __restrict__ indeg, int32_t* queue,
+                            unsigned long long* tail)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && indeg[v] == 0) queue[atomicAdd(tail, 1ull)] = (int32_t)v;
+}
+
+// Releases the dependents of one level; a dependent whose last dependency this was
+// joins the next level.
+__global__ void k_kahn(const int32_t* __restrict__ queue_in, int64_t qs, int64_t qe,
+                       const int64_t* __restrict__ dptr, const int32_t* __restrict__ dcol,
+                       int32_t* indeg, int32_t* queue, unsigned long long* tail)
+{
+    const int64_t i = qs + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= qe) return;
+    const int32_t v = queue_in[i];
+    for (int64_t q = dptr[v]; q < dptr[v + 1]; ++q) {
+        const int32_t u = dcol[q];
+        if (atomicSub(&indeg[u], 1) == 1) queue[atomicAdd(tail, 1ull)] = u;
+    }
+}
+
+__global__ void k_sum_u64(int64_t n, const uint64_t* __restrict__ x, unsigned long long* out)
+{
+    uint64_t s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s += x[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (unsigned long long)s);
+}
+
+int map_err(int e)
+{
+    if (e & ERR_ARG) return SRW_E_ARG;
+    if (e & ERR_NOT_R) return SRW_E_NOT_RMATRIX;
+    if (e & ERR_SINGULAR) return SRW_E_SINGULAR;
+    if (e & ERR_LIMIT) return SRW_E_WALK_LIMIT;
+    return SRW_OK;
+}
+
+// Dependency levels of a unit-triangular solve.  deps(v) = row v of (dptr, dcol)'s
+// transpose... expressed as: indeg(v) = #entries of row v in (rptr); dependents(v) =
+// row v of (dptr, dcol).
+int levels(int64_t n, const int64_t* rptr, const int64_t* dptr, const int32_t* dcol,
+           int32_t* queue, std::vector<int64_t>& lptr, Arena& tmp, int64_t* pinned,
+           hipStream_t s)
+{
+    int32_t* indeg = tmp.alloc<int32_t>(n);
+    unsigned long long* tail = tmp.alloc<unsigned long long>(1);
+    if (!indeg || !tail) return SRW_E_NOMEM;
+    const int g = grid_for(n, BLOCK);
+    k_indeg<<<g, BLOCK, 0, s>>>(n, rptr, indeg);
+    SRW_HIP(hipMemsetAsync(tail, 0, sizeof(unsigned long long), s));
+    k_frontier0<<<g, BLOCK, 0, s>>>(n, indeg, queue, tail);
+    lptr.assign(1, 0);
+    int64_t qs = 0;
+    for (;;) {
+        SRW_HIP(hipMemcpyAsync(pinned, tail, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SRW_HIP(hipStreamSynchronize(s));
+        const int64_t qe = pinned[0];
+        if (qe == qs) break;
+        lptr.push_back(qe);
+        if (qe >= n) break;
+        k_kahn<<<grid_for(qe - qs, BLOCK), BLOCK, 0, s>>>(queue, qs, qe, dptr, dcol, indeg, queue,
+                                                         tail);
+        SRW_HIP(hipGetLastError());
+        qs = qe;
+    }
+    if (lptr.back() != n) return SRW_E_HIP;  // a cycle cannot occur in a triangular factor
+    return SRW_OK;
+}
+
+}  // namespace
+
+int hip_fail(hipError_t e, const char* what)
+{
+    (void)what;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SRW_E_NOMEM;
+    return SRW_E_HIP;
+}
+
+void free_factor(srw_factor* F)
+{
+    if (!F) return;
+    for (void* p : F->allocations) (void)hipFree(p);
+    if (F->host_scalars) (void)hipHostFree(F->host_scalars);
+    delete F;
+}
+
+int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
+                      const srw_options* opt_in, srw_factor** out, hipStream_t s)
+{
+    srw_options opt;
+    srw_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.max_steps == 0) opt.max_steps = 1ull << 24;
+    if (opt.refill_period == 0) opt.refill_period = 1;
+    const int64_t n = A->n, nnz = A->nnz;
+    const int64_t nnz_off = nnz - n;
+
+    srw_factor* F = new srw_factor();
+    F->n = n;
+    F->nnz_a = nnz;
+    F->precision = opt.factor_precision;
+    F->keep = opt.keep;
+    Arena keep;  // blocks that end up owned by F
+    Arena tmp;   // build temporaries
+    int64_t* pinned = nullptr;
+    int status = SRW_OK;
+    const bool fp32 = opt.factor_precision == SRW_FP32;
+    const size_t vbytes = fp32 ? sizeof(float) : sizeof(double);
+
+#define FAIL(code)           \
+    do {                     \
+        status = (code);     \
+        goto done;           \
+    } while (0)
+#define CHECK_HIP(call)                                  \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) FAIL(hip_fail(e_, #call)); \
+    } while (0)
+#define ALLOC(arena, T, cnt) (arena).alloc<T>(cnt)
+
+    {
+        CHECK_HIP(hipHostMalloc((void**)&pinned, 8 * sizeof(int64_t), hipHostMallocDefault));
+        const int g = grid_for(n, BLOCK);
+        int* err = ALLOC(tmp, int, 1);
+        int* changed = ALLOC(tmp, int, 1);
+        uint8_t* grounded = ALLOC(keep, uint8_t, n);
+        int32_t* label = ALLOC(tmp, int32_t, n);
+        uint8_t* comp = ALLOC(tmp, uint8_t, n);
+        F->rank = ALLOC(keep, int32_t, n);
+        F->by_rank = ALLOC(keep, int32_t, n);
+        F->yptr = ALLOC(keep, int64_t, n + 1);
+        F->ytptr = ALLOC(keep, int64_t, n + 1);
+        if (!err || !changed || !grounded || !label || !comp || !F->rank || !F->by_rank ||
+            !F->yptr || !F->ytptr)
+            FAIL(SRW_E_NOMEM);
+        F->grounded = grounded;
+
+        // ---- 1. validation
+        CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+        k_check_structure<<<g, BLOCK, 0, s>>>(n, nnz, A->rowptr, A->col, err);
+        CHECK_HIP(hipGetLastError());
+        int herr = 0;
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], err, sizeof(int), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        std::memcpy(&herr, &pinned[0], sizeof(int));
+        if (herr) FAIL(map_err(herr));
+        if (nnz_off >= (int64_t)0xFFFFFFFFll) FAIL(SRW_E_ARG);
+        k_check_values<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, grounded, err);
+        k_cc_init<<<g, BLOCK, 0, s>>>(n, label);
+        for (int it = 0; it < 64 * 64; ++it) {
+            CHECK_HIP(hipMemsetAsync(changed, 0, sizeof(int), s));
+            k_cc_hook<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, label, changed);
+            k_cc_compress<<<g, BLOCK, 0, s>>>(n, label);
+            CHECK_HIP(hipMemcpyAsync(&pinned[1], changed, sizeof(int), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            int ch = 0;
+            std::memcpy(&ch, &pinned[1], sizeof(int));
+            if (!ch) break;
+        }
+        CHECK_HIP(hipMemsetAsync(comp, 0, n, s));
+        k_cc_ground<<<g, BLOCK, 0, s>>>(n, label, grounded, comp);
+        k_cc_check<<<g, BLOCK, 0, s>>>(n, label, comp, err);
+        CHECK_HIP(hipGetLastError());
+
+        // ---- 2. ordering
+        if (opt.ordering == SRW_ORDER_GIVEN) {
+            if (!opt.rank) FAIL(SRW_E_ARG);
+            int32_t* seen = ALLOC(tmp, int32_t, n);
+            if (!seen) FAIL(SRW_E_NOMEM);
+            CHECK_HIP(hipMemsetAsync(seen, 0, n * sizeof(int32_t), s));
+            k_rank_given<<<g, BLOCK, 0, s>>>(n, opt.rank, F->rank, F->by_rank, seen, err);
+        } else {
+            uint64_t* keys = ALLOC(tmp, uint64_t, n);
+            uint64_t* keys2 = ALLOC(tmp, uint64_t, n);
+            uint32_t* vals = ALLOC(tmp, uint32_t, n);
+            uint32_t* vals2 = ALLOC(tmp, uint32_t, n);
+            void* rt = ALLOC(tmp, char, radix_tmp_bytes(n));
+            if (!keys || !keys2 || !vals || !vals2 || !rt) FAIL(SRW_E_NOMEM);
+            k_rank_keys<<<g, BLOCK, 0, s>>>(n, seed, keys, vals);
+            uint64_t* ko;
+            uint32_t* vo;
+            CHECK_HIP(radix_sort_u64(keys, vals, keys2, vals2, n, 64, rt, &ko, &vo, s));
+            k_rank_scatter<<<g, BLOCK, 0, s>>>(n, vo, F->rank, F->by_rank);
+        }
+        CHECK_HIP(hipGetLastError());
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], err, sizeof(int), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        std::memcpy(&herr, &pinned[0], sizeof(int));
+        if (herr) FAIL(map_err(herr));
+
+        // ---- 3. transition table and walk budgets
+        uint2* ent = ALLOC(keep, uint2, nnz_off);
+        uint32_t* mthr = ALLOC(keep, uint32_t, nnz_off);
+        uint4* desc = ALLOC(tmp, uint4, n);
+        double* tau = ALLOC(keep, double, n);
+        int32_t* budget = ALLOC(keep, int32_t, n);
+        int32_t* maxb = ALLOC(tmp, int32_t, 1);
+        if (!ent || !mthr || !desc || !tau || !budget || !maxb) FAIL(SRW_E_NOMEM);
+        F->ent = ent;
+        F->mthr = mthr;
+        F->tau = tau;
+        F->budget = budget;
+        CHECK_HIP(hipMemsetAsync(maxb, 0, sizeof(int32_t), s));
+        k_table<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, grounded, walks_per_row,
+                                    opt.walks, ent, mthr, desc, tau, budget, maxb);
+        CHECK_HIP(hipGetLastError());
+
+        // record offsets (node order) and the rank-ordered list of walking rows
+        int64_t* rec_off = ALLOC(keep, int64_t, n);
+        int32_t* flag = ALLOC(tmp, int32_t, n);
+        int64_t* pos = ALLOC(tmp, int64_t, n);
+        int32_t* order = ALLOC(tmp, int32_t, n);
+        int32_t* chunks = ALLOC(tmp, int32_t, n);
+        int64_t* chunk_off = ALLOC(tmp, int64_t, n + 1);
+        int64_t* tot = ALLOC(tmp, int64_t, 4);
+        void* st = ALLOC(tmp, char, scan_tmp_bytes(n + 1));
+        if (!rec_off || !flag || !pos || !order || !chunks || !chunk_off || !tot || !st)
+            FAIL(SRW_E_NOMEM);
+        F->rec_off = rec_off;
+        CHECK_HIP(exclusive_scan_i32_to_i64(budget, rec_off, n, st, s));
+        k_read_last<<<1, 1, 0, s>>>(rec_off, budget, n, tot + 0);
+        k_flag_walking<<<g, BLOCK, 0, s>>>(n, F->by_rank, budget, flag);
+        CHECK_HIP(exclusive_scan_i32_to_i64(flag, pos, n, st, s));
+        k_read_last<<<1, 1, 0, s>>>(pos, flag, n, tot + 1);
+        k_compact_order<<<g, BLOCK, 0, s>>>(n, F->by_rank, budget, pos, order, chunks);
+        CHECK_HIP(hipGetLastError());
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipMemcpyAsync(&pinned[2], maxb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        const int64_t total_walks = pinned[0];
+        const int64_t norder = pinned[1];
+        int32_t max_budget = 0;
+        std::memcpy(&max_budget, &pinned[2], sizeof(int32_t));
+        CHECK_HIP(exclusive_scan_i32_to_i64(chunks, chunk_off, norder, st, s));
+        k_read_last<<<1, 1, 0, s>>>(chunk_off, chunks, norder, tot + 2);
+        CHECK_HIP(hipMemcpyAsync(&pinned[3], tot + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        const int64_t n_chunks = pinned[3];
+        F->walks_total = total_walks;
+
+        // ---- 4. walks
+        uint32_t* rec_end = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
+        uint32_t* rec_vis = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
+        uint32_t* rec_len = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
+        unsigned long long* queue = ALLOC(tmp, unsigned long long, 1);
+        if (!rec_end || !rec_vis || !rec_len || !queue) FAIL(SRW_E_NOMEM);
+        if (opt.keep >= 2) {
+            F->rec_end = rec_end;
+            F->rec_vis = rec_vis;
+            F->rec_len = rec_len;
+        }
+        if (n_chunks > 0) {
+            CHECK_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned long long), s));
+            WalkArgs wa;
+            wa.desc = desc;
+            wa.ent = ent;
+            wa.mthr = mthr;
+            wa.order = order;
+            wa.chunk_off = chunk_off;
+            wa.budget = budget;
+            wa.rec_off = rec_off;
+            wa.norder = norder;
+            wa.n_chunks = (uint64_t)n_chunks;
+            wa.seed = seed;
+            wa.max_steps = opt.max_steps;
+            wa.rec_end = rec_end;
+            wa.rec_vis = rec_vis;
+            wa.rec_len = rec_len;
+            wa.queue = queue;
+            wa.err = err;
+            int dev = 0, cus = 0;
+            CHECK_HIP(hipGetDevice(&dev));
+            CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            int64_t waves_needed = n_chunks;
+            int64_t blocks = (int64_t)cus * 8;
+            blocks = std::min<int64_t>(blocks, (waves_needed + BLOCK / 64 - 1) / (BLOCK / 64));
+            if (blocks < 1) blocks = 1;
+            switch (opt.refill_period) {
+                case 2: k_walk<2><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
+                case 4: k_walk<4><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
+                case 8: k_walk<8><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
+                default: k_walk<1><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
+            }
+            CHECK_HIP(hipGetLastError());
+        }
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], err, sizeof(int), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        std::memcpy(&herr, &pinned[0], sizeof(int));
+        if (herr) FAIL(map_err(herr));
+
+        // ---- 5. tallies
+        uint64_t* tJ = ALLOC(keep, uint64_t, n);
+        uint32_t* tG = ALLOC(keep, uint32_t, n);
+        uint64_t* tsteps = ALLOC(keep, uint64_t, n);
+        uint64_t* tvsq = ALLOC(keep, uint64_t, n);
+        int32_t* hlen = ALLOC(keep, int32_t, n);
+        // the H lists overwrite the records of their own row in place unless the
+        // records or the lists outlive the build
+        uint32_t* h_end = rec_end;
+        uint32_t* h_cnt = rec_vis;
+        if (opt.keep >= 1) {
+            h_end = ALLOC(keep, uint32_t, total_walks);
+            h_cnt = ALLOC(keep, uint32_t, total_walks);
+        }
+        if (!tJ || !tG || !tsteps || !tvsq || !hlen || !h_end || !h_cnt) FAIL(SRW_E_NOMEM);
+        F->tJ = tJ;
+        F->tG = tG;
+        F->tsteps = tsteps;
+        F->tvsq = tvsq;
+        F->hlen = hlen;
+        F->h_end = h_end;
+        F->h_cnt = h_cnt;
+        if (max_budget > 0) {
+            int P = 64;
+            while (P < max_budget) P <<= 1;
+            const size_t lds = (size_t)(2 * P + 1) * sizeof(uint32_t);
+            if (lds > 64 * 1024) FAIL(SRW_E_ARG);  // budgets above 8192 walks per row
+            k_tally<<<(unsigned)n, 64, lds, s>>>(n, budget, rec_off, rec_end, rec_vis, rec_len, P,
+                                                tJ, tG, tsteps, tvsq, hlen, h_end, h_cnt);
+            CHECK_HIP(hipGetLastError());
+        } else {
+            CHECK_HIP(hipMemsetAsync(tJ, 0, n * sizeof(uint64_t), s));
+            CHECK_HIP(hipMemsetAsync(tG, 0, n * sizeof(uint32_t), s));
+            CHECK_HIP(hipMemsetAsync(tsteps, 0, n * sizeof(uint64_t), s));
+            CHECK_HIP(hipMemsetAsync(tvsq, 0, n * sizeof(uint64_t), s));
+            CHECK_HIP(hipMemsetAsync(hlen, 0, n * sizeof(int32_t), s));
+        }
+        {
+            unsigned long long* ssum = (unsigned long long*)(tot + 3);
+            CHECK_HIP(hipMemsetAsync(ssum, 0, sizeof(int64_t), s));
+            k_sum_u64<<<std::min(grid_for(n, BLOCK), 2048), BLOCK, 0, s>>>(n, tsteps, ssum);
+            CHECK_HIP(hipMemcpyAsync(&pinned[4], ssum, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        }
+
+        // ---- 6. factor
+        int32_t* ynnz = ALLOC(tmp, int32_t, n);
+        if (!ynnz) FAIL(SRW_E_NOMEM);
+        k_factor<double, false><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
+                                                    budget, tJ, rec_off, hlen, h_end, h_cnt,
+                                                    drop_tol, ynnz, nullptr, nullptr, nullptr,
+                                                    nullptr);
+        CHECK_HIP(exclusive_scan_i32_to_i64(ynnz, F->yptr, n, st, s));
+        k_read_last<<<1, 1, 0, s>>>(F->yptr, ynnz, n, tot + 0);
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        const int64_t nnz_y = pinned[0];
+        F->steps_total = pinned[4];
+        F->nnz_y = nnz_y;
+        if (nnz_y >= (int64_t)0xFFFFFFFFll) FAIL(SRW_E_ARG);
+        k_set_last<<<1, 1, 0, s>>>(F->yptr, n, nnz_y);
+        F->ycol = ALLOC(keep, int32_t, nnz_y);
+        F->yval = ALLOC(keep, char, nnz_y * vbytes);
+        F->d = ALLOC(keep, char, n * vbytes);
+        F->ytcol = ALLOC(keep, int32_t, nnz_y);
+        F->ytval = ALLOC(keep, char, nnz_y * vbytes);
+        if (!F->ycol || !F->yval || !F->d || !F->ytcol || !F->ytval) FAIL(SRW_E_NOMEM);
+        if (fp32)
+            k_factor<float, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
+                                                     budget, tJ, rec_off, hlen, h_end, h_cnt,
+                                                     drop_tol, nullptr, F->yptr, F->ycol,
+                                                     (float*)F->yval, (float*)F->d);
+        else
+            k_factor<double, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
+                                                      budget, tJ, rec_off, hlen, h_end, h_cnt,
+                                                      drop_tol, nullptr, F->yptr, F->ycol,
+                                                      (double*)F->yval, (double*)F->d);
+        CHECK_HIP(hipGetLastError());
+
+        // ---- 7. Y^T by a stable sort of the entries on their column
+        {
+            uint32_t* rowid = ALLOC(tmp, uint32_t, nnz_y);
+            uint32_t* idx = ALLOC(tmp, uint32_t, nnz_y);
+            uint32_t* idx2 = ALLOC(tmp, uint32_t, nnz_y);
+            uint32_t* kcol2 = ALLOC(tmp, uint32_t, nnz_y);
+            uint32_t* kcol = ALLOC(tmp, uint32_t, nnz_y);
+            int32_t* ccount = ALLOC(tmp, int32_t, n);
+            void* rt = ALLOC(tmp, char, radix_tmp_bytes(nnz_y));
+            if (!rowid || !idx || !idx2 || !kcol2 || !kcol || !ccount || !rt) FAIL(SRW_E_NOMEM);
+            k_entry_rows<<<g, BLOCK, 0, s>>>(n, F->yptr, rowid, idx);
+            CHECK_HIP(hipMemcpyAsync(kcol, F->ycol, nnz_y * sizeof(uint32_t),
+                                     hipMemcpyDeviceToDevice, s));
+            int bits = 8;
+            while (bits < 32 && ((int64_t)1 << bits) < n) bits += 8;
+            uint32_t* ko;
+            uint32_t* vo;
+            CHECK_HIP(radix_sort_u32(kcol, idx, kcol2, idx2, nnz_y, bits, rt, &ko, &vo, s));
+            CHECK_HIP(hipMemsetAsync(ccount, 0, n * sizeof(int32_t), s));
+            k_col_count<<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(nnz_y, F->ycol, ccount);
+            CHECK_HIP(exclusive_scan_i32_to_i64(ccount, F->ytptr, n, st, s));
+            k_set_last<<<1, 1, 0, s>>>(F->ytptr, n, nnz_y);
+            if (fp32)
+                k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
+                    nnz_y, vo, rowid, (const float*)F->yval, F->ytcol, (float*)F->ytval);
+            else
+                k_transpose_fill<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
+                    nnz_y, vo, rowid, (const double*)F->yval, F->ytcol, (double*)F->ytval);
+            CHECK_HIP(hipGetLastError());
+        }
+
+        // ---- 8. level schedules
+        F->fwd_rows = ALLOC(keep, int32_t, n);
+        F->bwd_rows = ALLOC(keep, int32_t, n);
+        if (!F->fwd_rows || !F->bwd_rows) FAIL(SRW_E_NOMEM);
+        // Y z = v: row v waits for the entries of its Y row; releases its Y^T row.
+        status = levels(n, F->yptr, F->ytptr, F->ytcol, F->fwd_rows, F->fwd_lptr, tmp, pinned, s);
+        if (status) goto done;
+        // Y^T w = r: row v waits for its Y^T row; releases its Y row.
+        status = levels(n, F->ytptr, F->yptr, F->ycol, F->bwd_rows, F->bwd_lptr, tmp, pinned, s);
+        if (status) goto done;
+        CHECK_HIP(hipStreamSynchronize(s));
+        if (keep.last != hipSuccess || tmp.last != hipSuccess) FAIL(SRW_E_NOMEM);
+    }
+
+done:
+#undef FAIL
+#undef CHECK_HIP
+#undef ALLOC
+    if (status == SRW_OK) {
+        (void)hipStreamSynchronize(s);
+    } else {
+        (void)hipStreamSynchronize(s);
+    }
+    tmp.release();
+    if (pinned) (void)hipHostFree(pinned);
+    if (status != SRW_OK) {
+        keep.release();
+        delete F;
+        return status;
+    }
+    if (opt.keep < 1) {
+        // drop what only export needs
+        void* drop[] = {F->ent, F->mthr, F->tau, F->grounded, F->budget, F->rec_off, F->tJ, F->tG,
+                        F->tsteps, F->tvsq, F->hlen};
+        for (void* p : drop) {
+            auto it = std::find(keep.blocks.begin(), keep.blocks.end(), p);
+            if (it != keep.blocks.end()) {
+                (void)hipFree(p);
+                keep.blocks.erase(it);
+            }
+        }
+        F->ent = nullptr; F->mthr = nullptr; F->tau = nullptr; F->grounded = nullptr;
+        F->budget = nullptr; F->rec_off = nullptr; F->tJ = nullptr; F->tG = nullptr;
+        F->tsteps = nullptr; F->tvsq = nullptr; F->hlen = nullptr;
+        F->h_end = nullptr; F->h_cnt = nullptr;
+    }
+    F->allocations = std::move(keep.blocks);
+    *out = F;
+    return SRW_OK;
+}
+
+}  // namespace srw

@@ -1,0 +1,205 @@
+// extern "C" entry points of libsrw.so (declared in include/srw.h).
+#include <cmath>
+#include <new>
+
+#include "factor.hpp"
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool csr_ok(const srw_csr* A)
+{
+    if (!A || A->n < 0 || A->nnz < A->n || A->n >= (int64_t)0x7FFFFFFF) return false;
+    if (!A->rowptr) return false;
+    if (A->nnz > 0 && (!A->col || !A->val)) return false;
+    return true;
+}
+
+template <typename T>
+int copy_out(T* dst, const void* src, size_t count, hipStream_t s)
+{
+    if (!dst || count == 0) return SRW_OK;
+    if (!src) return SRW_E_ARG;
+    SRW_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return SRW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void srw_default_options(srw_options* opt)
+{
+    if (!opt) return;
+    opt->ordering = SRW_ORDER_RANDOM;
+    opt->rank = nullptr;
+    opt->walks = nullptr;
+    opt->factor_precision = SRW_FP64;
+    opt->max_steps = 0;
+    opt->keep = 0;
+    opt->refill_period = 0;
+}
+
+int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
+                     const srw_options* opt, srw_factor** out, void* stream)
+{
+    if (!out) return SRW_E_ARG;
+    *out = nullptr;
+    if (!csr_ok(A)) return SRW_E_ARG;
+    if (!(drop_tol >= 0.0) || !std::isfinite(drop_tol)) return SRW_E_ARG;
+    if (opt) {
+        if (opt->ordering != SRW_ORDER_RANDOM && opt->ordering != SRW_ORDER_GIVEN) return SRW_E_ARG;
+        if (opt->factor_precision != SRW_FP64 && opt->factor_precision != SRW_FP32) return SRW_E_ARG;
+        if (opt->keep < 0 || opt->keep > 2) return SRW_E_ARG;
+        const int rp = opt->refill_period;
+        if (rp != 0 && rp != 1 && rp != 2 && rp != 4 && rp != 8) return SRW_E_ARG;
+        if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && A->n > 0) return SRW_E_ARG;
+    }
+    if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
+    if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
+    try {
+        return srw::build_factor_impl(A, walks_per_row, drop_tol, seed, opt, out, as_stream(stream));
+    } catch (const std::bad_alloc&) {
+        return SRW_E_NOMEM;
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
+void srw_factor_free(srw_factor* F) { srw::free_factor(F); }
+
+int srw_factor_info(const srw_factor* F, int64_t* n, int64_t* nnz_y, int64_t* walks,
+                    int64_t* walk_steps, int32_t* levels_fwd, int32_t* levels_bwd,
+                    int32_t* precision, int32_t* keep)
+{
+    if (!F) return SRW_E_ARG;
+    if (n) *n = F->n;
+    if (nnz_y) *nnz_y = F->nnz_y;
+    if (walks) *walks = F->walks_total;
+    if (walk_steps) *walk_steps = F->steps_total;
+    if (levels_fwd) *levels_fwd = (int32_t)(F->fwd_lptr.empty() ? 0 : F->fwd_lptr.size() - 1);
+    if (levels_bwd) *levels_bwd = (int32_t)(F->bwd_lptr.empty() ? 0 : F->bwd_lptr.size() - 1);
+    if (precision) *precision = F->precision;
+    if (keep) *keep = F->keep;
+    return SRW_OK;
+}
+
+int srw_factor_export(const srw_factor* F, int64_t* yptr, int32_t* ycol, void* yval, void* d,
+                      int32_t* rank, void* stream)
+{
+    if (!F) return SRW_E_ARG;
+    hipStream_t s = as_stream(stream);
+    const size_t vb = F->precision == SRW_FP32 ? sizeof(float) : sizeof(double);
+    int st;
+    if ((st = copy_out(yptr, F->yptr, (size_t)F->n + 1, s))) return st;
+    if ((st = copy_out(ycol, F->ycol, (size_t)F->nnz_y, s))) return st;
+    if ((st = copy_out((char*)yval, F->yval, (size_t)F->nnz_y * vb, s))) return st;
+    if ((st = copy_out((char*)d, F->d, (size_t)F->n * vb, s))) return st;
+    if ((st = copy_out(rank, F->rank, (size_t)F->n, s))) return st;
+    SRW_HIP(hipStreamSynchronize(s));
+    return SRW_OK;
+}
+
+int srw_table_export(const srw_factor* F, int32_t* nbr, uint32_t* thr, uint32_t* mthr,
+                     double* tau, uint8_t* grounded, void* stream)
+{
+    if (!F) return SRW_E_ARG;
+    if (F->keep < 1) return SRW_E_ARG;
+    hipStream_t s = as_stream(stream);
+    const int64_t m = F->nnz_a - F->n;
+    if (m > 0 && (nbr || thr)) {
+        // entries are stored as {neighbour, threshold} pairs
+        if (nbr) SRW_HIP(hipMemcpy2DAsync(nbr, sizeof(int32_t), F->ent, sizeof(uint2), sizeof(int32_t),
+                                          (size_t)m, hipMemcpyDeviceToDevice, s));
+        if (thr) SRW_HIP(hipMemcpy2DAsync(thr, sizeof(uint32_t), (const char*)F->ent + sizeof(uint32_t),
+                                          sizeof(uint2), sizeof(uint32_t), (size_t)m,
+                                          hipMemcpyDeviceToDevice, s));
+    }
+    int st;
+    if ((st = copy_out(mthr, F->mthr, (size_t)m, s))) return st;
+    if ((st = copy_out(tau, F->tau, (size_t)F->n, s))) return st;
+    if ((st = copy_out(grounded, F->grounded, (size_t)F->n, s))) return st;
+    SRW_HIP(hipStreamSynchronize(s));
+    return SRW_OK;
+}
+
+int srw_tally_export(const srw_factor* F, uint32_t* walks, uint64_t* J, uint32_t* G,
+                     uint64_t* steps, uint64_t* visits_sq, int64_t* h_off, int32_t* hlen,
+                     int32_t* h_end, uint32_t* h_cnt, void* stream)
+{
+    if (!F) return SRW_E_ARG;
+    if (F->keep < 1) return SRW_E_ARG;
+    hipStream_t s = as_stream(stream);
+    const size_t n = (size_t)F->n, W = (size_t)F->walks_total;
+    int st;
+    if ((st = copy_out((int32_t*)walks, F->budget, n, s))) return st;
+    if ((st = copy_out(J, F->tJ, n, s))) return st;
+    if ((st = copy_out(G, F->tG, n, s))) return st;
+    if ((st = copy_out(steps, F->tsteps, n, s))) return st;
+    if ((st = copy_out(visits_sq, F->tvsq, n, s))) return st;
+    if ((st = copy_out(h_off, F->rec_off, n, s))) return st;
+    if ((st = copy_out(hlen, F->hlen, n, s))) return st;
+    if ((st = copy_out((uint32_t*)h_end, F->h_end, W, s))) return st;
+    if ((st = copy_out(h_cnt, F->h_cnt, W, s))) return st;
+    SRW_HIP(hipStreamSynchronize(s));
+    return SRW_OK;
+}
+
+int srw_walk_export(const srw_factor* F, int64_t* rec_off, int32_t* end, uint32_t* visits,
+                    uint32_t* length, void* stream)
+{
+    if (!F) return SRW_E_ARG;
+    if (F->keep < 2) return SRW_E_ARG;
+    hipStream_t s = as_stream(stream);
+    const size_t n = (size_t)F->n, W = (size_t)F->walks_total;
+    int st;
+    if ((st = copy_out(rec_off, F->rec_off, n, s))) return st;
+    if ((st = copy_out((uint32_t*)end, F->rec_end, W, s))) return st;
+    if ((st = copy_out(visits, F->rec_vis, W, s))) return st;
+    if ((st = copy_out(length, F->rec_len, W, s))) return st;
+    SRW_HIP(hipStreamSynchronize(s));
+    return SRW_OK;
+}
+
+int srw_pcg_solve(const srw_csr* A, const srw_factor* F, const double* b, double tol,
+                  int32_t max_iter, double* x, int32_t* iters, double* rel_residual, void* stream)
+{
+    if (!F || !csr_ok(A) || A->n != F->n || A->nnz != F->nnz_a) return SRW_E_ARG;
+    if (A->n > 0 && (!b || !x)) return SRW_E_ARG;
+    if (!(tol >= 0.0) || max_iter < 0) return SRW_E_ARG;
+    if (iters) *iters = 0;
+    if (rel_residual) *rel_residual = 0.0;
+    if (A->n == 0) return SRW_OK;
+    try {
+        return srw::pcg_impl(A, const_cast<srw_factor*>(F), b, tol, max_iter, x, iters,
+                             rel_residual, as_stream(stream));
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
+int srw_apply(const srw_factor* F, const double* r, double* z, void* stream)
+{
+    if (!F) return SRW_E_ARG;
+    if (F->n == 0) return SRW_OK;
+    if (!r || !z) return SRW_E_ARG;
+    return srw::apply_impl(const_cast<srw_factor*>(F), r, z, as_stream(stream));
+}
+
+const char* srw_status_string(int status)
+{
+    switch (status) {
+        case SRW_OK: return "SRW_OK";
+        case SRW_NOT_CONVERGED: return "SRW_NOT_CONVERGED: PCG reached max_iter";
+        case SRW_E_ARG: return "SRW_E_ARG: malformed arguments or CSR structure";
+        case SRW_E_NOT_RMATRIX: return "SRW_E_NOT_RMATRIX: matrix values violate the R-matrix definition";
+        case SRW_E_SINGULAR: return "SRW_E_SINGULAR: a connected component has no path to ground";
+        case SRW_E_WALK_LIMIT: return "SRW_E_WALK_LIMIT: a walk exceeded max_steps";
+        case SRW_E_NOMEM: return "SRW_E_NOMEM: device allocation failed";
+        case SRW_E_HIP: return "SRW_E_HIP: a HIP runtime call failed";
+        default: return "unknown srw status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal layout of srw_factor and the device-memory helpers of libsrw.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+// Library-owned preconditioner.  Node labels are the caller's row indices; Y is
+// stored by rows (CSR, ascending node id per row, strictly lower in rank) and by
+// columns (Yt = CSR of Y^T) for the two triangular solves.
+struct srw_factor {
+    int64_t n = 0;
+    int64_t nnz_a = 0;
+    int32_t precision = SRW_FP64;
+    int32_t keep = 0;
+    int64_t nnz_y = 0;
+    int64_t walks_total = 0;
+    int64_t steps_total = 0;
+
+    int32_t* rank = nullptr;     // [n]
+    int32_t* by_rank = nullptr;  // [n] node of each rank
+    int64_t* yptr = nullptr;     // [n+1]
+    int32_t* ycol = nullptr;     // [nnz_y]
+    void* yval = nullptr;        // [nnz_y] double or float
+    int64_t* ytptr = nullptr;    // [n+1]
+    int32_t* ytcol = nullptr;    // [nnz_y]
+    void* ytval = nullptr;       // [nnz_y]
+    void* d = nullptr;           // [n] double or float
+
+    // dependency-level schedules: rows of level L are rows[lptr[L] .. lptr[L+1])
+    int32_t* fwd_rows = nullptr;  // Y z = v, increasing rank
+    int32_t* bwd_rows = nullptr;  // Y^T w = r, decreasing rank
+    std::vector<int64_t> fwd_lptr, bwd_lptr;
+
+    // kept on request (srw_options.keep)
+    uint2* ent = nullptr;          // [nnz-n] {neighbour, threshold}
+    uint32_t* mthr = nullptr;      // [nnz-n]
+    double* tau = nullptr;         // [n]
+    uint8_t* grounded = nullptr;   // [n]
+    int32_t* budget = nullptr;     // [n] walks per row (0 = exact row)
+    int64_t* rec_off = nullptr;    // [n]
+    uint64_t* tJ = nullptr;        // [n]
+    uint32_t* tG = nullptr;        // [n]
+    uint64_t* tsteps = nullptr;    // [n]
+    uint64_t* tvsq = nullptr;      // [n]
+    int32_t* hlen = nullptr;       // [n]
+    uint32_t* h_end = nullptr;     // [walks_total]
+    uint32_t* h_cnt = nullptr;     // [walks_total]
+    uint32_t* rec_end = nullptr;   // [walks_total]
+    uint32_t* rec_vis = nullptr;   // [walks_total]
+    uint32_t* rec_len = nullptr;   // [walks_total]
+
+    // PCG workspace, allocated on first solve
+    double* ws = nullptr;          // r, z, p, q  (4 n)
+    void* ws_lo = nullptr;         // two low-precision work vectors for FP32 solves
+    double* partials = nullptr;
+    double* scalars = nullptr;
+    double* host_scalars = nullptr;  // pinned
+
+    std::vector<void*> allocations;  // every device/pinned block owned by this factor
+};
+
+namespace srw {
+
+// Device allocation tracked by an owner list (freed together).
+struct Arena {
+    std::vector<void*> blocks;
+    hipError_t last = hipSuccess;
+    template <typename T>
+    T* alloc(size_t count)
+    {
+        void* p = nullptr;
+        const size_t bytes = count ? count * sizeof(T) : sizeof(T);
+        hipError_t e = hipMalloc(&p, (bytes + 255) & ~(size_t)255);
+        if (e != hipSuccess) {
+            last = e;
+            return nullptr;
+        }
+        blocks.push_back(p);
+        return (T*)p;
+    }
+    void release()
+    {
+        for (void* p : blocks) (void)hipFree(p);
+        blocks.clear();
+    }
+};
+
+int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
+                      const srw_options* opt, srw_factor** out, hipStream_t s);
+int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
+             double* x, int32_t* iters, double* rel_residual, hipStream_t s);
+int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
+void free_factor(srw_factor* F);
+
+}  // namespace srw

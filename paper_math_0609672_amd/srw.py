@@ -1,0 +1,234 @@
+"""ctypes binding of libsrw.so (the C ABI of include/srw.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.  PyTorch
+supplies device memory (tensors) and the current stream.  Importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrw.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_NOT_RMATRIX, E_SINGULAR, E_WALK_LIMIT, E_NOMEM, E_HIP = -1, -2, -3, -4, -5, -6
+ORDER_RANDOM, ORDER_GIVEN = 0, 1
+FP64, FP32 = 0, 1
+
+
+class SrwError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("ordering", ctypes.c_int32), ("rank", ctypes.c_void_p), ("walks", ctypes.c_void_p),
+                ("factor_precision", ctypes.c_int32), ("max_steps", ctypes.c_uint64),
+                ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsrw.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P, _I64, _I32, _U64, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+_lib.srw_default_options.argtypes = [ctypes.POINTER(_Options)]
+_lib.srw_build_factor.argtypes = [ctypes.POINTER(_Csr), _I32, _D, _U64, ctypes.POINTER(_Options),
+                                  ctypes.POINTER(_P), _P]
+_lib.srw_factor_free.argtypes = [_P]
+_lib.srw_factor_info.argtypes = [_P] + [_P] * 8
+_lib.srw_factor_export.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+_lib.srw_table_export.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+_lib.srw_tally_export.argtypes = [_P] + [_P] * 9 + [_P]
+_lib.srw_walk_export.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.srw_pcg_solve.argtypes = [ctypes.POINTER(_Csr), _P, _P, _D, _I32, _P, ctypes.POINTER(_I32),
+                               ctypes.POINTER(_D), _P]
+_lib.srw_apply.argtypes = [_P, _P, _P, _P]
+_lib.srw_status_string.argtypes = [ctypes.c_int]
+_lib.srw_status_string.restype = ctypes.c_char_p
+
+EXPORTED = ["srw_default_options", "srw_build_factor", "srw_factor_free", "srw_factor_info",
+            "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
+            "srw_pcg_solve", "srw_apply", "srw_status_string"]
+
+
+def status_string(status: int) -> str:
+    return _lib.srw_status_string(int(status)).decode()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+@dataclass
+class Matrix:
+    """Device-resident CSR (int64 rowptr, int32 col, float64 val); see srw_csr."""
+
+    n: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @classmethod
+    def from_host(cls, A, device="cuda"):
+        return cls(A.n, torch.as_tensor(A.rowptr, dtype=torch.int64).to(device),
+                   torch.as_tensor(A.col, dtype=torch.int32).to(device),
+                   torch.as_tensor(A.val, dtype=torch.float64).to(device))
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def c(self) -> _Csr:
+        return _Csr(self.n, self.nnz, _ptr(self.rowptr), _ptr(self.col), _ptr(self.val))
+
+
+class Factor:
+    """Handle of a library-owned srw_factor."""
+
+    def __init__(self, handle: int, device):
+        self._h = ctypes.c_void_p(handle)
+        self.device = device
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.srw_factor_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n, nnz_y, walks, steps = (ctypes.c_int64() for _ in range(4))
+        lf, lb, prec, keep = (ctypes.c_int32() for _ in range(4))
+        st = _lib.srw_factor_info(self._h, *(ctypes.byref(v) for v in (n, nnz_y, walks, steps, lf, lb, prec, keep)))
+        _check(st, "srw_factor_info")
+        return dict(n=n.value, nnz_y=nnz_y.value, walks=walks.value, walk_steps=steps.value,
+                    levels_fwd=lf.value, levels_bwd=lb.value,
+                    precision="fp32" if prec.value == FP32 else "fp64", keep=keep.value)
+
+    def export(self, stream=None) -> dict:
+        i = self.info()
+        n, m = i["n"], i["nnz_y"]
+        vt = torch.float32 if i["precision"] == "fp32" else torch.float64
+        kw = dict(device=self.device)
+        out = dict(yptr=torch.empty(n + 1, dtype=torch.int64, **kw),
+                   ycol=torch.empty(m, dtype=torch.int32, **kw),
+                   yval=torch.empty(m, dtype=vt, **kw), d=torch.empty(n, dtype=vt, **kw),
+                   rank=torch.empty(n, dtype=torch.int32, **kw))
+        st = _lib.srw_factor_export(self._h, _ptr(out["yptr"]), _ptr(out["ycol"]), _ptr(out["yval"]),
+                                    _ptr(out["d"]), _ptr(out["rank"]), _stream(stream))
+        _check(st, "srw_factor_export")
+        return out
+
+    def table(self, nnz_a: int, stream=None) -> dict:
+        n = self.info()["n"]
+        m = nnz_a - n
+        kw = dict(device=self.device)
+        out = dict(nbr=torch.empty(m, dtype=torch.int32, **kw),
+                   thr=torch.empty(m, dtype=torch.int32, **kw),
+                   mthr=torch.empty(m, dtype=torch.int32, **kw),
+                   tau=torch.empty(n, dtype=torch.float64, **kw),
+                   grounded=torch.empty(n, dtype=torch.uint8, **kw))
+        st = _lib.srw_table_export(self._h, _ptr(out["nbr"]), _ptr(out["thr"]), _ptr(out["mthr"]),
+                                   _ptr(out["tau"]), _ptr(out["grounded"]), _stream(stream))
+        _check(st, "srw_table_export")
+        return out
+
+    def tallies(self, stream=None) -> dict:
+        i = self.info()
+        n, W = i["n"], i["walks"]
+        kw = dict(device=self.device)
+        out = dict(walks=torch.empty(n, dtype=torch.int32, **kw), J=torch.empty(n, dtype=torch.int64, **kw),
+                   G=torch.empty(n, dtype=torch.int32, **kw), steps=torch.empty(n, dtype=torch.int64, **kw),
+                   visits_sq=torch.empty(n, dtype=torch.int64, **kw),
+                   h_off=torch.empty(n, dtype=torch.int64, **kw), hlen=torch.empty(n, dtype=torch.int32, **kw),
+                   h_end=torch.empty(W, dtype=torch.int32, **kw), h_cnt=torch.empty(W, dtype=torch.int32, **kw))
+        st = _lib.srw_tally_export(self._h, *(_ptr(out[k]) for k in
+                                              ("walks", "J", "G", "steps", "visits_sq", "h_off", "hlen",
+                                               "h_end", "h_cnt")), _stream(stream))
+        _check(st, "srw_tally_export")
+        return out
+
+    def records(self, stream=None) -> dict:
+        i = self.info()
+        n, W = i["n"], i["walks"]
+        kw = dict(device=self.device)
+        out = dict(rec_off=torch.empty(n, dtype=torch.int64, **kw), end=torch.empty(W, dtype=torch.int32, **kw),
+                   visits=torch.empty(W, dtype=torch.int32, **kw), length=torch.empty(W, dtype=torch.int32, **kw))
+        st = _lib.srw_walk_export(self._h, _ptr(out["rec_off"]), _ptr(out["end"]), _ptr(out["visits"]),
+                                  _ptr(out["length"]), _stream(stream))
+        _check(st, "srw_walk_export")
+        return out
+
+
+def _check(st: int, what: str):
+    if st < 0:
+        raise SrwError(st, what)
+
+
+def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
+                 precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
+                 stream=None) -> Factor:
+    """srw_build_factor: the random-walk incomplete LDL^T factor of A."""
+    opt = _Options()
+    _lib.srw_default_options(ctypes.byref(opt))
+    if rank is not None:
+        opt.ordering = ORDER_GIVEN
+        opt.rank = _ptr(rank).value
+    if walks is not None:
+        opt.walks = _ptr(walks).value
+    opt.factor_precision = FP32 if precision == "fp32" else FP64
+    opt.max_steps = int(max_steps)
+    opt.keep = int(keep)
+    opt.refill_period = int(refill_period)
+    h = ctypes.c_void_p(0)
+    csr = A.c()
+    st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),
+                               ctypes.byref(opt), ctypes.byref(h), _stream(stream))
+    _check(st, "srw_build_factor")
+    return Factor(h.value, A.rowptr.device)
+
+
+def pcg_solve(A: Matrix, F: Factor, b: torch.Tensor, tol: float, max_iter: int = 10000, x=None,
+              stream=None):
+    """srw_pcg_solve.  Returns (status, x, iters, rel_residual); status is OK or
+    NOT_CONVERGED, errors raise SrwError."""
+    if x is None:
+        x = torch.empty_like(b)
+    it = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    csr = A.c()
+    st = _lib.srw_pcg_solve(ctypes.byref(csr), F.handle, _ptr(b), float(tol), int(max_iter), _ptr(x),
+                            ctypes.byref(it), ctypes.byref(rel), _stream(stream))
+    _check(st, "srw_pcg_solve")
+    return st, x, it.value, rel.value
+
+
+def apply(F: Factor, r: torch.Tensor, stream=None) -> torch.Tensor:
+    """srw_apply: z = (Y^T D Y)^{-1} r."""
+    z = torch.empty_like(r)
+    st = _lib.srw_apply(F.handle, _ptr(r), _ptr(z), _stream(stream))
+    _check(st, "srw_apply")
+    return z

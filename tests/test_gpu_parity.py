@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: ranks, transition table, per-walk records and tallies bit-exact; the FP64
+factor bit-exact (both sides evaluate eqs. newy/newz/d in the same operation order
+without contraction); one preconditioner application within 1e-12 and PCG iterates
+within 1e-10 relative after the same number of iterations (dot products are summed
+in different orders).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_math_0609672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def srw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_math_0609672_amd import srw as s
+    return s
+
+
+DEV = "cuda:0"
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def cases():
+    return {
+        "grid2d_32": (W.config_grid2d_32(0), 64),
+        "grid3d_12": (W.grid((12, 12, 12), g=("loguniform", 1e-2, 1e2), ground_frac=0.01,
+                             excess=("uniform", 0.01, 1.0), seed=3), 256),
+        "grid2d_37x29": (W.grid((37, 29), g=("uniform", 0.1, 10.0), ground_frac=0.02,
+                                excess=("uniform", 0.1, 10.0), seed=5), 100),
+        "random_3000": (W.random_graph(3000, 9000, seed=7, ground_frac=0.01), 37),
+    }
+
+
+CASES = cases()
+
+
+def gpu_build(srw, A, walks, drop, seed, **kw):
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, drop, seed, **kw)
+    return M, F
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 9), (1000, 0), (4097, 123456789), (300001, 77)])
+def test_rank_bit_exact(srw, n, seed):
+    # a diagonal matrix: the ordering is exercised without any walk
+    empty = np.zeros(0, np.int64)
+    A = W.assemble(n, empty, empty, np.zeros(0), np.ones(n))
+    _, F = gpu_build(srw, A, 1, 0.0, seed)
+    assert np.array_equal(np_(F.export()["rank"]), O.rank(n, seed))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_table_bit_exact(srw, name):
+    A, walks = CASES[name]
+    M, F = gpu_build(srw, A, walks, 0.0, 11, keep=1)
+    tb = F.table(A.nnz)
+    ref = O.table(A, O.rank(A.n, 11))
+    assert np.array_equal(np_(tb["nbr"]), ref.nbr)
+    assert np.array_equal(np_(tb["thr"]).view(np.uint32), ref.thr)
+    assert np.array_equal(np_(tb["mthr"]).view(np.uint32), ref.mthr)
+    assert np.array_equal(np_(tb["tau"]), ref.tau)
+    assert np.array_equal(np_(tb["grounded"]), ref.grounded)
+
+
+def compare_walks(srw, A, walks, seed, budget=None, refill=0):
+    Mx = srw.Matrix.from_host(A, DEV)
+    kw = dict(keep=2, refill_period=refill)
+    if budget is not None:
+        kw["walks"] = torch.as_tensor(budget, dtype=torch.int32, device=DEV)
+    F = srw.build_factor(Mx, walks, 0.0, seed, **kw)
+    rec = {k: np_(v) for k, v in F.records().items()}
+    tl = {k: np_(v) for k, v in F.tallies().items()}
+    rk = O.rank(A.n, seed)
+    tb = O.table(A, rk)
+    b = walks if budget is None else np.maximum(np.asarray(budget), 1)
+    wk = O.walk_rows(A, rk, tb, seed, np.arange(A.n), b)
+    # per-walk records
+    assert np.array_equal(rec["rec_off"], wk.rec_off[:-1])
+    assert np.array_equal(rec["end"], wk.end)
+    assert np.array_equal(rec["visits"].view(np.uint32), wk.visits)
+    assert np.array_equal(rec["length"].view(np.uint32), wk.length)
+    # tallies
+    t = O.tally(wk)
+    assert np.array_equal(tl["walks"], wk.budget)
+    assert np.array_equal(tl["J"].view(np.uint64), t.J)
+    assert np.array_equal(tl["G"].view(np.uint32), t.G)
+    assert np.array_equal(tl["steps"].view(np.uint64), t.steps)
+    assert np.array_equal(tl["visits_sq"].view(np.uint64), t.visits_sq)
+    assert np.array_equal(tl["hlen"], t.hlen)
+    valid = np.zeros(tl["h_end"].size, bool)
+    idx = np.repeat(t.h_off, t.hlen) + (np.arange(t.hlen.sum()) - np.repeat(np.cumsum(t.hlen) - t.hlen, t.hlen))
+    valid[idx] = True
+    assert np.array_equal(tl["h_end"][valid], t.h_end[valid])
+    assert np.array_equal(tl["h_cnt"].view(np.uint32)[valid], t.h_cnt[valid])
+    return F, t
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_walks_and_tallies_bit_exact(srw, name):
+    A, walks = CASES[name]
+    F, t = compare_walks(srw, A, walks, 5)
+    assert F.info()["walk_steps"] == int(t.steps.sum())
+
+
+@pytest.mark.parametrize("refill", [1, 2, 4, 8])
+def test_walks_independent_of_scheduling(srw, refill):
+    A, walks = CASES["grid3d_12"]
+    compare_walks(srw, A, walks, 21, refill=refill)
+
+
+def test_per_row_budgets_ragged(srw):
+    A, _ = CASES["random_3000"]
+    rng = np.random.default_rng(0)
+    budget = rng.integers(-2, 300, A.n).astype(np.int32)  # < 1 counts as 1
+    compare_walks(srw, A, 64, 8, budget=budget)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("drop", [0.0, 1e-3, 2e-2])
+def test_factor_bit_exact(srw, name, drop):
+    A, walks = CASES[name]
+    _, F = gpu_build(srw, A, walks, drop, 3)
+    ref = O.build_factor(A, walks, drop, 3)
+    got = {k: np_(v) for k, v in F.export().items()}
+    assert np.array_equal(got["yptr"], ref.yptr)
+    assert np.array_equal(got["ycol"], ref.ycol)
+    assert np.array_equal(got["yval"], ref.yval)
+    assert np.array_equal(got["d"], ref.d)
+    assert F.info()["nnz_y"] == ref.yptr[-1]
+
+
+def test_fp32_factor_is_rounded_fp64_factor(srw):
+    A, walks = CASES["grid2d_37x29"]
+    _, F = gpu_build(srw, A, walks, 1e-3, 4, precision="fp32")
+    ref = O.build_factor(A, walks, 1e-3, 4)
+    got = {k: np_(v) for k, v in F.export().items()}
+    assert got["yval"].dtype == np.float32
+    assert np.array_equal(got["ycol"], ref.ycol)
+    assert np.array_equal(got["yval"], ref.yval.astype(np.float32))
+    assert np.array_equal(got["d"], ref.d.astype(np.float32))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_matches_oracle(srw, name):
+    A, walks = CASES[name]
+    _, F = gpu_build(srw, A, walks, 1e-3, 2)
+    ref = O.build_factor(A, walks, 1e-3, 2)
+    r = W.rhs(A.n, seed=4)
+    z = np_(srw.apply(F, torch.as_tensor(r, device=DEV)))
+    zr = O.apply(ref, r)
+    assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("tol", [1e-8, 1e-10])
+def test_pcg_matches_oracle(srw, name, tol):
+    A, walks = CASES[name]
+    M, F = gpu_build(srw, A, walks, 1e-3, 0)
+    ref = O.build_factor(A, walks, 1e-3, 0)
+    b = W.rhs(A.n, seed=1)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), tol)
+    st_o, x_o, it_o, rel_o = O.pcg(A, ref, b, tol)
+    assert st == st_o == 0
+    assert it == it_o
+    x = np_(x)
+    assert np.linalg.norm(x - x_o) <= 1e-10 * np.linalg.norm(x_o)
+    # final residual vectors agree: ||(b - A x) - (b - A x_o)|| <= 1e-10 ||b||
+    As = A.to_scipy()
+    assert np.linalg.norm(As @ (x - x_o)) <= 1e-10 * np.linalg.norm(b)
+    # independent check of the returned residual
+    true = np.linalg.norm(b - As @ x) / np.linalg.norm(b)
+    assert rel <= tol and np.isclose(true, rel, rtol=1e-6)
+
+
+def test_fp32_factor_pcg_reaches_tolerance(srw):
+    A, walks = CASES["grid3d_12"]
+    M, F = gpu_build(srw, A, walks, 1e-3, 0, precision="fp32")
+    ref = O.build_factor(A, walks, 1e-3, 0)
+    b = W.rhs(A.n, seed=1)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), 1e-10)
+    st_o, x_o, it_o, _ = O.pcg(A, ref, b, 1e-10)
+    assert st == 0 and rel <= 1e-10
+    x = np_(x)
+    # the FP32 preconditioner changes the iterates, not the solution tolerance
+    assert np.linalg.norm(x - x_o) <= 1e-8 * np.linalg.norm(x_o)
+    assert it <= it_o + 3
+
+
+# -------------------------------------------------------------------- edge cases
+def test_diagonal_matrix_all_rows_exact(srw):
+    A = W.from_dense(np.diag(np.linspace(1.0, 3.0, 100)))
+    M, F = gpu_build(srw, A, 64, 0.0, 0)
+    i = F.info()
+    assert i["nnz_y"] == 0 and i["walks"] == 0 and i["levels_fwd"] == 1
+    b = W.rhs(100, seed=0)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), 1e-12)
+    assert st == 0 and it == 1
+    assert np.allclose(np_(x), b / np.linspace(1.0, 3.0, 100), rtol=1e-15)
+
+
+def test_single_node_and_two_nodes(srw):
+    A1 = W.from_dense(np.array([[2.5]]))
+    M, F = gpu_build(srw, A1, 16, 0.0, 0)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.tensor([5.0], dtype=torch.float64, device=DEV), 1e-12)
+    assert st == 0 and it == 1 and np_(x)[0] == 2.0
+    A2 = W.from_dense(np.array([[3.0, -1.0], [-1.0, 2.0]]))
+    compare_walks(srw, A2, 1000, 4)
+
+
+def test_disconnected_grounded_components_and_one_walk(srw):
+    Ad = np.zeros((6, 6))
+    for (i, j) in [(0, 1), (1, 2), (3, 4)]:
+        Ad[i, j] = Ad[j, i] = -1.0
+    Ad[np.diag_indices(6)] = -Ad.sum(axis=1) + np.array([0.5, 0, 0, 0, 0.25, 1.0])
+    A = W.from_dense(Ad)
+    compare_walks(srw, A, 1, 2)
+    _, F = gpu_build(srw, A, 1, 0.0, 2)
+    ref = O.build_factor(A, 1, 0.0, 2)
+    assert np.array_equal(np_(F.export()["yval"]), ref.yval)
+
+
+def test_zero_rhs_and_iteration_cap(srw):
+    A, walks = CASES["grid2d_32"]
+    M, F = gpu_build(srw, A, walks, 1e-3, 0)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.zeros(A.n, dtype=torch.float64, device=DEV), 1e-8)
+    assert st == srw.OK and it == 0 and rel == 0.0 and not np_(x).any()
+    b = W.rhs(A.n, seed=1)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), 1e-14, max_iter=3)
+    ref = O.build_factor(A, walks, 1e-3, 0)
+    st_o, x_o, it_o, _ = O.pcg(A, ref, b, 1e-14, max_iter=3)
+    assert st == srw.NOT_CONVERGED == st_o and it == 3 == it_o
+    assert np.linalg.norm(np_(x) - x_o) <= 1e-12 * np.linalg.norm(x_o)
+
+
+def test_error_statuses(srw):
+    good = W.config_grid2d_32()
+    D = good.dense()
+    i, j = np.argwhere(D < 0)[0]
+    bad = D.copy()
+    bad[i, j] = bad[j, i] = 0.3
+    with pytest.raises(srw.SrwError) as e:
+        gpu_build(srw, W.from_dense(bad), 8, 0.0, 0)
+    assert e.value.status == srw.E_NOT_RMATRIX
+    asym = D.copy()
+    asym[i, j] *= 1.01
+    with pytest.raises(srw.SrwError) as e:
+        gpu_build(srw, W.from_dense(asym), 8, 0.0, 0)
+    assert e.value.status == srw.E_NOT_RMATRIX
+    ungrounded = np.array([[2.0, -1, 0, 0], [-1, 2.0, 0, 0], [0, 0, 1.0, -1], [0, 0, -1, 1.0]])
+    with pytest.raises(srw.SrwError) as e:
+        gpu_build(srw, W.from_dense(ungrounded), 8, 0.0, 0)
+    assert e.value.status == srw.E_SINGULAR
+    unsorted = W.CSR(good.n, good.rowptr.copy(), good.col.copy(), good.val.copy())
+    unsorted.col[0:2] = unsorted.col[0:2][::-1]
+    with pytest.raises(srw.SrwError) as e:
+        gpu_build(srw, unsorted, 8, 0.0, 0)
+    assert e.value.status == srw.E_ARG
+    with pytest.raises(srw.SrwError) as e:
+        gpu_build(srw, good, 64, 0.0, 0, max_steps=2)
+    assert e.value.status == srw.E_WALK_LIMIT
+    notperm = torch.zeros(good.n, dtype=torch.int32, device=DEV)
+    with pytest.raises(srw.SrwError) as e:
+        gpu_build(srw, good, 8, 0.0, 0, rank=notperm)
+    assert e.value.status == srw.E_ARG
+
+
+def test_given_ordering_matches_oracle(srw):
+    A, walks = CASES["grid2d_37x29"]
+    rk = np.random.default_rng(3).permutation(A.n).astype(np.int32)
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, 1e-3, 9, rank=torch.as_tensor(rk, device=DEV))
+    ref = O.build_factor(A, walks, 1e-3, 9, rk=rk)
+    got = {k: np_(v) for k, v in F.export().items()}
+    assert np.array_equal(got["rank"], rk)
+    assert np.array_equal(got["yval"], ref.yval) and np.array_equal(got["d"], ref.d)

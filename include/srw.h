@@ -70,13 +70,19 @@ typedef struct {
     const int32_t* walks;      /* device int32[n] per-row walk budgets, or NULL for
                                   the uniform walks_per_row; values < 1 count as 1  */
     int32_t factor_precision;  /* SRW_FP64                                          */
-    uint64_t max_steps;        /* per-walk step cap, 0 = 2^24; exceeding it fails
+    uint64_t max_steps;        /* per-walk step cap, 0 = 2^22; exceeding it fails
                                   the build with SRW_E_WALK_LIMIT                    */
     int32_t keep;              /* 0 = keep only the factor; 1 = also keep the
                                   transition table and per-row tallies; 2 = also keep
                                   the per-walk records (for export / inspection)    */
-    int32_t refill_period;     /* walk scheduling: lanes take new walks every this
-                                  many steps (1, 2, 4 or 8); 0 = library default    */
+    int32_t refill_period;     /* walk scheduling: idle lanes take new walks every
+                                  this many steps (1, 2, 4 or 8); 0 = 8, which keeps
+                                  every lane on the same random-number block phase  */
+    int32_t profile;           /* 1 = time the build phases with HIP events on the
+                                  build stream (see srw_factor_stats); 0 = off      */
+    int32_t schedule;          /* walk order: 0 = all rows by rank (longest walks
+                                  first); 1 (default) = rows ranked below n/256 by
+                                  rank, then the rest in node-id slabs, one per XCD */
 } srw_options;
 
 void srw_default_options(srw_options* opt);
@@ -105,7 +111,7 @@ typedef struct srw_factor srw_factor;
  *      D_k = a_k / (1 + tau_k (J'_k/M'_k - 1)) (eqs. newz, d), with
  *      tau_k = (sum of A_kj over higher-ranked j) / -A_kk, and drops entries with
  *      |Y_ki| < drop_tol (Section 4, footnote);
- *   7. schedules the triangular solves by dependency level.
+ *   7. stores Y by rows and by columns for the two triangular solves.
  * Y is unit lower triangular in rank order; the preconditioner is (Y^T D Y)^{-1},
  * i.e. (L D L^T)^{-1} with L = rev(Y)^T of eq. y in the reversed ordering.
  * A must stay valid only during the call.  *out receives a new factor. */
@@ -116,11 +122,37 @@ void srw_factor_free(srw_factor* F);
 
 /* Sizes and counters of a factor (host outputs; any pointer may be NULL):
  * n, nnz_y (strictly triangular entries kept), walks (simulated walks), walk_steps
- * (their total steps), levels_fwd / levels_bwd (dependency levels of the two
- * triangular solves), precision (SRW_FP64 / SRW_FP32), keep (srw_options.keep). */
+ * (their total steps), levels_fwd / levels_bwd (length of the longest dependency
+ * chain of the triangular solves, the same for both; -1 until srw_factor_depth has
+ * computed it), precision (SRW_FP64 / SRW_FP32), keep (srw_options.keep). */
 int srw_factor_info(const srw_factor* F, int64_t* n, int64_t* nnz_y, int64_t* walks,
                     int64_t* walk_steps, int32_t* levels_fwd, int32_t* levels_bwd,
                     int32_t* precision, int32_t* keep);
+
+/* Build phases timed when srw_options.profile = 1, in this order. */
+#define SRW_NUM_PHASES 8
+/* validate, rank, table, schedule (record offsets and the walk queue), walk (the
+ * walk kernel alone), tally, factor, transpose */
+
+typedef struct {
+    int64_t n, nnz_a, nnz_y;
+    int64_t walks;         /* simulated walks                                       */
+    int64_t walk_steps;    /* their total steps                                     */
+    int64_t walk_deg_sum;  /* sum over steps of the degree of the node left: the
+                              walk kernel's algorithmic bytes are
+                              12 * walk_steps + 8 * walk_deg_sum                     */
+    int32_t levels_fwd, levels_bwd; /* dependency depth, -1 until srw_factor_depth  */
+    int32_t precision, keep;
+    double phase_ms[SRW_NUM_PHASES]; /* milliseconds, -1 when not profiled           */
+} srw_stats;
+
+/* Counters and (if profiled) phase times of a factor; host output. */
+int srw_factor_stats(const srw_factor* F, srw_stats* out);
+
+/* Length of the longest dependency chain of the triangular solves (the number of
+ * levels a level-by-level substitution would need), computed on the device and cached
+ * in the factor; *depth is a host output.  Not needed to solve. */
+int srw_factor_depth(srw_factor* F, int32_t* depth, void* stream);
 
 /* Copies the factor to caller device buffers: yptr int64[n+1], ycol int32[nnz_y]
  * (ascending node id per row), yval float64[nnz_y] (FP64 factor) or float32[nnz_y]

@@ -10,8 +10,7 @@
 //   tally         one wave per row: LDS bitonic sort + run-length of end nodes
 //                 (H'_{k,i}), wave sums of stays (J'_k) -- no global atomics
 //   factor        eqs. newy, newz, d and the drop (Sections 3.3, 4, 5.2), FP64
-//   transpose     Y^T by a stable radix sort of the entries on their column
-//   levels        dependency levels of both triangular solves (Kahn frontiers)
+//   transpose     Y^T by a stable radix sort of the entries on (column, source rank)
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -239,26 +238,39 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
 }
 
 // ------------------------------------------------------------- walk schedule
-__global__ void k_flag_walking(int64_t n, const int32_t* __restrict__ by_rank,
-                               const int32_t* __restrict__ budget, int32_t* flag)
+// Work is cut into chunks of up to 64 walks of one row.  Chunks come in NSEG
+// segments: segment 0 holds the rows ranked below `long_rank` (their walks meet few
+// homes and run longest) in rank order, so they start first; segments 1..8 split the
+// remaining rows by node id into eight slabs, one per XCD, so the walks in flight on
+// one XCD share a compact part of the graph and of that XCD's L2.
+constexpr int NSLAB = 8;
+constexpr int NSEG = NSLAB + 1;
+
+__global__ void k_flag_long(int64_t n, int64_t long_rank, const int32_t* __restrict__ by_rank,
+                            const int32_t* __restrict__ budget, int32_t* flag)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) flag[p] = budget[by_rank[p]] > 0 ? 1 : 0;
+    if (p < long_rank) flag[p] = budget[by_rank[p]] > 0 ? 1 : 0;
 }
 
-__global__ void k_compact_order(int64_t n, const int32_t* __restrict__ by_rank,
-                                const int32_t* __restrict__ budget,
-                                const int64_t* __restrict__ pos, int32_t* order,
-                                int32_t* chunks)
+__global__ void k_flag_slab(int64_t n, int64_t long_rank, const int32_t* __restrict__ rank,
+                            const int32_t* __restrict__ budget, int32_t* flag)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t v = by_rank[p];
-    const int32_t b = budget[v];
-    if (b > 0) {
-        order[pos[p]] = v;
-        chunks[pos[p]] = (b + SRW_WAVE - 1) / SRW_WAVE;
-    }
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = (budget[v] > 0 && rank[v] >= long_rank) ? 1 : 0;
+}
+
+// order[pos] = row, chunks[pos] = its number of chunks
+__global__ void k_compact(int64_t count, const int32_t* __restrict__ rows_or_null,
+                          const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                          int64_t base, const int32_t* __restrict__ budget, int32_t* order,
+                          int32_t* chunks)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count || !flag[i]) return;
+    const int32_t v = rows_or_null ? rows_or_null[i] : (int32_t)i;
+    order[base + pos[i]] = v;
+    chunks[base + pos[i]] = (budget[v] + SRW_WAVE - 1) / SRW_WAVE;
 }
 
 __global__ void k_read_last(const int64_t* scan, const int32_t* last_in, int64_t n, int64_t* out)
@@ -266,30 +278,60 @@ __global__ void k_read_last(const int64_t* scan, const int32_t* last_in, int64_t
     out[0] = n > 0 ? scan[n - 1] + (int64_t)last_in[n - 1] : 0;
 }
 
+// chunk descriptor: x = row, y = first walk | (walk count << 16)
+__global__ void k_chunks(int64_t norder, const int32_t* __restrict__ order,
+                         const int64_t* __restrict__ chunk_off, const int32_t* __restrict__ budget,
+                         uint2* __restrict__ cdesc)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= norder) return;
+    const int32_t v = order[j];
+    const int32_t b = budget[v];
+    for (int64_t c = chunk_off[j]; c < chunk_off[j + 1]; ++c) {
+        const uint32_t w0 = (uint32_t)(c - chunk_off[j]) * SRW_WAVE;
+        const uint32_t cnt = min((uint32_t)SRW_WAVE, (uint32_t)b - w0);
+        cdesc[c] = make_uint2((uint32_t)v, w0 | (cnt << 16));
+    }
+}
+
+// bounds[0..NSEG]: first chunk of each segment (bounds[NSEG] = all chunks)
+__global__ void k_seg_bounds(int64_t n, int64_t nlong, int64_t nslab_rows,
+                             const int64_t* __restrict__ pos_slab,
+                             const int64_t* __restrict__ chunk_off, int64_t* bounds)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    bounds[0] = 0;
+    for (int x = 0; x < NSLAB; ++x) {
+        const int64_t node = (int64_t)x * n / NSLAB;
+        const int64_t opos = nlong + (node < n ? pos_slab[node] : nslab_rows);
+        bounds[1 + x] = chunk_off[opos];
+    }
+    bounds[NSEG] = chunk_off[nlong + nslab_rows];
+}
+
 // ----------------------------------------------------------------------- walks
 struct WalkArgs {
     const uint4* desc;
     const uint2* ent;
     const uint32_t* mthr;
-    const int32_t* order;
-    const int64_t* chunk_off;
-    const int32_t* budget;
+    const uint2* chunks;       // chunk descriptors
+    const int64_t* bounds;     // NSEG + 1 segment starts
     const int64_t* rec_off;
-    int64_t norder;
-    uint64_t n_chunks;
     uint64_t seed;
     uint64_t max_steps;
     uint32_t* rec_end;
     uint32_t* rec_vis;
     uint32_t* rec_len;
     unsigned long long* queue;
+    unsigned long long* deg_sum;
     int* err;
 };
 
 // Persistent walk kernel.  Every wave owns up to 64 walks at a time, one per lane.
 // Every R steps the idle lanes of a wave take the next walks of the current chunk
 // (up to 64 walks of one row); an exhausted chunk is replaced by the next one from
-// a global queue ordered by rank (longest walks first).  A lane's draws come from
+// the segment queues: the long-walk segment first, then the wave's own slab (by the
+// XCD its workgroup runs on), then the other slabs in turn.  A lane's draws come from
 // the Philox block of its (row, walk, step div 8), generated when step mod 8 = 0.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
@@ -299,11 +341,13 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
     // wave-uniform chunk state
     uint32_t c_row = 0, c_next = 0, c_end = 0;
     bool done = false;
+    const int home = 1 + (int)(blockIdx.x % NSLAB);
+    int seg = 0, tried = 0;
     // per-lane walk state
     bool active = false;
     uint32_t k = 0, w = 0, visits = 0, rank_k = 0, last_motel = 0;
     uint32_t cs = 0, cd = 0;  // current node: first entry, degree | flags
-    uint64_t t = 0, rec = 0;
+    uint64_t t = 0, rec = 0, degsum = 0;
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0, q7 = 0;
 
     for (uint32_t iter = 0;; ++iter) {
@@ -311,22 +355,29 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
             uint64_t idle = ballot(!active);
             while (idle != 0) {
                 if (c_next >= c_end) {
-                    unsigned long long c = 0;
-                    if (lane == 0) c = atomicAdd(a.queue, 1ull);
-                    c = __shfl(c, 0, 64);
-                    if (c >= a.n_chunks) {
-                        done = true;
-                        break;
+                    // next chunk: long segment, then home slab, then the other slabs
+                    bool got = false;
+                    unsigned long long cidx = 0;
+                    while (!done && !got) {
+                        const int sq = seg == 0 ? 0 : 1 + (home - 1 + tried) % NSLAB;
+                        const unsigned long long size =
+                            (unsigned long long)(a.bounds[sq + 1] - a.bounds[sq]);
+                        const unsigned long long c =
+                            lane0_u64(atomicAdd(&a.queue[sq], lane == 0 ? 1ull : 0ull));
+                        if (c < size) {
+                            got = true;
+                            cidx = (unsigned long long)a.bounds[sq] + c;
+                        } else if (seg == 0) {
+                            seg = 1;
+                        } else if (++tried >= NSLAB) {
+                            done = true;
+                        }
                     }
-                    int64_t lo = 0, hi = a.norder - 1;
-                    while (lo < hi) {
-                        const int64_t mid = (lo + hi + 1) >> 1;
-                        if ((unsigned long long)a.chunk_off[mid] <= c) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    c_row = (uint32_t)a.order[lo];
-                    c_next = (uint32_t)(c - (unsigned long long)a.chunk_off[lo]) * SRW_WAVE;
-                    c_end = min(c_next + SRW_WAVE, (uint32_t)a.budget[c_row]);
+                    if (done) break;
+                    const uint2 cd = a.chunks[cidx];
+                    c_row = cd.x;
+                    c_next = cd.y & 0xFFFFu;
+                    c_end = c_next + (cd.y >> 16);
                 }
                 const uint32_t avail = c_end - c_next;
                 const uint32_t pos = (uint32_t)__popcll(idle & lt);
@@ -353,8 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
             if (done) break;
             continue;
         }
-        if (!active) continue;
-
+        if (active) {  // structured: the lanes rejoin before the next refill's ballots
         if ((t & 7) == 0) {
             const u64x4 b = philox4x64_10(t >> 3, w, k, STREAM_WALK, a.seed, 0);
             q0 = (uint32_t)b.x0; q1 = (uint32_t)(b.x0 >> 32);
@@ -366,6 +416,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
         q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
 
         const uint32_t deg = cd & DESC_DEG_MASK;
+        degsum += deg;
         uint32_t nxt = 0;
         bool to_ground = false;
         if (t == 0) {
@@ -430,7 +481,10 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
             a.rec_len[rec] = (uint32_t)t;
             active = false;
         }
+        }  // active
     }
+    degsum = wave_sum(degsum);
+    if (lane == 0 && degsum) atomicAdd(a.deg_sum, (unsigned long long)degsum);
 }
 
 // --------------------------------------------------------------------- tallies
@@ -595,14 +649,20 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
 }
 
 // ------------------------------------------------------------------- transpose
-__global__ void k_entry_rows(int64_t n, const int64_t* __restrict__ yptr, uint32_t* rowid,
-                             uint32_t* idx)
+// Sort key of entry (k, i) of Y for the rows of Y^T: column i first, then the rank
+// of k descending -- the order in which the backward substitution finishes the
+// w_k it needs, so a long Y^T row meets its last-ready values at its end.
+__global__ void k_entry_keys(int64_t n, const int64_t* __restrict__ yptr,
+                             const int32_t* __restrict__ ycol, const int32_t* __restrict__ rank,
+                             int rank_bits, uint32_t* rowid, uint32_t* idx, uint64_t* key)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    const uint64_t rdesc = (uint64_t)(n - 1 - rank[k]);
     for (int64_t q = yptr[k]; q < yptr[k + 1]; ++q) {
         rowid[q] = (uint32_t)k;
         idx[q] = (uint32_t)q;
+        key[q] = ((uint64_t)(uint32_t)ycol[q] << rank_bits) | rdesc;
     }
 }
 
@@ -626,35 +686,6 @@ __global__ void k_transpose_fill(int64_t nnz, const uint32_t* __restrict__ sorte
 
 __global__ void k_set_last(int64_t* ptr, int64_t n, int64_t v) { ptr[n] = v; }
 
-// ---------------------------------------------------------------------- levels
-__global__ void k_indeg(int64_t n, const int64_t* __restrict__ ptr, int32_t* indeg)
-{
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) indeg[v] = (int32_t)(ptr[v + 1] - ptr[v]);
-}
-
-__global__ void k_frontier0(int64_t n, const int32_t* __restrict__ indeg, int32_t* queue,
-                            unsigned long long* tail)
-{
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n && indeg[v] == 0) queue[atomicAdd(tail, 1ull)] = (int32_t)v;
-}
-
-// Releases the dependents of one level; a dependent whose last dependency this was
-// joins the next level.
-__global__ void k_kahn(const int32_t* __restrict__ queue_in, int64_t qs, int64_t qe,
-                       const int64_t* __restrict__ dptr, const int32_t* __restrict__ dcol,
-                       int32_t* indeg, int32_t* queue, unsigned long long* tail)
-{
-    const int64_t i = qs + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= qe) return;
-    const int32_t v = queue_in[i];
-    for (int64_t q = dptr[v]; q < dptr[v + 1]; ++q) {
-        const int32_t u = dcol[q];
-        if (atomicSub(&indeg[u], 1) == 1) queue[atomicAdd(tail, 1ull)] = u;
-    }
-}
-
 __global__ void k_sum_u64(int64_t n, const uint64_t* __restrict__ x, unsigned long long* out)
 {
     uint64_t s = 0;
@@ -671,38 +702,6 @@ int map_err(int e)
     if (e & ERR_NOT_R) return SRW_E_NOT_RMATRIX;
     if (e & ERR_SINGULAR) return SRW_E_SINGULAR;
     if (e & ERR_LIMIT) return SRW_E_WALK_LIMIT;
-    return SRW_OK;
-}
-
-// Dependency levels of a unit-triangular solve.  deps(v) = row v of (dptr, dcol)'s
-// transpose... expressed as: indeg(v) = #entries of row v in (rptr); dependents(v) =
-// row v of (dptr, dcol).
-int levels(int64_t n, const int64_t* rptr, const int64_t* dptr, const int32_t* dcol,
-           int32_t* queue, std::vector<int64_t>& lptr, Arena& tmp, int64_t* pinned,
-           hipStream_t s)
-{
-    int32_t* indeg = tmp.alloc<int32_t>(n);
-    unsigned long long* tail = tmp.alloc<unsigned long long>(1);
-    if (!indeg || !tail) return SRW_E_NOMEM;
-    const int g = grid_for(n, BLOCK);
-    k_indeg<<<g, BLOCK, 0, s>>>(n, rptr, indeg);
-    SRW_HIP(hipMemsetAsync(tail, 0, sizeof(unsigned long long), s));
-    k_frontier0<<<g, BLOCK, 0, s>>>(n, indeg, queue, tail);
-    lptr.assign(1, 0);
-    int64_t qs = 0;
-    for (;;) {
-        SRW_HIP(hipMemcpyAsync(pinned, tail, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SRW_HIP(hipStreamSynchronize(s));
-        const int64_t qe = pinned[0];
-        if (qe == qs) break;
-        lptr.push_back(qe);
-        if (qe >= n) break;
-        k_kahn<<<grid_for(qe - qs, BLOCK), BLOCK, 0, s>>>(queue, qs, qe, dptr, dcol, indeg, queue,
-                                                         tail);
-        SRW_HIP(hipGetLastError());
-        qs = qe;
-    }
-    if (lptr.back() != n) return SRW_E_HIP;  // a cycle cannot occur in a triangular factor
     return SRW_OK;
 }
 
@@ -729,8 +728,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
     srw_options opt;
     srw_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    if (opt.max_steps == 0) opt.max_steps = 1ull << 24;
-    if (opt.refill_period == 0) opt.refill_period = 1;
+    if (opt.max_steps == 0) opt.max_steps = 1ull << 22;
+    if (opt.refill_period == 0) opt.refill_period = 8;
     const int64_t n = A->n, nnz = A->nnz;
     const int64_t nnz_off = nnz - n;
 
@@ -758,6 +757,14 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
     } while (0)
 #define ALLOC(arena, T, cnt) (arena).alloc<T>(cnt)
 
+    hipEvent_t ev[SRW_NUM_PHASES + 1] = {};
+    const bool prof = opt.profile != 0;
+    auto mark = [&](int i) {
+        if (prof) (void)hipEventRecord(ev[i], s);
+    };
+    if (prof)
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) e = nullptr;
     {
         CHECK_HIP(hipHostMalloc((void**)&pinned, 8 * sizeof(int64_t), hipHostMallocDefault));
         const int g = grid_for(n, BLOCK);
@@ -776,6 +783,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         F->grounded = grounded;
 
         // ---- 1. validation
+        mark(0);
         CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
         k_check_structure<<<g, BLOCK, 0, s>>>(n, nnz, A->rowptr, A->col, err);
         CHECK_HIP(hipGetLastError());
@@ -803,6 +811,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipGetLastError());
 
         // ---- 2. ordering
+        mark(1);
         if (opt.ordering == SRW_ORDER_GIVEN) {
             if (!opt.rank) FAIL(SRW_E_ARG);
             int32_t* seen = ALLOC(tmp, int32_t, n);
@@ -840,73 +849,92 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         F->mthr = mthr;
         F->tau = tau;
         F->budget = budget;
+        mark(2);
         CHECK_HIP(hipMemsetAsync(maxb, 0, sizeof(int32_t), s));
         k_table<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, grounded, walks_per_row,
                                     opt.walks, ent, mthr, desc, tau, budget, maxb);
         CHECK_HIP(hipGetLastError());
 
-        // record offsets (node order) and the rank-ordered list of walking rows
+        // record offsets (node order) and the segmented chunk list
         int64_t* rec_off = ALLOC(keep, int64_t, n);
         int32_t* flag = ALLOC(tmp, int32_t, n);
+        int32_t* flag2 = ALLOC(tmp, int32_t, n);
         int64_t* pos = ALLOC(tmp, int64_t, n);
+        int64_t* pos2 = ALLOC(tmp, int64_t, n);
         int32_t* order = ALLOC(tmp, int32_t, n);
-        int32_t* chunks = ALLOC(tmp, int32_t, n);
+        int32_t* chunks = ALLOC(tmp, int32_t, n + 1);
         int64_t* chunk_off = ALLOC(tmp, int64_t, n + 1);
-        int64_t* tot = ALLOC(tmp, int64_t, 4);
+        int64_t* tot = ALLOC(tmp, int64_t, 8);
+        int64_t* bounds = ALLOC(tmp, int64_t, NSEG + 1);
         void* st = ALLOC(tmp, char, scan_tmp_bytes(n + 1));
-        if (!rec_off || !flag || !pos || !order || !chunks || !chunk_off || !tot || !st)
+        if (!rec_off || !flag || !flag2 || !pos || !pos2 || !order || !chunks || !chunk_off ||
+            !tot || !bounds || !st)
             FAIL(SRW_E_NOMEM);
         F->rec_off = rec_off;
+        mark(3);
+        // schedule 0: every walking row in the rank-ordered segment
+        const int64_t long_rank = opt.schedule == 1 ? std::max<int64_t>(1, n / 256) : n;
         CHECK_HIP(exclusive_scan_i32_to_i64(budget, rec_off, n, st, s));
         k_read_last<<<1, 1, 0, s>>>(rec_off, budget, n, tot + 0);
-        k_flag_walking<<<g, BLOCK, 0, s>>>(n, F->by_rank, budget, flag);
-        CHECK_HIP(exclusive_scan_i32_to_i64(flag, pos, n, st, s));
-        k_read_last<<<1, 1, 0, s>>>(pos, flag, n, tot + 1);
-        k_compact_order<<<g, BLOCK, 0, s>>>(n, F->by_rank, budget, pos, order, chunks);
-        CHECK_HIP(hipGetLastError());
-        CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        CHECK_HIP(hipMemcpyAsync(&pinned[2], maxb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        k_flag_long<<<grid_for(long_rank, BLOCK), BLOCK, 0, s>>>(n, long_rank, F->by_rank, budget, flag);
+        CHECK_HIP(exclusive_scan_i32_to_i64(flag, pos, long_rank, st, s));
+        k_read_last<<<1, 1, 0, s>>>(pos, flag, long_rank, tot + 1);
+        k_flag_slab<<<g, BLOCK, 0, s>>>(n, long_rank, F->rank, budget, flag2);
+        CHECK_HIP(exclusive_scan_i32_to_i64(flag2, pos2, n, st, s));
+        k_read_last<<<1, 1, 0, s>>>(pos2, flag2, n, tot + 2);
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipMemcpyAsync(&pinned[3], maxb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipStreamSynchronize(s));
         const int64_t total_walks = pinned[0];
-        const int64_t norder = pinned[1];
+        const int64_t nlong = pinned[1];
+        const int64_t nslab_rows = pinned[2];
+        const int64_t norder = nlong + nslab_rows;
         int32_t max_budget = 0;
-        std::memcpy(&max_budget, &pinned[2], sizeof(int32_t));
+        std::memcpy(&max_budget, &pinned[3], sizeof(int32_t));
+        k_compact<<<grid_for(long_rank, BLOCK), BLOCK, 0, s>>>(long_rank, F->by_rank, flag, pos, 0,
+                                                               budget, order, chunks);
+        k_compact<<<g, BLOCK, 0, s>>>(n, nullptr, flag2, pos2, nlong, budget, order, chunks);
         CHECK_HIP(exclusive_scan_i32_to_i64(chunks, chunk_off, norder, st, s));
-        k_read_last<<<1, 1, 0, s>>>(chunk_off, chunks, norder, tot + 2);
-        CHECK_HIP(hipMemcpyAsync(&pinned[3], tot + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        k_read_last<<<1, 1, 0, s>>>(chunk_off, chunks, norder, tot + 3);
+        CHECK_HIP(hipMemcpyAsync(&pinned[4], tot + 3, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipStreamSynchronize(s));
-        const int64_t n_chunks = pinned[3];
+        const int64_t n_chunks = pinned[4];
         F->walks_total = total_walks;
+        uint2* cdesc = ALLOC(tmp, uint2, n_chunks);
+        if (!cdesc) FAIL(SRW_E_NOMEM);
+        k_set_last<<<1, 1, 0, s>>>(chunk_off, norder, n_chunks);
+        k_chunks<<<grid_for(norder, BLOCK), BLOCK, 0, s>>>(norder, order, chunk_off, budget, cdesc);
+        k_seg_bounds<<<1, 1, 0, s>>>(n, nlong, nslab_rows, pos2, chunk_off, bounds);
+        CHECK_HIP(hipGetLastError());
 
         // ---- 4. walks
         uint32_t* rec_end = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
         uint32_t* rec_vis = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
         uint32_t* rec_len = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
-        unsigned long long* queue = ALLOC(tmp, unsigned long long, 1);
+        unsigned long long* queue = ALLOC(tmp, unsigned long long, NSEG + 1);
         if (!rec_end || !rec_vis || !rec_len || !queue) FAIL(SRW_E_NOMEM);
+        CHECK_HIP(hipMemsetAsync(queue, 0, (NSEG + 1) * sizeof(unsigned long long), s));
         if (opt.keep >= 2) {
             F->rec_end = rec_end;
             F->rec_vis = rec_vis;
             F->rec_len = rec_len;
         }
+        mark(4);
         if (n_chunks > 0) {
-            CHECK_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned long long), s));
             WalkArgs wa;
             wa.desc = desc;
             wa.ent = ent;
             wa.mthr = mthr;
-            wa.order = order;
-            wa.chunk_off = chunk_off;
-            wa.budget = budget;
+            wa.chunks = cdesc;
+            wa.bounds = bounds;
             wa.rec_off = rec_off;
-            wa.norder = norder;
-            wa.n_chunks = (uint64_t)n_chunks;
             wa.seed = seed;
             wa.max_steps = opt.max_steps;
             wa.rec_end = rec_end;
             wa.rec_vis = rec_vis;
             wa.rec_len = rec_len;
             wa.queue = queue;
+            wa.deg_sum = queue + NSEG;
             wa.err = err;
             int dev = 0, cus = 0;
             CHECK_HIP(hipGetDevice(&dev));
@@ -923,10 +951,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             }
             CHECK_HIP(hipGetLastError());
         }
+        mark(5);
+        CHECK_HIP(hipMemcpyAsync(&pinned[5], queue + NSEG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipMemcpyAsync(&pinned[0], err, sizeof(int), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipStreamSynchronize(s));
         std::memcpy(&herr, &pinned[0], sizeof(int));
         if (herr) FAIL(map_err(herr));
+        F->deg_sum = pinned[5];
 
         // ---- 5. tallies
         uint64_t* tJ = ALLOC(keep, uint64_t, n);
@@ -975,6 +1006,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         // ---- 6. factor
         int32_t* ynnz = ALLOC(tmp, int32_t, n);
         if (!ynnz) FAIL(SRW_E_NOMEM);
+        mark(6);
         k_factor<double, false><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
                                                     budget, tJ, rec_off, hlen, h_end, h_cnt,
                                                     drop_tol, ynnz, nullptr, nullptr, nullptr,
@@ -1007,23 +1039,22 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipGetLastError());
 
         // ---- 7. Y^T by a stable sort of the entries on their column
+        mark(7);
         {
             uint32_t* rowid = ALLOC(tmp, uint32_t, nnz_y);
             uint32_t* idx = ALLOC(tmp, uint32_t, nnz_y);
             uint32_t* idx2 = ALLOC(tmp, uint32_t, nnz_y);
-            uint32_t* kcol2 = ALLOC(tmp, uint32_t, nnz_y);
-            uint32_t* kcol = ALLOC(tmp, uint32_t, nnz_y);
+            uint64_t* key = ALLOC(tmp, uint64_t, nnz_y);
+            uint64_t* key2 = ALLOC(tmp, uint64_t, nnz_y);
             int32_t* ccount = ALLOC(tmp, int32_t, n);
             void* rt = ALLOC(tmp, char, radix_tmp_bytes(nnz_y));
-            if (!rowid || !idx || !idx2 || !kcol2 || !kcol || !ccount || !rt) FAIL(SRW_E_NOMEM);
-            k_entry_rows<<<g, BLOCK, 0, s>>>(n, F->yptr, rowid, idx);
-            CHECK_HIP(hipMemcpyAsync(kcol, F->ycol, nnz_y * sizeof(uint32_t),
-                                     hipMemcpyDeviceToDevice, s));
-            int bits = 8;
-            while (bits < 32 && ((int64_t)1 << bits) < n) bits += 8;
-            uint32_t* ko;
+            if (!rowid || !idx || !idx2 || !key || !key2 || !ccount || !rt) FAIL(SRW_E_NOMEM);
+            int rbits = 1;
+            while (rbits < 31 && ((int64_t)1 << rbits) < n) ++rbits;
+            k_entry_keys<<<g, BLOCK, 0, s>>>(n, F->yptr, F->ycol, F->rank, rbits, rowid, idx, key);
+            uint64_t* ko;
             uint32_t* vo;
-            CHECK_HIP(radix_sort_u32(kcol, idx, kcol2, idx2, nnz_y, bits, rt, &ko, &vo, s));
+            CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, 2 * rbits, rt, &ko, &vo, s));
             CHECK_HIP(hipMemsetAsync(ccount, 0, n * sizeof(int32_t), s));
             k_col_count<<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(nnz_y, F->ycol, ccount);
             CHECK_HIP(exclusive_scan_i32_to_i64(ccount, F->ytptr, n, st, s));
@@ -1037,17 +1068,15 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipGetLastError());
         }
 
-        // ---- 8. level schedules
-        F->fwd_rows = ALLOC(keep, int32_t, n);
-        F->bwd_rows = ALLOC(keep, int32_t, n);
-        if (!F->fwd_rows || !F->bwd_rows) FAIL(SRW_E_NOMEM);
-        // Y z = v: row v waits for the entries of its Y row; releases its Y^T row.
-        status = levels(n, F->yptr, F->ytptr, F->ytcol, F->fwd_rows, F->fwd_lptr, tmp, pinned, s);
-        if (status) goto done;
-        // Y^T w = r: row v waits for its Y^T row; releases its Y row.
-        status = levels(n, F->ytptr, F->yptr, F->ycol, F->bwd_rows, F->bwd_lptr, tmp, pinned, s);
-        if (status) goto done;
+        mark(8);
         CHECK_HIP(hipStreamSynchronize(s));
+        if (prof) {
+            for (int i = 0; i < SRW_NUM_PHASES; ++i) {
+                float ms = -1.0f;
+                if (ev[i] && ev[i + 1] && hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess)
+                    F->phase_ms[i] = ms;
+            }
+        }
         if (keep.last != hipSuccess || tmp.last != hipSuccess) FAIL(SRW_E_NOMEM);
     }
 
@@ -1062,6 +1091,8 @@ done:
     }
     tmp.release();
     if (pinned) (void)hipHostFree(pinned);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (status != SRW_OK) {
         keep.release();
         delete F;

@@ -39,6 +39,8 @@ void srw_default_options(srw_options* opt)
     opt->max_steps = 0;
     opt->keep = 0;
     opt->refill_period = 0;
+    opt->profile = 0;
+    opt->schedule = 1;
 }
 
 int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
@@ -54,6 +56,7 @@ int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, u
         if (opt->keep < 0 || opt->keep > 2) return SRW_E_ARG;
         const int rp = opt->refill_period;
         if (rp != 0 && rp != 1 && rp != 2 && rp != 4 && rp != 8) return SRW_E_ARG;
+        if (opt->schedule != 0 && opt->schedule != 1) return SRW_E_ARG;
         if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && A->n > 0) return SRW_E_ARG;
     }
     if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
@@ -78,10 +81,40 @@ int srw_factor_info(const srw_factor* F, int64_t* n, int64_t* nnz_y, int64_t* wa
     if (nnz_y) *nnz_y = F->nnz_y;
     if (walks) *walks = F->walks_total;
     if (walk_steps) *walk_steps = F->steps_total;
-    if (levels_fwd) *levels_fwd = (int32_t)(F->fwd_lptr.empty() ? 0 : F->fwd_lptr.size() - 1);
-    if (levels_bwd) *levels_bwd = (int32_t)(F->bwd_lptr.empty() ? 0 : F->bwd_lptr.size() - 1);
+    if (levels_fwd) *levels_fwd = F->depth;
+    if (levels_bwd) *levels_bwd = F->depth;
     if (precision) *precision = F->precision;
     if (keep) *keep = F->keep;
+    return SRW_OK;
+}
+
+int srw_factor_stats(const srw_factor* F, srw_stats* out)
+{
+    if (!F || !out) return SRW_E_ARG;
+    out->n = F->n;
+    out->nnz_a = F->nnz_a;
+    out->nnz_y = F->nnz_y;
+    out->walks = F->walks_total;
+    out->walk_steps = F->steps_total;
+    out->walk_deg_sum = F->deg_sum;
+    out->levels_fwd = F->depth;
+    out->levels_bwd = F->depth;
+    out->precision = F->precision;
+    out->keep = F->keep;
+    for (int i = 0; i < SRW_NUM_PHASES; ++i) out->phase_ms[i] = F->phase_ms[i];
+    return SRW_OK;
+}
+
+int srw_factor_depth(srw_factor* F, int32_t* depth, void* stream)
+{
+    if (!F || !depth) return SRW_E_ARG;
+    if (F->depth < 0) {
+        int32_t d = 0;
+        const int st = srw::dag_depth(F, &d, as_stream(stream));
+        if (st != SRW_OK) return st;
+        F->depth = d;
+    }
+    *depth = F->depth;
     return SRW_OK;
 }
 

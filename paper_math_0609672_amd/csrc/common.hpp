@@ -81,6 +81,17 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Lane 0's value as a wave-uniform (scalar) value.  v_readlane reads the lane whatever
+// the execution mask, and the scalar result lets the compiler keep every branch on
+// it uniform -- a broadcast through a shuffle would not, and the structurizer may then
+// place the shuffle where lane 0's register no longer holds the value.
+__device__ __forceinline__ uint64_t lane0_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint32_t readfirstlane(uint32_t v)
 {
     return __builtin_amdgcn_readfirstlane(v);

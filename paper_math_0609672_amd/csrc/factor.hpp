@@ -16,6 +16,8 @@ struct srw_factor {
     int64_t nnz_y = 0;
     int64_t walks_total = 0;
     int64_t steps_total = 0;
+    int64_t deg_sum = 0;
+    double phase_ms[SRW_NUM_PHASES] = {-1, -1, -1, -1, -1, -1, -1, -1};
 
     int32_t* rank = nullptr;     // [n]
     int32_t* by_rank = nullptr;  // [n] node of each rank
@@ -27,10 +29,8 @@ struct srw_factor {
     void* ytval = nullptr;       // [nnz_y]
     void* d = nullptr;           // [n] double or float
 
-    // dependency-level schedules: rows of level L are rows[lptr[L] .. lptr[L+1])
-    int32_t* fwd_rows = nullptr;  // Y z = v, increasing rank
-    int32_t* bwd_rows = nullptr;  // Y^T w = r, decreasing rank
-    std::vector<int64_t> fwd_lptr, bwd_lptr;
+    // longest dependency chain of the triangular solves, -1 until srw_factor_depth
+    int32_t depth = -1;
 
     // kept on request (srw_options.keep)
     uint2* ent = nullptr;          // [nnz-n] {neighbour, threshold}
@@ -91,6 +91,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
+int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);
 void free_factor(srw_factor* F);
 
 }  // namespace srw

@@ -18,7 +18,8 @@ constexpr int64_t SCAN_TILE = (int64_t)SCAN_BLOCK * SCAN_ITEMS;
 // Block-wide exclusive scan of one int64 per thread; returns the block total.
 __device__ int64_t block_exclusive(int64_t v, int64_t* out_excl, int64_t* lds_waves)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
     int64_t incl = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(RADIX_BLOCK) void radix_hist(const K* keys, int64_t
                                                           int64_t ntile, int32_t* hist)
 {
     __shared__ int32_t cnt[RADIX_BLOCK / 64][256];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
     for (int d = lane; d < 256; d += 64) cnt[wave][d] = 0;
     __syncthreads();
     const int64_t tile = (int64_t)blockIdx.x * (RADIX_BLOCK / 64) + wave;
@@ -153,7 +155,8 @@ __global__ __launch_bounds__(RADIX_BLOCK) void radix_scatter(const K* keys, cons
                                                              const int64_t* offs)
 {
     __shared__ int64_t off[RADIX_BLOCK / 64][256];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
     const int64_t tile = (int64_t)blockIdx.x * (RADIX_BLOCK / 64) + wave;
     if (tile >= ntile) return;  // whole wave leaves; no block barrier below
     for (int d = lane; d < 256; d += 64) off[wave][d] = offs[(int64_t)d * ntile + tile];

@@ -35,7 +35,20 @@ class _Csr(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int32), ("rank", ctypes.c_void_p), ("walks", ctypes.c_void_p),
                 ("factor_precision", ctypes.c_int32), ("max_steps", ctypes.c_uint64),
-                ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32)]
+                ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
+NUM_PHASES = 8
+PHASES = ("validate", "rank", "table", "schedule", "walk", "tally", "factor", "transpose")
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz_a", ctypes.c_int64), ("nnz_y", ctypes.c_int64),
+                ("walks", ctypes.c_int64), ("walk_steps", ctypes.c_int64),
+                ("walk_deg_sum", ctypes.c_int64), ("levels_fwd", ctypes.c_int32),
+                ("levels_bwd", ctypes.c_int32), ("precision", ctypes.c_int32), ("keep", ctypes.c_int32),
+                ("phase_ms", ctypes.c_double * NUM_PHASES)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -48,6 +61,8 @@ _lib.srw_build_factor.argtypes = [ctypes.POINTER(_Csr), _I32, _D, _U64, ctypes.P
                                   ctypes.POINTER(_P), _P]
 _lib.srw_factor_free.argtypes = [_P]
 _lib.srw_factor_info.argtypes = [_P] + [_P] * 8
+_lib.srw_factor_stats.argtypes = [_P, ctypes.POINTER(_Stats)]
+_lib.srw_factor_depth.argtypes = [_P, ctypes.POINTER(_I32), _P]
 _lib.srw_factor_export.argtypes = [_P, _P, _P, _P, _P, _P, _P]
 _lib.srw_table_export.argtypes = [_P, _P, _P, _P, _P, _P, _P]
 _lib.srw_tally_export.argtypes = [_P] + [_P] * 9 + [_P]
@@ -59,6 +74,7 @@ _lib.srw_status_string.argtypes = [ctypes.c_int]
 _lib.srw_status_string.restype = ctypes.c_char_p
 
 EXPORTED = ["srw_default_options", "srw_build_factor", "srw_factor_free", "srw_factor_info",
+            "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
             "srw_pcg_solve", "srw_apply", "srw_status_string"]
 
@@ -128,6 +144,19 @@ class Factor:
                     levels_fwd=lf.value, levels_bwd=lb.value,
                     precision="fp32" if prec.value == FP32 else "fp64", keep=keep.value)
 
+    def stats(self) -> dict:
+        st = _Stats()
+        _check(_lib.srw_factor_stats(self._h, ctypes.byref(st)), "srw_factor_stats")
+        d = {f: getattr(st, f) for f, _ in _Stats._fields_ if f != "phase_ms"}
+        d["phase_ms"] = {name: st.phase_ms[i] for i, name in enumerate(PHASES)}
+        return d
+
+    def depth(self, stream=None) -> int:
+        """srw_factor_depth: longest dependency chain of the triangular solves."""
+        d = _I32(0)
+        _check(_lib.srw_factor_depth(self._h, ctypes.byref(d), _stream(stream)), "srw_factor_depth")
+        return d.value
+
     def export(self, stream=None) -> dict:
         i = self.info()
         n, m = i["n"], i["nnz_y"]
@@ -190,7 +219,7 @@ def _check(st: int, what: str):
 
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
-                 stream=None) -> Factor:
+                 profile: bool = False, schedule: int = 1, stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A."""
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
@@ -203,6 +232,8 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
     opt.max_steps = int(max_steps)
     opt.keep = int(keep)
     opt.refill_period = int(refill_period)
+    opt.profile = 1 if profile else 0
+    opt.schedule = int(schedule)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),

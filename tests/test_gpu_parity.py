@@ -74,9 +74,9 @@ def test_table_bit_exact(srw, name):
     assert np.array_equal(np_(tb["grounded"]), ref.grounded)
 
 
-def compare_walks(srw, A, walks, seed, budget=None, refill=0):
+def compare_walks(srw, A, walks, seed, budget=None, refill=0, schedule=0):
     Mx = srw.Matrix.from_host(A, DEV)
-    kw = dict(keep=2, refill_period=refill)
+    kw = dict(keep=2, refill_period=refill, schedule=schedule)
     if budget is not None:
         kw["walks"] = torch.as_tensor(budget, dtype=torch.int32, device=DEV)
     F = srw.build_factor(Mx, walks, 0.0, seed, **kw)
@@ -115,9 +115,10 @@ def test_walks_and_tallies_bit_exact(srw, name):
 
 
 @pytest.mark.parametrize("refill", [1, 2, 4, 8])
-def test_walks_independent_of_scheduling(srw, refill):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_walks_independent_of_scheduling(srw, refill, schedule):
     A, walks = CASES["grid3d_12"]
-    compare_walks(srw, A, walks, 21, refill=refill)
+    compare_walks(srw, A, walks, 21, refill=refill, schedule=schedule)
 
 
 def test_per_row_budgets_ragged(srw):
@@ -203,7 +204,7 @@ def test_diagonal_matrix_all_rows_exact(srw):
     A = W.from_dense(np.diag(np.linspace(1.0, 3.0, 100)))
     M, F = gpu_build(srw, A, 64, 0.0, 0)
     i = F.info()
-    assert i["nnz_y"] == 0 and i["walks"] == 0 and i["levels_fwd"] == 1
+    assert i["nnz_y"] == 0 and i["walks"] == 0 and F.depth() == 1
     b = W.rhs(100, seed=0)
     st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), 1e-12)
     assert st == 0 and it == 1

@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=1)
+    ap.add_argument("--solve-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU baseline)")
     return ap.parse_args()
@@ -113,7 +114,8 @@ def main():
     def step():
         t0 = time.perf_counter()
         F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
-                             refill_period=args.refill, schedule=args.schedule, profile=True)
+                             refill_period=args.refill, schedule=args.schedule,
+                             solve_order=args.solve_order, profile=True)
         t1 = time.perf_counter()
         st, _, it, rel = srw.pcg_solve(M, F, b, tol, 10000, x=x)
         t2 = time.perf_counter()
@@ -140,7 +142,8 @@ def main():
     K = args.steps
     s0 = runs[-1]["stats"]
     F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
-                         refill_period=args.refill, schedule=args.schedule)
+                         refill_period=args.refill, schedule=args.schedule,
+                         solve_order=args.solve_order)
     depth = F.depth()  # reported only; outside the timed steps
     F.free()
     walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in runs) / K

@@ -83,6 +83,9 @@ typedef struct {
     int32_t schedule;          /* walk order: 0 = all rows by rank (longest walks
                                   first); 1 (default) = rows ranked below n/256 by
                                   rank, then the rest in node-id slabs, one per XCD */
+    int32_t solve_order;       /* order in which the triangular solves take rows:
+                                  0 = rank; 1 (default) = dependency level, then rank
+                                  (the build computes the levels once)              */
 } srw_options;
 
 void srw_default_options(srw_options* opt);
@@ -132,7 +135,7 @@ int srw_factor_info(const srw_factor* F, int64_t* n, int64_t* nnz_y, int64_t* wa
 /* Build phases timed when srw_options.profile = 1, in this order. */
 #define SRW_NUM_PHASES 8
 /* validate, rank, table, schedule (record offsets and the walk queue), walk (the
- * walk kernel alone), tally, factor, transpose */
+ * walk kernel alone), tally, factor, transpose (Y by columns and the solve order) */
 
 typedef struct {
     int64_t n, nnz_a, nnz_y;

@@ -686,6 +686,18 @@ __global__ void k_transpose_fill(int64_t nnz, const uint32_t* __restrict__ sorte
 
 __global__ void k_set_last(int64_t* ptr, int64_t n, int64_t v) { ptr[n] = v; }
 
+// (level, node) pairs listed in rank order, so a stable sort on the level keeps rank
+// order inside each level.
+__global__ void k_level_keys(int64_t n, const int32_t* __restrict__ by_rank,
+                             const int32_t* __restrict__ lev, uint32_t* key, uint32_t* val)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t v = by_rank[p];
+    key[p] = (uint32_t)lev[v];
+    val[p] = (uint32_t)v;
+}
+
 __global__ void k_sum_u64(int64_t n, const uint64_t* __restrict__ x, unsigned long long* out)
 {
     uint64_t s = 0;
@@ -1068,6 +1080,29 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipGetLastError());
         }
 
+        // ---- 8. order of rows for the triangular solves: (dependency level, rank)
+        if (opt.solve_order == 1 && n > 0) {
+            int32_t* lev = ALLOC(tmp, int32_t, n);
+            uint32_t* lkey = ALLOC(tmp, uint32_t, n);
+            uint32_t* lkey2 = ALLOC(tmp, uint32_t, n);
+            uint32_t* lval = ALLOC(tmp, uint32_t, n);
+            uint32_t* lval2 = ALLOC(tmp, uint32_t, n);
+            void* rt = ALLOC(tmp, char, radix_tmp_bytes(n));
+            F->solve_order = ALLOC(keep, int32_t, n);
+            if (!lev || !lkey || !lkey2 || !lval || !lval2 || !rt || !F->solve_order)
+                FAIL(SRW_E_NOMEM);
+            int32_t depth = 0;
+            status = dag_levels(F, lev, &depth, s);
+            if (status) goto done;
+            F->depth = depth;
+            k_level_keys<<<g, BLOCK, 0, s>>>(n, F->by_rank, lev, lkey, lval);
+            int bits = 8;
+            while (bits < 32 && ((int64_t)1 << bits) <= depth) bits += 8;
+            uint32_t* ko;
+            uint32_t* vo;
+            CHECK_HIP(radix_sort_u32(lkey, lval, lkey2, lval2, n, bits, rt, &ko, &vo, s));
+            CHECK_HIP(hipMemcpyAsync(F->solve_order, vo, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        }
         mark(8);
         CHECK_HIP(hipStreamSynchronize(s));
         if (prof) {

@@ -41,6 +41,7 @@ void srw_default_options(srw_options* opt)
     opt->refill_period = 0;
     opt->profile = 0;
     opt->schedule = 1;
+    opt->solve_order = 1;
 }
 
 int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
@@ -57,6 +58,7 @@ int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, u
         const int rp = opt->refill_period;
         if (rp != 0 && rp != 1 && rp != 2 && rp != 4 && rp != 8) return SRW_E_ARG;
         if (opt->schedule != 0 && opt->schedule != 1) return SRW_E_ARG;
+        if (opt->solve_order != 0 && opt->solve_order != 1) return SRW_E_ARG;
         if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && A->n > 0) return SRW_E_ARG;
     }
     if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;

@@ -21,6 +21,7 @@ struct srw_factor {
 
     int32_t* rank = nullptr;     // [n]
     int32_t* by_rank = nullptr;  // [n] node of each rank
+    int32_t* solve_order = nullptr;  // [n] rows by (dependency level, rank), or null
     int64_t* yptr = nullptr;     // [n+1]
     int32_t* ycol = nullptr;     // [nnz_y]
     void* yval = nullptr;        // [nnz_y] double or float
@@ -92,6 +93,8 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
 int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);
+// Dependency level of every row (lev, caller-allocated [n]) and the depth.
+int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s);
 void free_factor(srw_factor* F);
 
 }  // namespace srw

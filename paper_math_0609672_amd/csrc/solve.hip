@@ -148,9 +148,10 @@ __global__ __launch_bounds__(BLOCK) void k_copy(int64_t n, const double* __restr
 }
 
 // ----------------------------------------------------------- triangular solves
-// Sync-free substitution.  Rows are handed out as tickets in a topological order
-// (increasing rank for Y z = v, decreasing rank for Y^T w = r): a wave takes one
-// ticket at a time with a global atomic.  A row only waits on smaller tickets, and the
+// Sync-free substitution.  Rows are handed out as tickets in a topological order of
+// Y z = v -- increasing (level, rank) or increasing rank -- and in the reverse order for
+// Y^T w = r (a row's backward dependencies all have a higher level and rank): a wave
+// takes one ticket at a time with a global atomic.  A row only waits on smaller tickets, and the
 // smallest unfinished ticket always has all its dependencies done and is the current
 // row of its wave, so the solve always progresses.  The
 // solution vector starts filled with a signalling-NaN pattern that arithmetic never
@@ -331,11 +332,12 @@ hipError_t apply_syncfree(const srw_factor* F, const double* r, T* work, T* zlo,
     const int fg = (int)std::min<int64_t>(grid_for(n, BLOCK), 2048);
     const int pb = persistent_blocks();
     k_fill_sentinel<T><<<fg, BLOCK, 0, s>>>(n, work, tickets);
-    k_trsv_syncfree<T, false><<<pb, BLOCK, 0, s>>>(F->by_rank, n, F->ytptr, F->ytcol,
+    const int32_t* order = F->solve_order ? F->solve_order : F->by_rank;
+    k_trsv_syncfree<T, false><<<pb, BLOCK, 0, s>>>(order, n, F->ytptr, F->ytcol,
                                                    (const T*)F->ytval, (const T*)F->d, r, nullptr,
                                                    work, nullptr, tickets, err);
     k_fill_sentinel<T><<<fg, BLOCK, 0, s>>>(n, zlo, tickets + 1);
-    k_trsv_syncfree<T, true><<<pb, BLOCK, 0, s>>>(F->by_rank, n, F->yptr, F->ycol,
+    k_trsv_syncfree<T, true><<<pb, BLOCK, 0, s>>>(order, n, F->yptr, F->ycol,
                                                   (const T*)F->yval, (const T*)F->d, nullptr, work,
                                                   zlo, z, tickets + 1, err);
     return hipGetLastError();
@@ -381,15 +383,14 @@ int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s)
     return herr ? SRW_E_HIP : SRW_OK;
 }
 
-int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s)
+int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s)
 {
     const int64_t n = F->n;
     *depth_out = 0;
     if (n == 0) return SRW_OK;
     char* ws = nullptr;
-    SRW_HIP(hipMallocAsync((void**)&ws, n * sizeof(int32_t) + 64, s));
-    int32_t* lev = (int32_t*)ws;
-    unsigned long long* tickets = (unsigned long long*)(ws + ((n * sizeof(int32_t) + 15) & ~(size_t)15));
+    SRW_HIP(hipMallocAsync((void**)&ws, 64, s));
+    unsigned long long* tickets = (unsigned long long*)ws;
     int* depth = (int*)(tickets + 1);
     int* err = depth + 1;
     hipError_t e = hipMemsetAsync(depth, 0, 2 * sizeof(int), s);
@@ -408,6 +409,19 @@ int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s)
     if (host[1]) return SRW_E_HIP;
     *depth_out = host[0];
     return SRW_OK;
+}
+
+int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s)
+{
+    const int64_t n = F->n;
+    *depth_out = 0;
+    if (n == 0) return SRW_OK;
+    int32_t* lev = nullptr;
+    SRW_HIP(hipMallocAsync((void**)&lev, n * sizeof(int32_t), s));
+    const int st = dag_levels(F, lev, depth_out, s);
+    (void)hipFreeAsync(lev, s);
+    (void)hipStreamSynchronize(s);
+    return st;
 }
 
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,

@@ -36,7 +36,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int32), ("rank", ctypes.c_void_p), ("walks", ctypes.c_void_p),
                 ("factor_precision", ctypes.c_int32), ("max_steps", ctypes.c_uint64),
                 ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("solve_order", ctypes.c_int32)]
 
 
 NUM_PHASES = 8
@@ -219,7 +220,8 @@ def _check(st: int, what: str):
 
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
-                 profile: bool = False, schedule: int = 1, stream=None) -> Factor:
+                 profile: bool = False, schedule: int = 1, solve_order: int = 1,
+                 stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A."""
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
@@ -234,6 +236,7 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
     opt.refill_period = int(refill_period)
     opt.profile = 1 if profile else 0
     opt.schedule = int(schedule)
+    opt.solve_order = int(solve_order)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),

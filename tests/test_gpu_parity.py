@@ -165,6 +165,19 @@ def test_apply_matches_oracle(srw, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_solve_order_does_not_change_results(srw, name):
+    """Each row's sum has a fixed order, so the ticket order (rank or level) cannot
+    change the preconditioner's result."""
+    A, walks = CASES[name]
+    M = srw.Matrix.from_host(A, DEV)
+    F0 = srw.build_factor(M, walks, 1e-3, 6, solve_order=0)
+    F1 = srw.build_factor(M, walks, 1e-3, 6, solve_order=1)
+    r = torch.as_tensor(W.rhs(A.n, seed=8), device=DEV)
+    assert torch.equal(srw.apply(F0, r), srw.apply(F1, r))
+    assert F1.depth() == F0.depth()
+
+
+@pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("tol", [1e-8, 1e-10])
 def test_pcg_matches_oracle(srw, name, tol):
     A, walks = CASES[name]

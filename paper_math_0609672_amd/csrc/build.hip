@@ -188,15 +188,33 @@ __global__ void k_rank_given(int64_t n, const int32_t* __restrict__ given, int32
 }
 
 // ----------------------------------------------------------------------- table
-// Node descriptor: x = first off-diagonal entry of the row, y = degree | grounded
-// flag, z = rank, w = index (within the row) of the last higher-ranked neighbour.
+// Walk record of node v: 64-byte lines starting at line rline[v].  32-bit words:
+// [0] rank, [1] degree | grounded flag, [2] node id, [3] zero, then for off-diagonal
+// entry m (CSR order) a threshold floor(2^32 c_m / a_v) and the line of the
+// neighbour's record: words 4 + 2m, 5 + 2m for m < 6 in the first line, and eight
+// pairs per further line.  A node of degree <= 6 fits one line, so a walk step is one
+// dependent 64-byte load: the next node's record, whose header holds the rank for the
+// home test and the node id to record where the walk ends.
+// Start descriptor (read once per walk): x = record line, y = first off-diagonal
+// entry (index into the first-step thresholds), z = rank, w = degree | grounded; the
+// index of the last higher-ranked neighbour goes to lastm[v].
+constexpr int REC_WORDS = 16;
+
+__global__ void k_rec_lines(int64_t n, const int64_t* __restrict__ rowptr, int32_t* lines)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) lines[v] = (int32_t)((rowptr[v + 1] - rowptr[v] - 1 + 9) / 8);
+}
+
 __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
                         const int32_t* __restrict__ col, const double* __restrict__ val,
                         const int32_t* __restrict__ rank, const uint8_t* __restrict__ grounded,
                         int32_t walks_per_row, const int32_t* __restrict__ budget_in,
+                        const int64_t* __restrict__ rline, uint32_t* __restrict__ recs,
                         uint2* __restrict__ ent, uint32_t* __restrict__ mthr,
-                        uint4* __restrict__ desc, double* __restrict__ tau,
-                        int32_t* __restrict__ budget, int32_t* max_budget)
+                        uint4* __restrict__ desc, uint32_t* __restrict__ lastm,
+                        double* __restrict__ tau, int32_t* __restrict__ budget,
+                        int32_t* max_budget)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
@@ -209,6 +227,7 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
         else if (rank[j] > rv) motel = motel + (-val[p]);
     }
     const int64_t start = r0 - v;
+    uint32_t* rec = recs + (size_t)rline[v] * REC_WORDS;
     double c = 0.0, cm = 0.0;
     uint32_t m = 0, last_motel = 0;
     for (int64_t p = r0; p < r1; ++p) {
@@ -221,12 +240,21 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
             cm = cm + w;
             last_motel = m;
         }
-        ent[start + m] = make_uint2((uint32_t)j, threshold32(c, a));
+        const uint32_t thr = threshold32(c, a);
+        const uint32_t slot = m < 6 ? 4 + 2 * m : 16 + 2 * (m - 6);
+        rec[slot] = thr;
+        rec[slot + 1] = (uint32_t)rline[j];
+        if (ent) ent[start + m] = make_uint2((uint32_t)j, thr);
         mthr[start + m] = motel > 0.0 ? threshold32(cm, motel) : 0u;
         ++m;
     }
     const uint32_t flags = grounded[v] ? DESC_GROUNDED : 0u;
-    desc[v] = make_uint4((uint32_t)start, m | flags, (uint32_t)rv, last_motel);
+    rec[0] = (uint32_t)rv;
+    rec[1] = m | flags;
+    rec[2] = (uint32_t)v;
+    rec[3] = 0;
+    desc[v] = make_uint4((uint32_t)rline[v], (uint32_t)start, (uint32_t)rv, m | flags);
+    lastm[v] = last_motel;
     tau[v] = motel / a;
     int32_t b = 0;
     if (motel > 0.0) {
@@ -312,7 +340,8 @@ __global__ void k_seg_bounds(int64_t n, int64_t nlong, int64_t nslab_rows,
 // ----------------------------------------------------------------------- walks
 struct WalkArgs {
     const uint4* desc;
-    const uint2* ent;
+    const uint32_t* lastm;
+    const uint4* recs;         // walk records, 4 x 16 bytes per line
     const uint32_t* mthr;
     const uint2* chunks;       // chunk descriptors
     const int64_t* bounds;     // NSEG + 1 segment starts
@@ -346,7 +375,9 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
     // per-lane walk state
     bool active = false;
     uint32_t k = 0, w = 0, visits = 0, rank_k = 0, last_motel = 0;
-    uint32_t cs = 0, cd = 0;  // current node: first entry, degree | flags
+    uint32_t kline = 0, kstart = 0, kdeg = 0;  // start node: record line, entries, degree
+    uint32_t cline = 0;                        // current node's record line
+    uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;  // its first line
     uint64_t t = 0, rec = 0, degsum = 0;
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0, q7 = 0;
 
@@ -389,10 +420,11 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
                     visits = 1;
                     active = true;
                     const uint4 dk = a.desc[k];
-                    cs = dk.x;
-                    cd = dk.y;
+                    kline = dk.x;
+                    kstart = dk.y;
                     rank_k = dk.z;
-                    last_motel = dk.w;
+                    kdeg = dk.w & DESC_DEG_MASK;
+                    last_motel = a.lastm[k];
                     rec = (uint64_t)a.rec_off[k] + w;
                 }
                 const uint64_t taken = ballot(take);
@@ -415,42 +447,57 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
         const uint32_t u = q0;
         q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
 
-        const uint32_t deg = cd & DESC_DEG_MASK;
-        degsum += deg;
-        uint32_t nxt = 0;
+        uint32_t next_line = 0;
         bool to_ground = false;
         if (t == 0) {
             // first step: among higher-ranked neighbours of k (exact one-step part)
+            degsum += kdeg;
             uint32_t sel = last_motel;
-            for (uint32_t m = 0; m < deg; ++m)
-                if (u < a.mthr[cs + m]) {
+            for (uint32_t m = 0; m < kdeg; ++m)
+                if (u < a.mthr[kstart + m]) {
                     sel = m;
                     break;
                 }
-            nxt = a.ent[cs + sel].x;
+            const uint32_t* kr = (const uint32_t*)a.recs + (size_t)kline * REC_WORDS;
+            next_line = kr[sel < 6 ? 5 + 2 * sel : 17 + 2 * (sel - 6)];
         } else {
+            const uint32_t deg = r0.y & DESC_DEG_MASK;
+            degsum += deg;
+            // entries 0..5 sit in the first line (words 4..15), held in registers
+            const uint32_t e[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                                    r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
             bool found = false;
-            uint32_t lastx = 0;
-            for (uint32_t m0 = 0; m0 < deg; m0 += 8) {
-                uint2 e[8];
+            uint32_t lastn = 0;
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    e[j] = (m0 + j < deg) ? a.ent[cs + m0 + j] : make_uint2(0u, 0u);
+            for (int m = 0; m < 6; ++m) {
+                if ((uint32_t)m < deg) {
+                    if (!found && u < e[4 + 2 * m]) {
+                        found = true;
+                        next_line = e[5 + 2 * m];
+                    }
+                    lastn = e[5 + 2 * m];
+                }
+            }
+            // further lines of a node of degree > 6: 8 entries per line
+            for (uint32_t m0 = 6, l = 1; !found && m0 < deg; m0 += 8, ++l) {
+                const uint4* lp = a.recs + ((size_t)(cline + l) * 4);
+                const uint4 x0 = lp[0], x1 = lp[1], x2 = lp[2], x3 = lp[3];
+                const uint32_t f[16] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w,
+                                        x2.x, x2.y, x2.z, x2.w, x3.x, x3.y, x3.z, x3.w};
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (m0 + j < deg) {
-                        if (!found && u < e[j].y) {
+                for (int i = 0; i < 8; ++i) {
+                    if (m0 + i < deg) {
+                        if (!found && u < f[2 * i]) {
                             found = true;
-                            nxt = e[j].x;
+                            next_line = f[2 * i + 1];
                         }
-                        lastx = e[j].x;
+                        lastn = f[2 * i + 1];
                     }
                 }
-                if (found) break;
             }
             if (!found) {
-                if (cd & DESC_GROUNDED) to_ground = true;
-                else nxt = lastx;
+                if (r0.y & DESC_GROUNDED) to_ground = true;
+                else next_line = lastn;
             }
         }
         bool fin = false;
@@ -459,14 +506,19 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
             fin = true;
             endv = END_GROUND;
         } else {
-            const uint4 dn = a.desc[nxt];
-            if (t > 0 && dn.z < rank_k) {
+            const uint4* lp = a.recs + (size_t)next_line * 4;
+            const uint4 n0 = lp[0], n1 = lp[1], n2 = lp[2], n3 = lp[3];
+            const uint32_t rank_next = n0.x;
+            if (t > 0 && rank_next < rank_k) {
                 fin = true;
-                endv = nxt;
+                endv = n0.z;
             } else {
-                visits += (nxt == k);
-                cs = dn.x;
-                cd = dn.y;
+                visits += (rank_next == rank_k);
+                cline = next_line;
+                r0 = n0;
+                r1 = n1;
+                r2 = n2;
+                r3 = n3;
             }
         }
         ++t;
@@ -850,13 +902,30 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (herr) FAIL(map_err(herr));
 
         // ---- 3. transition table and walk budgets
-        uint2* ent = ALLOC(keep, uint2, nnz_off);
+        // walk records: line offsets from an exclusive scan of the lines per node
+        int32_t* nlines = ALLOC(tmp, int32_t, n);
+        int64_t* rline = ALLOC(tmp, int64_t, n);
+        int64_t* ltot = ALLOC(tmp, int64_t, 1);
+        void* lst = ALLOC(tmp, char, scan_tmp_bytes(n));
+        if (!nlines || !rline || !ltot || !lst) FAIL(SRW_E_NOMEM);
+        k_rec_lines<<<g, BLOCK, 0, s>>>(n, A->rowptr, nlines);
+        CHECK_HIP(exclusive_scan_i32_to_i64(nlines, rline, n, lst, s));
+        k_read_last<<<1, 1, 0, s>>>(rline, nlines, n, ltot);
+        CHECK_HIP(hipMemcpyAsync(&pinned[0], ltot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        const int64_t n_lines = pinned[0];
+        if (n_lines >= (int64_t)UINT32_MAX) FAIL(SRW_E_ARG);  // line indices are 32-bit
+        uint4* recs = ALLOC(tmp, uint4, n_lines * 4);
+        uint2* ent = opt.keep >= 1 ? ALLOC(keep, uint2, nnz_off) : nullptr;  // export only
         uint32_t* mthr = ALLOC(keep, uint32_t, nnz_off);
         uint4* desc = ALLOC(tmp, uint4, n);
+        uint32_t* lastm = ALLOC(tmp, uint32_t, n);
         double* tau = ALLOC(keep, double, n);
         int32_t* budget = ALLOC(keep, int32_t, n);
         int32_t* maxb = ALLOC(tmp, int32_t, 1);
-        if (!ent || !mthr || !desc || !tau || !budget || !maxb) FAIL(SRW_E_NOMEM);
+        if (!recs || (opt.keep >= 1 && !ent) || !mthr || !desc || !lastm || !tau || !budget ||
+            !maxb)
+            FAIL(SRW_E_NOMEM);
         F->ent = ent;
         F->mthr = mthr;
         F->tau = tau;
@@ -864,7 +933,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         mark(2);
         CHECK_HIP(hipMemsetAsync(maxb, 0, sizeof(int32_t), s));
         k_table<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, grounded, walks_per_row,
-                                    opt.walks, ent, mthr, desc, tau, budget, maxb);
+                                    opt.walks, rline, (uint32_t*)recs, ent, mthr, desc, lastm, tau,
+                                    budget, maxb);
         CHECK_HIP(hipGetLastError());
 
         // record offsets (node order) and the segmented chunk list
@@ -935,7 +1005,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (n_chunks > 0) {
             WalkArgs wa;
             wa.desc = desc;
-            wa.ent = ent;
+            wa.lastm = lastm;
+            wa.recs = recs;
             wa.mthr = mthr;
             wa.chunks = cdesc;
             wa.bounds = bounds;
@@ -951,16 +1022,20 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             int dev = 0, cus = 0;
             CHECK_HIP(hipGetDevice(&dev));
             CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            int64_t waves_needed = n_chunks;
-            int64_t blocks = (int64_t)cus * 8;
-            blocks = std::min<int64_t>(blocks, (waves_needed + BLOCK / 64 - 1) / (BLOCK / 64));
-            if (blocks < 1) blocks = 1;
+            // persistent grid: as many blocks as fit on the chip at once
+            void (*kern)(WalkArgs) = k_walk<1>;
             switch (opt.refill_period) {
-                case 2: k_walk<2><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
-                case 4: k_walk<4><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
-                case 8: k_walk<8><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
-                default: k_walk<1><<<(unsigned)blocks, BLOCK, 0, s>>>(wa); break;
+                case 2: kern = k_walk<2>; break;
+                case 4: kern = k_walk<4>; break;
+                case 8: kern = k_walk<8>; break;
+                default: break;
             }
+            int per_cu = 0;
+            CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
+            int64_t blocks = (int64_t)cus * std::max(1, per_cu);
+            blocks = std::min<int64_t>(blocks, (n_chunks + BLOCK / 64 - 1) / (BLOCK / 64));
+            if (blocks < 1) blocks = 1;
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, wa);
             CHECK_HIP(hipGetLastError());
         }
         mark(5);

@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--solve-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the steps, copy a buffer of this many MiB device to device "
+                         "three times (a plain copy kernel of known traffic, for scaling "
+                         "hardware byte counters)")
     return ap.parse_args()
 
 
@@ -87,6 +91,34 @@ def cpu_baseline(A, walks, seed, target_s):
         "walk_steps_per_s": round(steps / max(t_walk, 1e-9), 1),
         "sample_walk_s": round(t_walk, 3),
     }
+
+
+WALK_SOURCES = ("paper_math_0609672_amd/csrc/build.hip", "paper_math_0609672_amd/csrc/common.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_traffic.json")
+
+
+def walk_source_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in WALK_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per walk launch from the committed counter summary, if it was taken
+    on this workload with the walk kernel's current source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_sha256") != walk_source_sha() or t.get("workload") != workload
+            or t.get("precision") != precision):
+        return None
+    return t.get("traffic_bytes")
 
 
 def main():
@@ -200,6 +232,16 @@ def main():
             "avg_launch_ms": round(walk_ms, 3),
         },
     }
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB device-to-device")
+        del src, dst
+    out["roofline"]["traffic"] = measured_traffic(args.workload, args.precision)
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(A, walks, args.seed, args.cpu_seconds)

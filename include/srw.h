@@ -135,7 +135,8 @@ int srw_factor_info(const srw_factor* F, int64_t* n, int64_t* nnz_y, int64_t* wa
 /* Build phases timed when srw_options.profile = 1, in this order. */
 #define SRW_NUM_PHASES 8
 /* validate, rank, table, schedule (record offsets and the walk queue), walk (the
- * walk kernel alone), tally, factor, transpose (Y by columns and the solve order) */
+ * walk kernel alone), tally, factor, plan (Y by columns; both triangles relabelled
+ * by solve slot, with the dependency levels when the level order is asked for) */
 
 typedef struct {
     int64_t n, nnz_a, nnz_y;

@@ -10,7 +10,8 @@
 //   tally         one wave per row: LDS bitonic sort + run-length of end nodes
 //                 (H'_{k,i}), wave sums of stays (J'_k) -- no global atomics
 //   factor        eqs. newy, newz, d and the drop (Sections 3.3, 4, 5.2), FP64
-//   transpose     Y^T by a stable radix sort of the entries on (column, source rank)
+//   plan          Y^T by a stable radix sort of the entries on (column, source rank);
+//                 the rows of Y and Y^T relabelled by solve slot (rank or level order)
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -738,16 +739,67 @@ __global__ void k_transpose_fill(int64_t nnz, const uint32_t* __restrict__ sorte
 
 __global__ void k_set_last(int64_t* ptr, int64_t n, int64_t v) { ptr[n] = v; }
 
-// (level, node) pairs listed in rank order, so a stable sort on the level keeps rank
-// order inside each level.
-__global__ void k_level_keys(int64_t n, const int32_t* __restrict__ by_rank,
+// ------------------------------------------------------------------- solve plan
+__global__ void k_copy_i32(int64_t n, const int32_t* __restrict__ a, int32_t* __restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ void k_invert(int64_t n, const int32_t* __restrict__ slot_node, int32_t* node_slot)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) node_slot[slot_node[s]] = (int32_t)s;
+}
+
+__global__ void k_slot_lens(int64_t n, const int32_t* __restrict__ slot_node,
+                            const int64_t* __restrict__ ptr, int32_t* __restrict__ lens)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) {
+        const int32_t k = slot_node[s];
+        lens[s] = (int32_t)(ptr[k + 1] - ptr[k]);
+    }
+}
+
+// Row of node slot_node[s] copied to slot s, entries in their order, columns as slots;
+// one wave per slot.
+template <typename T>
+__global__ void k_permute_rows(int64_t n, const int32_t* __restrict__ slot_node,
+                               const int32_t* __restrict__ node_slot,
+                               const int64_t* __restrict__ sptr, const int32_t* __restrict__ scol,
+                               const T* __restrict__ sval, const int64_t* __restrict__ dptr,
+                               int32_t* __restrict__ dcol, T* __restrict__ dval)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); s < n; s += nw) {
+        const int32_t k = slot_node[s];
+        const int64_t a = sptr[k], len = sptr[k + 1] - a, o = dptr[s];
+        for (int64_t j = lane; j < len; j += 64) {
+            dcol[o + j] = node_slot[scol[a + j]];
+            dval[o + j] = sval[a + j];
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_gather_slots(int64_t n, const int32_t* __restrict__ slot_node,
+                               const T* __restrict__ src, T* __restrict__ dst)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = src[slot_node[s]];
+}
+
+// (level, node) pairs of a rank-ordered plan, listed by slot, so a stable sort on the
+// level keeps rank order inside each level.
+__global__ void k_level_keys(int64_t n, const int32_t* __restrict__ slot_node,
                              const int32_t* __restrict__ lev, uint32_t* key, uint32_t* val)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t v = by_rank[p];
-    key[p] = (uint32_t)lev[v];
-    val[p] = (uint32_t)v;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    key[s] = (uint32_t)lev[s];
+    val[s] = (uint32_t)slot_node[s];
 }
 
 __global__ void k_sum_u64(int64_t n, const uint64_t* __restrict__ x, unsigned long long* out)
@@ -840,9 +892,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         F->rank = ALLOC(keep, int32_t, n);
         F->by_rank = ALLOC(keep, int32_t, n);
         F->yptr = ALLOC(keep, int64_t, n + 1);
-        F->ytptr = ALLOC(keep, int64_t, n + 1);
         if (!err || !changed || !grounded || !label || !comp || !F->rank || !F->by_rank ||
-            !F->yptr || !F->ytptr)
+            !F->yptr)
             FAIL(SRW_E_NOMEM);
         F->grounded = grounded;
 
@@ -1110,9 +1161,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         F->ycol = ALLOC(keep, int32_t, nnz_y);
         F->yval = ALLOC(keep, char, nnz_y * vbytes);
         F->d = ALLOC(keep, char, n * vbytes);
-        F->ytcol = ALLOC(keep, int32_t, nnz_y);
-        F->ytval = ALLOC(keep, char, nnz_y * vbytes);
-        if (!F->ycol || !F->yval || !F->d || !F->ytcol || !F->ytval) FAIL(SRW_E_NOMEM);
+        if (!F->ycol || !F->yval || !F->d) FAIL(SRW_E_NOMEM);
         if (fp32)
             k_factor<float, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
                                                      budget, tJ, rec_off, hlen, h_end, h_cnt,
@@ -1125,8 +1174,12 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
                                                       (double*)F->yval, (double*)F->d);
         CHECK_HIP(hipGetLastError());
 
-        // ---- 7. Y^T by a stable sort of the entries on their column
+        // ---- 7. Y^T by a stable sort of the entries on their column, then the plan
         mark(7);
+        int64_t* ytptr = ALLOC(tmp, int64_t, n + 1);
+        int32_t* ytcol = ALLOC(tmp, int32_t, nnz_y);
+        void* ytval = ALLOC(tmp, char, nnz_y * vbytes);
+        if (!ytptr || !ytcol || !ytval) FAIL(SRW_E_NOMEM);
         {
             uint32_t* rowid = ALLOC(tmp, uint32_t, nnz_y);
             uint32_t* idx = ALLOC(tmp, uint32_t, nnz_y);
@@ -1144,18 +1197,57 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, 2 * rbits, rt, &ko, &vo, s));
             CHECK_HIP(hipMemsetAsync(ccount, 0, n * sizeof(int32_t), s));
             k_col_count<<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(nnz_y, F->ycol, ccount);
-            CHECK_HIP(exclusive_scan_i32_to_i64(ccount, F->ytptr, n, st, s));
-            k_set_last<<<1, 1, 0, s>>>(F->ytptr, n, nnz_y);
+            CHECK_HIP(exclusive_scan_i32_to_i64(ccount, ytptr, n, st, s));
+            k_set_last<<<1, 1, 0, s>>>(ytptr, n, nnz_y);
             if (fp32)
                 k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, vo, rowid, (const float*)F->yval, F->ytcol, (float*)F->ytval);
+                    nnz_y, vo, rowid, (const float*)F->yval, ytcol, (float*)ytval);
             else
                 k_transpose_fill<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, vo, rowid, (const double*)F->yval, F->ytcol, (double*)F->ytval);
+                    nnz_y, vo, rowid, (const double*)F->yval, ytcol, (double*)ytval);
             CHECK_HIP(hipGetLastError());
         }
 
-        // ---- 8. order of rows for the triangular solves: (dependency level, rank)
+        // solve plan: rows of Y and Y^T by slot, starting from the rank order
+        F->slot_node = ALLOC(keep, int32_t, n);
+        F->node_slot = ALLOC(keep, int32_t, n);
+        F->fptr = ALLOC(keep, int64_t, n + 1);
+        F->fcol = ALLOC(keep, int32_t, nnz_y);
+        F->fval = ALLOC(keep, char, nnz_y * vbytes);
+        F->bptr = ALLOC(keep, int64_t, n + 1);
+        F->bcol = ALLOC(keep, int32_t, nnz_y);
+        F->bval = ALLOC(keep, char, nnz_y * vbytes);
+        F->dslot = ALLOC(keep, char, n * vbytes);
+        int32_t* lens = ALLOC(tmp, int32_t, n);
+        if (!F->slot_node || !F->node_slot || !F->fptr || !F->fcol || !F->fval || !F->bptr ||
+            !F->bcol || !F->bval || !F->dslot || !lens)
+            FAIL(SRW_E_NOMEM);
+        auto relabel = [&](const int64_t* sptr, const int32_t* scol, const void* sval,
+                           int64_t* dptr, int32_t* dcol, void* dval) -> hipError_t {
+            k_slot_lens<<<g, BLOCK, 0, s>>>(n, F->slot_node, sptr, lens);
+            hipError_t e = exclusive_scan_i32_to_i64(lens, dptr, n, st, s);
+            if (e != hipSuccess) return e;
+            k_set_last<<<1, 1, 0, s>>>(dptr, n, nnz_y);
+            const unsigned pg = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
+            if (fp32)
+                k_permute_rows<float><<<pg, BLOCK, 0, s>>>(n, F->slot_node, F->node_slot, sptr,
+                                                           scol, (const float*)sval, dptr, dcol,
+                                                           (float*)dval);
+            else
+                k_permute_rows<double><<<pg, BLOCK, 0, s>>>(n, F->slot_node, F->node_slot, sptr,
+                                                            scol, (const double*)sval, dptr, dcol,
+                                                            (double*)dval);
+            return hipGetLastError();
+        };
+        if (n > 0) {
+            k_copy_i32<<<g, BLOCK, 0, s>>>(n, F->by_rank, F->slot_node);
+            k_copy_i32<<<g, BLOCK, 0, s>>>(n, F->rank, F->node_slot);
+            CHECK_HIP(relabel(F->yptr, F->ycol, F->yval, F->fptr, F->fcol, F->fval));
+        } else {
+            CHECK_HIP(hipMemsetAsync(F->fptr, 0, sizeof(int64_t), s));
+            CHECK_HIP(hipMemsetAsync(F->bptr, 0, sizeof(int64_t), s));
+        }
+        // level order: slots by (dependency level, rank)
         if (opt.solve_order == 1 && n > 0) {
             int32_t* lev = ALLOC(tmp, int32_t, n);
             uint32_t* lkey = ALLOC(tmp, uint32_t, n);
@@ -1163,20 +1255,30 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             uint32_t* lval = ALLOC(tmp, uint32_t, n);
             uint32_t* lval2 = ALLOC(tmp, uint32_t, n);
             void* rt = ALLOC(tmp, char, radix_tmp_bytes(n));
-            F->solve_order = ALLOC(keep, int32_t, n);
-            if (!lev || !lkey || !lkey2 || !lval || !lval2 || !rt || !F->solve_order)
-                FAIL(SRW_E_NOMEM);
+            if (!lev || !lkey || !lkey2 || !lval || !lval2 || !rt) FAIL(SRW_E_NOMEM);
             int32_t depth = 0;
             status = dag_levels(F, lev, &depth, s);
             if (status) goto done;
             F->depth = depth;
-            k_level_keys<<<g, BLOCK, 0, s>>>(n, F->by_rank, lev, lkey, lval);
+            k_level_keys<<<g, BLOCK, 0, s>>>(n, F->slot_node, lev, lkey, lval);
             int bits = 8;
             while (bits < 32 && ((int64_t)1 << bits) <= depth) bits += 8;
             uint32_t* ko;
             uint32_t* vo;
             CHECK_HIP(radix_sort_u32(lkey, lval, lkey2, lval2, n, bits, rt, &ko, &vo, s));
-            CHECK_HIP(hipMemcpyAsync(F->solve_order, vo, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            k_copy_i32<<<g, BLOCK, 0, s>>>(n, (const int32_t*)vo, F->slot_node);
+            k_invert<<<g, BLOCK, 0, s>>>(n, F->slot_node, F->node_slot);
+            CHECK_HIP(relabel(F->yptr, F->ycol, F->yval, F->fptr, F->fcol, F->fval));
+        }
+        if (n > 0) {
+            CHECK_HIP(relabel(ytptr, ytcol, ytval, F->bptr, F->bcol, F->bval));
+            if (fp32)
+                k_gather_slots<float><<<g, BLOCK, 0, s>>>(n, F->slot_node, (const float*)F->d,
+                                                          (float*)F->dslot);
+            else
+                k_gather_slots<double><<<g, BLOCK, 0, s>>>(n, F->slot_node, (const double*)F->d,
+                                                           (double*)F->dslot);
+            CHECK_HIP(hipGetLastError());
         }
         mark(8);
         CHECK_HIP(hipStreamSynchronize(s));

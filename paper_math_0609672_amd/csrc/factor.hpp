@@ -6,8 +6,9 @@
 #include "common.hpp"
 
 // Library-owned preconditioner.  Node labels are the caller's row indices; Y is
-// stored by rows (CSR, ascending node id per row, strictly lower in rank) and by
-// columns (Yt = CSR of Y^T) for the two triangular solves.
+// stored by rows (CSR, ascending node id per row, strictly lower in rank).  The
+// triangular solves run over a solve plan: the rows of Y and of Y^T listed by slot --
+// the position of a row in the order the solves take -- with columns given as slots.
 struct srw_factor {
     int64_t n = 0;
     int64_t nnz_a = 0;
@@ -21,14 +22,21 @@ struct srw_factor {
 
     int32_t* rank = nullptr;     // [n]
     int32_t* by_rank = nullptr;  // [n] node of each rank
-    int32_t* solve_order = nullptr;  // [n] rows by (dependency level, rank), or null
     int64_t* yptr = nullptr;     // [n+1]
     int32_t* ycol = nullptr;     // [nnz_y]
     void* yval = nullptr;        // [nnz_y] double or float
-    int64_t* ytptr = nullptr;    // [n+1]
-    int32_t* ytcol = nullptr;    // [nnz_y]
-    void* ytval = nullptr;       // [nnz_y]
     void* d = nullptr;           // [n] double or float
+
+    // solve plan: slots in increasing (level, rank) or increasing rank
+    int32_t* slot_node = nullptr;  // [n] node of each slot
+    int32_t* node_slot = nullptr;  // [n]
+    int64_t* fptr = nullptr;       // [n+1] rows of Y by slot
+    int32_t* fcol = nullptr;       // [nnz_y] slots, row order of Y kept
+    void* fval = nullptr;          // [nnz_y]
+    int64_t* bptr = nullptr;       // [n+1] rows of Y^T by slot
+    int32_t* bcol = nullptr;       // [nnz_y] slots, source rank descending in a row
+    void* bval = nullptr;          // [nnz_y]
+    void* dslot = nullptr;         // [n] D by slot
 
     // longest dependency chain of the triangular solves, -1 until srw_factor_depth
     int32_t depth = -1;
@@ -93,7 +101,7 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
 int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);
-// Dependency level of every row (lev, caller-allocated [n]) and the depth.
+// Dependency level of every slot of the plan (lev, caller-allocated [n]) and the depth.
 int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s);
 void free_factor(srw_factor* F);
 

@@ -1,5 +1,6 @@
 // Solve phase of the hybrid solver (Algorithm 1, "solve"): PCG with the
-// preconditioner (Y^T D Y)^{-1} applied by two sync-free triangular solves.
+// preconditioner (Y^T D Y)^{-1} applied by two sync-free triangular solves over the
+// slot-ordered solve plan.
 //
 // Reductions are deterministic: every dot product is summed per block of a fixed
 // grid into partials and the partials are added by one block in a fixed order.
@@ -148,212 +149,272 @@ __global__ __launch_bounds__(BLOCK) void k_copy(int64_t n, const double* __restr
 }
 
 // ----------------------------------------------------------- triangular solves
-// Sync-free substitution.  Rows are handed out as tickets in a topological order of
-// Y z = v -- increasing (level, rank) or increasing rank -- and in the reverse order for
-// Y^T w = r (a row's backward dependencies all have a higher level and rank): a wave
-// takes one ticket at a time with a global atomic.  A row only waits on smaller tickets, and the
-// smallest unfinished ticket always has all its dependencies done and is the current
-// row of its wave, so the solve always progresses.  The
-// solution vector starts filled with a signalling-NaN pattern that arithmetic never
-// produces; a row's value is published with one device-scope store, and a consumer
-// spins (device-scope loads) until the pattern is gone -- the value is its own ready
-// flag, no fence is needed.  A wave-wide butterfly adds the lane partial sums, so the
-// result does not depend on timing.
-//   backward  (Y^T w = r):   w_k = r_k - sum_q Yt_kq w_q
-//   forward   (Y z = v):     z_k = w_k / D_k - sum_q Y_kq z_q
+// Both substitutions run over the solve plan: the rows of Y (and of Y^T) stored by
+// slot -- the position of the row in a topological order of Y z = v, increasing
+// (level, rank) or increasing rank -- with every column replaced by its slot, so a
+// row only depends on smaller slots going forward and on larger slots going backward.
+//   backward  (Y^T w = r):   w_s = r_node(s) - sum_q Yt_sq w_q     (slots descending)
+//   forward   (Y z = v):     z_s = w_s / D_s - sum_q Y_sq z_q       (slots ascending)
+// A cooperative launch keeps every wave of the grid resident, and wave i takes the
+// rows i, i + W, i + 2W, ... of the order (W waves): no counter is shared.  The wave
+// that holds the first unfinished row has finished all its earlier rows and that
+// row's dependencies are all done, so the solve always progresses.  The solution
+// starts filled with a signalling-NaN pattern that arithmetic never produces; a
+// row's value is published with one device-scope store and is its own ready flag.
+// A waiting wave polls one address only -- that of its missing dependency which the
+// order solves last -- and reloads its other missing values once that one is there.
+// The lane partial sums are added by a wave-wide butterfly, so the result does not
+// depend on timing.
 template <typename T>
 struct Bits;
 template <>
 struct Bits<double> {
     using U = unsigned long long;
     static constexpr U sentinel = 0x7FF4DEADBEEF5A5Aull;
+    static __device__ U nan_bits() { return 0x7FF8000000000000ull; }  // quiet NaN
 };
 template <>
 struct Bits<float> {
     using U = unsigned int;
     static constexpr U sentinel = 0x7FA5A5A5u;
+    static __device__ U nan_bits() { return 0x7FC00000u; }  // quiet NaN
+};
+template <>
+struct Bits<int32_t> {
+    using U = unsigned int;
+    static constexpr U sentinel = 0xFFFFFFFFu;  // level -1: not yet known
+    static __device__ U nan_bits() { return 0u; }
 };
 
 // A wait that outlives this many polls (about a second) marks the solve failed and
 // proceeds with a NaN; the caller then reports the failure.
 constexpr uint32_t SPIN_LIMIT = 1u << 20;
 
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_fill_sentinel(int64_t n, T* x, unsigned long long* tickets)
-{
-    using U = typename Bits<T>::U;
-    const int64_t i0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i0 == 0) tickets[0] = 0;
-    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * BLOCK) ((U*)x)[i] = Bits<T>::sentinel;
-}
-
-constexpr unsigned long long TICKETS_PER_WAVE = 1;
-
-// First of the wave's next TICKETS_PER_WAVE tickets.  Every lane executes the atomic
-// (lane 0 adds the batch, the others 0), so no lane-divergent branch precedes the
-// scalar broadcast.
-__device__ __forceinline__ unsigned long long wave_batch(unsigned long long* tickets)
-{
-    const bool l0 = (threadIdx.x & 63) == 0;
-    return lane0_u64(atomicAdd(tickets, l0 ? TICKETS_PER_WAVE : 0ull));
-}
-
 #ifndef SRW_POLL_SLEEP
 #define SRW_POLL_SLEEP 2  // s_sleep units (64 clocks) between polls of a missing value
 #endif
 
-// acc += sum over the entries [q0, q1) of val[q] * sol[col[q]], waiting for every
-// sol value to be published.  Each 64-entry chunk issues all its loads at once; the
-// wave then re-polls only the lanes still holding the sentinel, as one wave-uniform
-// loop (no lane spins on its own), and gives up after SPIN_LIMIT polls.
 template <typename T>
-__device__ __forceinline__ T gather_published(const int64_t q0, const int64_t q1,
-                                              const int32_t* __restrict__ col,
-                                              const T* __restrict__ val, const T* sol, int* err)
+__global__ __launch_bounds__(BLOCK) void k_fill_sentinel(int64_t n, T* x)
+{
+    using U = typename Bits<T>::U;
+    const int64_t i0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * BLOCK) ((U*)x)[i] = Bits<T>::sentinel;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename U>
+__device__ __forceinline__ U load_published(const U* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until no valid lane holds the sentinel in `bits` (each lane's value of slot
+// c).  LATE_HIGH: the order solves higher slots later (forward), else lower slots.
+// A wait that gives up raises *err and leaves a NaN in the missing lanes.
+template <typename T, bool LATE_HIGH>
+__device__ __forceinline__ void wait_published(typename Bits<T>::U& bits, const int32_t c,
+                                               const bool valid, const T* sol, int* err)
 {
     using U = typename Bits<T>::U;
     const int lane = threadIdx.x & 63;
-    T acc = T(0);
-    for (int64_t qb = q0; qb < q1; qb += 64) {
-        const int64_t q = qb + lane;
-        const bool valid = q < q1;
-        const int32_t c = valid ? col[q] : 0;
-        const T v = valid ? val[q] : T(0);
-        const U* p = (const U*)sol + c;
-        U bits = valid ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : U(0);
-        uint32_t spins = 0;
-        while (ballot(bits == Bits<T>::sentinel) != 0) {
-            if (++spins > SPIN_LIMIT) {
-                if (lane == 0) atomicOr(err, 1);
-                if (bits == Bits<T>::sentinel) bits = __builtin_bit_cast(U, (T)NAN);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(SRW_POLL_SLEEP);
-            if (bits == Bits<T>::sentinel)
-                bits = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t miss = ballot(valid && bits == Bits<T>::sentinel);
+    uint32_t spins = 0;
+    while (miss != 0) {
+        if (++spins > SPIN_LIMIT) {
+            if (lane == 0) atomicOr(err, 1);
+            if ((miss >> lane) & 1ull) bits = Bits<T>::nan_bits();
+            break;
         }
-        acc += v * __builtin_bit_cast(T, bits);
+        const bool mine = (miss >> lane) & 1ull;
+        const int key = wave_max_i32(mine ? (LATE_HIGH ? c : -c) : INT_MIN);
+        const int32_t lead = LATE_HIGH ? key : -key;
+        const U lb = load_published((const U*)sol + lead);  // one address for the wave
+        if (lb == Bits<T>::sentinel) {
+            __builtin_amdgcn_s_sleep(SRW_POLL_SLEEP);
+            continue;
+        }
+        if (mine) bits = load_published((const U*)sol + c);
+        miss = ballot(valid && bits == Bits<T>::sentinel);
     }
-    return acc;
 }
 
 template <typename T, bool FWD>
-__global__ __launch_bounds__(BLOCK) void k_trsv_syncfree(
-    const int32_t* __restrict__ by_rank, int64_t n, const int64_t* __restrict__ ptr,
-    const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ dvec,
-    const double* __restrict__ rhs, const T* __restrict__ w, T* sol, double* __restrict__ sol64,
-    unsigned long long* tickets, int* err)
+__global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __restrict__ ptr,
+                                                const int32_t* __restrict__ col,
+                                                const T* __restrict__ val,
+                                                const T* __restrict__ dslot,
+                                                const int32_t* __restrict__ slot_node,
+                                                const double* __restrict__ rhs,
+                                                const T* __restrict__ w, T* sol,
+                                                double* __restrict__ out, int* err)
 {
     using U = typename Bits<T>::U;
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        const unsigned long long t = wave_batch(tickets);
-        if (t >= (unsigned long long)n) break;
-        const int32_t k = by_rank[FWD ? (int64_t)t : n - 1 - (int64_t)t];
-        T acc = gather_published<T>(ptr[k], ptr[k + 1], col, val, sol, err);
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
+    const int64_t wid =
+        (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= n) return;  // whole wave
+    // the wave's next row, loaded one row ahead: bounds and first 64 entries
+    int64_t s = FWD ? wid : n - 1 - wid;
+    int64_t q0 = ptr[s], q1 = ptr[s + 1];
+    int32_t c = 0;
+    T v = T(0);
+    if (q0 + lane < q1) {
+        c = col[q0 + lane];
+        v = val[q0 + lane];
+    }
+    for (int64_t i = wid; i < n; i += nw) {
+        const bool valid = q0 + lane < q1;
+        U bits = valid ? load_published((const U*)sol + c) : U(0);
+        const int32_t node = slot_node[s];
+        const T base = FWD ? w[s] / dslot[s] : (T)rhs[node];
+        const int64_t i2 = i + nw;
+        int64_t s2 = 0, p0 = 0, p1 = 0;
+        int32_t c2 = 0;
+        T v2 = T(0);
+        if (i2 < n) {
+            s2 = FWD ? i2 : n - 1 - i2;
+            p0 = ptr[s2];
+            p1 = ptr[s2 + 1];
+            if (p0 + lane < p1) {
+                c2 = col[p0 + lane];
+                v2 = val[p0 + lane];
+            }
+        }
+        wait_published<T, FWD>(bits, c, valid, sol, err);
+        T acc = v * __builtin_bit_cast(T, bits);
+        for (int64_t qb = q0 + 64; qb < q1; qb += 64) {  // rows longer than 64 entries
+            const int64_t q = qb + lane;
+            const bool ok = q < q1;
+            const int32_t cc = ok ? col[q] : 0;
+            const T vv = ok ? val[q] : T(0);
+            U bb = ok ? load_published((const U*)sol + cc) : U(0);
+            wait_published<T, FWD>(bb, cc, ok, sol, err);
+            acc += vv * __builtin_bit_cast(T, bb);
+        }
         acc = wave_sum(acc);
         if (lane == 0) {
-            const T v = FWD ? w[k] / dvec[k] - acc : (T)rhs[k] - acc;
-            __hip_atomic_store((U*)sol + k, __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+            const T x = base - acc;
+            __hip_atomic_store((U*)sol + s, __builtin_bit_cast(U, x), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            if (sol64) sol64[k] = (double)v;
+            if (out) out[node] = (double)x;
         }
+        s = s2;
+        q0 = p0;
+        q1 = p1;
+        c = c2;
+        v = v2;
     }
 }
 
-// Longest dependency chain of Y (the same for Y^T): lev_k = 1 + max over the row's
-// entries, 0 for an empty row; rows in increasing rank, same publication scheme.
-__global__ __launch_bounds__(BLOCK) void k_depth(const int32_t* __restrict__ by_rank, int64_t n,
-                                                 const int64_t* __restrict__ ptr,
-                                                 const int32_t* __restrict__ col, int32_t* lev,
-                                                 unsigned long long* tickets, int* depth, int* err)
+// Dependency level of every slot over the forward plan: lev_s = 1 + the largest
+// level among the row's columns, 0 for an empty row; the same scheme as k_trsv.
+// Each wave keeps the largest level it met; one atomic per wave gives the depth.
+__global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, int32_t* lev,
+                                                  int* depth, int* err)
 {
+    using U = Bits<int32_t>::U;
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        const unsigned long long base = wave_batch(tickets);
-        if (base >= (unsigned long long)n) break;
-        for (unsigned long long j = 0; j < TICKETS_PER_WAVE; ++j) {
-        const unsigned long long t = base + j;
-        if (t >= (unsigned long long)n) break;
-        const int32_t k = by_rank[t];
-        int32_t m = -1;
-        for (int64_t q = ptr[k] + lane; q < ptr[k + 1]; q += 64) {
-            const int32_t* p = lev + col[q];
-            int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t spins = 0;
-            while (v < 0) {
-                if (++spins > SPIN_LIMIT) {
-                    atomicOr(err, 1);
-                    v = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            m = max(m, v);
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
+    const int64_t wid =
+        (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int wmax = 0;
+    for (int64_t s = wid; s < n; s += nw) {
+        int m = -1;
+        for (int64_t qb = ptr[s]; qb < ptr[s + 1]; qb += 64) {
+            const int64_t q = qb + lane;
+            const bool ok = q < ptr[s + 1];
+            const int32_t c = ok ? col[q] : 0;
+            U bits = ok ? load_published((const U*)lev + c) : U(0);
+            wait_published<int32_t, true>(bits, c, ok, lev, err);
+            if (ok) m = max(m, (int)bits);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-        if (lane == 0) {
-            __hip_atomic_store(lev + k, m + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicMax(depth, m + 2);
-        }
-        }  // tickets of this wave
+        m = wave_max_i32(m) + 1;
+        wmax = max(wmax, m + 1);
+        if (lane == 0)
+            __hip_atomic_store((U*)lev + s, (U)m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (lane == 0 && wid < n) atomicMax(depth, wmax);
 }
 
-__global__ void k_fill_i32(int64_t n, int32_t* x, int32_t v, unsigned long long* tickets)
+// Grid of a cooperative launch: every block resident at once (occupancy x CUs),
+// capped at the blocks the work can use.
+template <typename K>
+hipError_t coop_launch(K kernel, int64_t rows, void** args, hipStream_t s)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i0 == 0) tickets[0] = 0;
-    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (int64_t)cus * std::max(1, per_cu);
+    blocks = std::min<int64_t>(blocks, (rows + BLOCK / 64 - 1) / (BLOCK / 64));
+    if (blocks < 1) blocks = 1;
+    return hipLaunchCooperativeKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK),
+                                      args, 0, s);
 }
 
-int persistent_blocks()
-{
-    static int blocks = 0;
-    if (!blocks) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 256;
-        blocks = cus * 8;
-    }
-    return blocks;
-}
+int fill_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(grid_for(n, BLOCK), 1), 2048); }
 
-// w and z scratch: work (n values of T), ticket counters and an error flag.
-// zlo receives z in the factor's precision; z (if not null) a double copy.
+// work, sol: n values of T each; z (node order) receives the result as doubles.
 template <typename T>
-hipError_t apply_syncfree(const srw_factor* F, const double* r, T* work, T* zlo, double* z,
-                          unsigned long long* tickets, int* err, hipStream_t s)
+hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, double* z, int* err,
+                      hipStream_t s)
 {
-    const int64_t n = F->n;
-    const int fg = (int)std::min<int64_t>(grid_for(n, BLOCK), 2048);
-    const int pb = persistent_blocks();
-    k_fill_sentinel<T><<<fg, BLOCK, 0, s>>>(n, work, tickets);
-    const int32_t* order = F->solve_order ? F->solve_order : F->by_rank;
-    k_trsv_syncfree<T, false><<<pb, BLOCK, 0, s>>>(order, n, F->ytptr, F->ytcol,
-                                                   (const T*)F->ytval, (const T*)F->d, r, nullptr,
-                                                   work, nullptr, tickets, err);
-    k_fill_sentinel<T><<<fg, BLOCK, 0, s>>>(n, zlo, tickets + 1);
-    k_trsv_syncfree<T, true><<<pb, BLOCK, 0, s>>>(order, n, F->yptr, F->ycol,
-                                                  (const T*)F->yval, (const T*)F->d, nullptr, work,
-                                                  zlo, z, tickets + 1, err);
-    return hipGetLastError();
+    int64_t n = F->n;
+    k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, work);
+    k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, sol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        const int64_t* ptr = F->bptr;
+        const int32_t* col = F->bcol;
+        const T* val = (const T*)F->bval;
+        const T* dslot = nullptr;
+        const int32_t* slot_node = F->slot_node;
+        const double* rhs = r;
+        const T* w = nullptr;
+        T* out_sol = work;
+        double* out = nullptr;
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        e = coop_launch(k_trsv<T, false>, n, args, s);
+        if (e != hipSuccess) return e;
+    }
+    {
+        const int64_t* ptr = F->fptr;
+        const int32_t* col = F->fcol;
+        const T* val = (const T*)F->fval;
+        const T* dslot = (const T*)F->dslot;
+        const int32_t* slot_node = F->slot_node;
+        const double* rhs = nullptr;
+        const T* w = work;
+        T* out_sol = sol;
+        double* out = z;
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        e = coop_launch(k_trsv<T, true>, n, args, s);
+    }
+    return e;
 }
 
-// work: 2 n doubles of scratch; tickets: 2 counters; err: one int (0 on entry).
-hipError_t apply_any(const srw_factor* F, const double* r, void* work, double* z,
-                     unsigned long long* tickets, int* err, hipStream_t s)
+// work: 2 n doubles of scratch; err: one int (0 on entry).
+hipError_t apply_any(const srw_factor* F, const double* r, void* work, double* z, int* err,
+                     hipStream_t s)
 {
     if (F->n == 0) return hipSuccess;
     if (F->precision == SRW_FP32) {
         float* w = (float*)work;
-        return apply_syncfree<float>(F, r, w, w + F->n, z, tickets, err, s);
+        return apply_plan<float>(F, r, w, w + F->n, z, err, s);
     }
-    // FP64: the forward solve publishes straight into z
-    return apply_syncfree<double>(F, r, (double*)work, z, nullptr, tickets, err, s);
+    double* w = (double*)work;
+    return apply_plan<double>(F, r, w, w + F->n, z, err, s);
 }
 
 int red_grid(int64_t n)
@@ -370,10 +431,9 @@ int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s)
     char* ws = nullptr;
     const size_t vec = (size_t)std::max<int64_t>(n, 1);
     SRW_HIP(hipMallocAsync((void**)&ws, 2 * vec * sizeof(double) + 64, s));
-    unsigned long long* tickets = (unsigned long long*)(ws + 2 * vec * sizeof(double));
-    int* err = (int*)(tickets + 2);
+    int* err = (int*)(ws + 2 * vec * sizeof(double));
     hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
-    if (e == hipSuccess) e = apply_any(F, r, ws, z, tickets, err, s);
+    if (e == hipSuccess) e = apply_any(F, r, ws, z, err, s);
     int herr = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -385,20 +445,23 @@ int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s)
 
 int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s)
 {
-    const int64_t n = F->n;
+    int64_t n = F->n;
     *depth_out = 0;
     if (n == 0) return SRW_OK;
     char* ws = nullptr;
     SRW_HIP(hipMallocAsync((void**)&ws, 64, s));
-    unsigned long long* tickets = (unsigned long long*)ws;
-    int* depth = (int*)(tickets + 1);
+    int* depth = (int*)ws;
     int* err = depth + 1;
     hipError_t e = hipMemsetAsync(depth, 0, 2 * sizeof(int), s);
     if (e == hipSuccess) {
-        k_fill_i32<<<(int)std::min<int64_t>(grid_for(n, BLOCK), 2048), BLOCK, 0, s>>>(n, lev, -1, tickets);
-        k_depth<<<persistent_blocks(), BLOCK, 0, s>>>(F->by_rank, n, F->yptr, F->ycol, lev, tickets,
-                                                      depth, err);
+        k_fill_sentinel<int32_t><<<fill_grid(n), BLOCK, 0, s>>>(n, lev);
         e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        const int64_t* ptr = F->fptr;
+        const int32_t* col = F->fcol;
+        void* args[] = {&n, &ptr, &col, &lev, &depth, &err};
+        e = coop_launch(k_levels, n, args, s);
     }
     int host[2] = {0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(host, depth, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -437,8 +500,7 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
     double *r = ws, *z = ws + vec, *p = ws + 2 * vec, *q = ws + 3 * vec, *work = ws + 4 * vec;
     double* partials = ws + 6 * vec;
     double* sc = partials + RED_GRID;
-    unsigned long long* tickets = (unsigned long long*)(sc + S_COUNT);
-    int* err = (int*)(tickets + 2);
+    int* err = (int*)(sc + S_COUNT);
     hipError_t herr = hipHostMalloc((void**)&host, 4 * sizeof(double), hipHostMallocDefault);
     if (herr != hipSuccess) {
         (void)hipFreeAsync(ws, s);
@@ -482,7 +544,7 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
             goto out;
         }
         STEP((k_copy<<<eg, BLOCK, 0, s>>>(n, b, r)));
-        STEP(e = apply_any(F, r, work, z, tickets, err, s));
+        STEP(e = apply_any(F, r, work, z, err, s));
         STEP((k_update_p<<<eg, BLOCK, 0, s>>>(n, z, p, nullptr)));
         STEP((k_dot<<<rg, BLOCK, 0, s>>>(n, r, z, partials)));
         STEP((k_finalize<<<1, BLOCK, 0, s>>>(partials, rg, sc, OP_RHO0)));
@@ -507,13 +569,13 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
                     break;
                 }
                 // restart from the true residual
-                STEP(e = apply_any(F, r, work, z, tickets, err, s));
+                STEP(e = apply_any(F, r, work, z, err, s));
                 STEP((k_update_p<<<eg, BLOCK, 0, s>>>(n, z, p, nullptr)));
                 STEP((k_dot<<<rg, BLOCK, 0, s>>>(n, r, z, partials)));
                 STEP((k_finalize<<<1, BLOCK, 0, s>>>(partials, rg, sc, OP_RHO0)));
                 continue;
             }
-            STEP(e = apply_any(F, r, work, z, tickets, err, s));
+            STEP(e = apply_any(F, r, work, z, err, s));
             STEP((k_dot<<<rg, BLOCK, 0, s>>>(n, r, z, partials)));
             STEP((k_finalize<<<1, BLOCK, 0, s>>>(partials, rg, sc, OP_BETA)));
             STEP((k_update_p<<<eg, BLOCK, 0, s>>>(n, z, p, sc)));

@@ -41,7 +41,7 @@ class _Options(ctypes.Structure):
 
 
 NUM_PHASES = 8
-PHASES = ("validate", "rank", "table", "schedule", "walk", "tally", "factor", "transpose")
+PHASES = ("validate", "rank", "table", "schedule", "walk", "tally", "factor", "plan")
 
 
 class _Stats(ctypes.Structure):

@@ -184,3 +184,128 @@ def config_grid3d(m: int = 128, seed: int = 0) -> CSR:
     grounded with excess ~ U[0.01, 1]; m = 128 gives n = 2,097,152."""
     return grid((m, m, m), g=("loguniform", 1e-2, 1e2), ground_frac=0.01,
                 excess=("uniform", 0.01, 1.0), seed=seed)
+
+
+def rgg_connect_probability(r: float) -> float:
+    """Probability that two independent uniform points of the unit cube lie within
+    distance r <= 1: the integral of prod_i (1 - |d_i|) over the ball |d| <= r,
+    (4 pi/3) r^3 - (3 pi/2) r^4 + (8/5) r^5 - r^6 / 6 (boundary effects included)."""
+    r = float(r)
+    return 4.0 * np.pi / 3.0 * r ** 3 - 1.5 * np.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6.0
+
+
+def _rgg_pairs(pts: np.ndarray, r: float):
+    """All pairs u < v of points closer than r, by a cell list with cell side >= r:
+    each cell meets itself and 13 of its 26 neighbour cells (one of each opposite
+    pair).  Returns (u, v, dist)."""
+    n = pts.shape[0]
+    m = max(1, int(np.floor(1.0 / r)))
+    cell = np.minimum((pts * m).astype(np.int64), m - 1)
+    cid = cell[:, 0] + m * (cell[:, 1] + m * cell[:, 2])
+    order = np.argsort(cid, kind="stable")
+    cs = cid[order]
+    start = np.searchsorted(cs, np.arange(m ** 3 + 1))
+    cnt = np.diff(start)
+    offs = [(0, 0, 0)] + [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                          if (dz, dy, dx) > (0, 0, 0)]
+    us, vs, ds = [], [], []
+    r2 = r * r
+    pc = cell[order]
+    for dx, dy, dz in offs:
+        nc = pc + np.array([dx, dy, dz])
+        ok = np.all((nc >= 0) & (nc < m), axis=1)
+        src = np.nonzero(ok)[0]  # positions in sorted order
+        ncid = nc[src, 0] + m * (nc[src, 1] + m * nc[src, 2])
+        k = cnt[ncid]
+        if (dx, dy, dz) == (0, 0, 0):
+            # same cell: partners after the point itself
+            k = start[ncid + 1] - (src + 1)
+            base = src + 1
+        else:
+            base = start[ncid]
+        tot = int(k.sum())
+        if tot == 0:
+            continue
+        a = np.repeat(src, k)
+        first = np.repeat(base - np.concatenate(([0], np.cumsum(k)[:-1])), k)
+        b = first + np.arange(tot)
+        pa, pb = order[a], order[b]
+        d2 = np.sum((pts[pa] - pts[pb]) ** 2, axis=1)
+        keep = d2 < r2
+        pa, pb, d = pa[keep], pb[keep], np.sqrt(d2[keep])
+        lo, hi = np.minimum(pa, pb), np.maximum(pa, pb)
+        us.append(lo)
+        vs.append(hi)
+        ds.append(d)
+    if not us:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z, np.zeros(0)
+    return np.concatenate(us), np.concatenate(vs), np.concatenate(ds)
+
+
+def rgg(n: int, mean_degree: float = 24.0, *, ground_frac=0.005, excess=("uniform", 0.1, 10.0),
+        w_clip=(1.0, 1e3), seed=0, tol=0.1, return_info=False):
+    """Random geometric graph resistor network: n points uniform in [0,1]^3, an edge
+    between points closer than r with conductance clip(1/dist, w_clip).  r starts at
+    the value whose expected mean degree (boundary effects included) is mean_degree
+    and is bisected on the realised mean degree until it is within tol.
+    round(ground_frac*n) (>= 1) nodes are grounded with excess drawn from `excess`;
+    then every connected component without a grounded node gets one (its smallest
+    node id, excess from the same distribution); their count is reported in info."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 3))
+    target = float(mean_degree)
+
+    def expected_r():
+        lo, hi = 0.0, 1.0
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            if (n - 1) * rgg_connect_probability(mid) < target:
+                lo = mid
+            else:
+                hi = mid
+        return 0.5 * (lo + hi)
+
+    r = expected_r()
+    u, v, d = _rgg_pairs(pts, r)
+    deg = 2.0 * u.size / n
+    if abs(deg - target) > tol:
+        lo, hi = (r, 2.0 * r) if deg < target else (0.5 * r, r)
+        for _ in range(60):
+            r = 0.5 * (lo + hi)
+            u, v, d = _rgg_pairs(pts, r)
+            deg = 2.0 * u.size / n
+            if abs(deg - target) <= tol:
+                break
+            if deg < target:
+                lo = r
+            else:
+                hi = r
+    order = np.lexsort((v, u))
+    u, v, d = u[order], v[order], d[order]
+    g = np.clip(1.0 / d, w_clip[0], w_clip[1])
+    exc = _ground(rng, n, ground_frac, 1, excess)
+    ncomp, label = connected_components(
+        coo_matrix((np.ones(u.size), (u, v)), shape=(n, n)), directed=False)
+    grounded_comp = np.zeros(ncomp, dtype=bool)
+    grounded_comp[label[exc > 0]] = True
+    first = np.full(ncomp, n, dtype=np.int64)
+    np.minimum.at(first, label, np.arange(n))
+    add = first[~grounded_comp]
+    if add.size:
+        exc[add] = _draw(rng, excess, add.size)
+    A = assemble(n, u, v, g, exc)
+    if return_info:
+        return A, {"radius": r, "mean_degree": deg, "components": int(ncomp),
+                   "grounds_added": int(add.size)}
+    return A
+
+
+def config_rgg(n: int = 2_000_000, seed: int = 0, return_info=False):
+    """3D random geometric graph, n = 2,000,000 points, mean degree 24,
+    w = clip(1/dist, 1, 1e3), 0.5% grounded with excess ~ U[0.1, 10]."""
+    return rgg(n, 24.0, ground_frac=0.005, excess=("uniform", 0.1, 10.0), w_clip=(1.0, 1e3),
+               seed=seed, return_info=return_info)

@@ -51,9 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="after the steps, copy a buffer of this many MiB device to device "
-                         "three times (a plain copy kernel of known traffic, for scaling "
-                         "hardware byte counters)")
+                    help="after the steps, copy a buffer of this many MiB three times with an "
+                         "elementwise kernel (known traffic, for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -237,9 +236,9 @@ def main():
         src = torch.ones(nel, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # an elementwise kernel: reads and writes nel doubles
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 x {args.copy_calibration} MiB device-to-device")
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB read + written by one kernel")
         del src, dst
     out["roofline"]["traffic"] = measured_traffic(args.workload, args.precision)
     if args.cpu_seconds > 0:

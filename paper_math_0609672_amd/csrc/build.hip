@@ -363,8 +363,11 @@ struct WalkArgs {
 // the segment queues: the long-walk segment first, then the wave's own slab (by the
 // XCD its workgroup runs on), then the other slabs in turn.  A lane's draws come from
 // the Philox block of its (row, walk, step div 8), generated when step mod 8 = 0.
+#ifndef SRW_WALK_WAVES
+#define SRW_WALK_WAVES 6  // waves per SIMD the register budget is cut for
+#endif
 template <int R>
-__global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_WAVES))) void k_walk(WalkArgs a)
 {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
@@ -464,20 +467,21 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
         } else {
             const uint32_t deg = r0.y & DESC_DEG_MASK;
             degsum += deg;
-            // entries 0..5 sit in the first line (words 4..15), held in registers
+            // The next node is the first entry m with u < threshold_m.  Entries 0..5
+            // sit in the first line (words 4..15), held in registers; they are
+            // scanned from the top with selects (the lowest hit is taken last), so
+            // the scan has no branches.
             const uint32_t e[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
                                     r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
-            bool found = false;
-            uint32_t lastn = 0;
+            uint32_t lastn = e[5];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                if ((uint32_t)m < deg) {
-                    if (!found && u < e[4 + 2 * m]) {
-                        found = true;
-                        next_line = e[5 + 2 * m];
-                    }
-                    lastn = e[5 + 2 * m];
-                }
+            for (int m = 1; m < 6; ++m) lastn = (uint32_t)m < deg ? e[5 + 2 * m] : lastn;
+            bool found = false;
+#pragma unroll
+            for (int m = 5; m >= 0; --m) {
+                const bool hit = (uint32_t)m < deg && u < e[4 + 2 * m];
+                next_line = hit ? e[5 + 2 * m] : next_line;
+                found = found || hit;
             }
             // further lines of a node of degree > 6: 8 entries per line
             for (uint32_t m0 = 6, l = 1; !found && m0 < deg; m0 += 8, ++l) {
@@ -485,16 +489,18 @@ __global__ __launch_bounds__(BLOCK) void k_walk(WalkArgs a)
                 const uint4 x0 = lp[0], x1 = lp[1], x2 = lp[2], x3 = lp[3];
                 const uint32_t f[16] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w,
                                         x2.x, x2.y, x2.z, x2.w, x3.x, x3.y, x3.z, x3.w};
+                uint32_t nl = 0;
+                bool hit_any = false;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    if (m0 + i < deg) {
-                        if (!found && u < f[2 * i]) {
-                            found = true;
-                            next_line = f[2 * i + 1];
-                        }
-                        lastn = f[2 * i + 1];
-                    }
+                for (int i = 7; i >= 0; --i) {
+                    const bool hit = m0 + i < deg && u < f[2 * i];
+                    nl = hit ? f[2 * i + 1] : nl;
+                    hit_any = hit_any || hit;
                 }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) lastn = m0 + i < deg ? f[2 * i + 1] : lastn;
+                next_line = hit_any ? nl : next_line;
+                found = hit_any;
             }
             if (!found) {
                 if (r0.y & DESC_GROUNDED) to_ground = true;

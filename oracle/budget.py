@@ -148,7 +148,8 @@ def mlp_forward(p: dict, X: np.ndarray, round_bf16: bool = False):
     h2 = np.maximum(z2, 0.0)
     h2r = r(h2)
     y = h2r @ r(p["W3"]) + p["b3"][0]
-    cache = {"X": X, "z1": z1, "h1": h1r, "z2": z2, "h2": h2r, "W2": r(p["W2"]), "W3": r(p["W3"])}
+    cache = {"X": X, "z1": z1, "h1": h1r, "z2": z2, "h2": h2r, "W2": r(p["W2"]), "W3": r(p["W3"]),
+             "round": round_bf16}
     return y, cache
 
 
@@ -158,14 +159,17 @@ def mse(y: np.ndarray, t: np.ndarray) -> float:
 
 def mlp_backward(p: dict, cache: dict, dy: np.ndarray) -> dict:
     """Gradients of sum(dy * y) with respect to every parameter (chain rule of the
-    forward pass above, the rounded operands treated as constants)."""
+    forward pass above, the rounded operands treated as constants).  When the forward
+    pass rounded its operands, the pre-activation gradients dZ2 and dZ1 are rounded to
+    bfloat16 too before they enter a product, as the GPU kernels do."""
+    r = bf16 if cache.get("round") else (lambda v: v)
     g = {}
     g["W3"] = cache["h2"].T @ dy
     g["b3"] = np.array([dy.sum()])
-    dz2 = np.outer(dy, cache["W3"]) * (cache["z2"] > 0)
+    dz2 = r(np.outer(dy, cache["W3"]) * (cache["z2"] > 0))
     g["W2"] = cache["h1"].T @ dz2
     g["b2"] = dz2.sum(axis=0)
-    dz1 = (dz2 @ cache["W2"].T) * (cache["z1"] > 0)
+    dz1 = r((dz2 @ cache["W2"].T) * (cache["z1"] > 0))
     g["W1"] = cache["X"].T @ dz1
     g["b1"] = dz1.sum(axis=0)
     return g

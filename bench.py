@@ -34,6 +34,8 @@ WORKLOADS = {
     "grid3d_128": ("config_grid3d", dict(m=128), 256, 1e-4, 1e-8),
     "grid3d_64": ("config_grid3d", dict(m=64), 256, 1e-4, 1e-8),
     "grid2d_32": ("config_grid2d_32", dict(), 64, 1e-3, 1e-8),
+    # 3D random geometric graph, n = 2,000,000, mean degree 24 (generation ~1 min on a host core)
+    "rgg_2m": ("config_rgg", dict(), 512, 1e-4, 1e-10),
 }
 
 
@@ -50,6 +52,9 @@ def parse():
     ap.add_argument("--solve-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="after the timed steps, run one step with the other factor precision "
+                         "(fp32 <-> fp64) and report it under ext_precision")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, copy a buffer of this many MiB three times with an "
                          "elementwise kernel (known traffic, for scaling hardware byte counters)")
@@ -92,7 +97,7 @@ def cpu_baseline(A, walks, seed, target_s):
     }
 
 
-WALK_SOURCES = ("paper_math_0609672_amd/csrc/build.hip", "paper_math_0609672_amd/csrc/common.hpp")
+WALK_SOURCES = ("paper_math_0609672_amd/csrc/walk.hpp", "paper_math_0609672_amd/csrc/common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_traffic.json")
 
 
@@ -231,6 +236,30 @@ def main():
             "avg_launch_ms": round(walk_ms, 3),
         },
     }
+    if args.compare_precision:
+        other = "fp32" if args.precision == "fp64" else "fp64"
+        x_main = x.clone()
+        F2 = srw.build_factor(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
+                              schedule=args.schedule, solve_order=args.solve_order)
+        F2.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F2 = srw.build_factor(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
+                              schedule=args.schedule, solve_order=args.solve_order)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st2, x2, it2, rel2 = srw.pcg_solve(M, F2, b, tol, 10000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F2.free()
+        x64, x32 = (x_main, x2) if args.precision == "fp64" else (x2, x_main)
+        out["ext_precision"] = {
+            "factor_precision": other,
+            "seconds": round(t2 - t0, 4), "build_s": round(t1 - t0, 4), "pcg_s": round(t2 - t1, 4),
+            "pcg_iters": it2, "rel_residual": rel2, "converged": st2 == srw.OK,
+            "x_rel_diff_fp32_vs_fp64": float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)),
+        }
+        log(f"{other} factor: build {t1 - t0:.3f} s, pcg {t2 - t1:.3f} s, iters {it2}")
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device=dev)

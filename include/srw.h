@@ -208,6 +208,95 @@ int srw_pcg_solve(const srw_csr* A, const srw_factor* F, const double* b, double
  * each; r is not modified). */
 int srw_apply(const srw_factor* F, const double* r, double* z, void* stream);
 
+/* ---- batched builds and solves (an extension: the factor does not depend on b and
+ * serves every right-hand side, Sections 2.2 and 6) --------------------------------- */
+
+/* Builds nmat independent R-matrices (A: host array of nmat descriptors of device CSR
+ * arrays) as one block-diagonal matrix: one walk launch for all of them.  Matrix i is
+ * ordered at random with seeds[i] (host array) and its walks are keyed by its own node
+ * ids and seeds[i], so rows off_i .. off_i + n_i - 1 of the result (off_i = n_0 + ... +
+ * n_{i-1}) are the factor srw_build_factor gives for A[i] with seed seeds[i], with node
+ * ids shifted by off_i.  opt as for srw_build_factor, except that the ordering must be
+ * SRW_ORDER_RANDOM; opt->walks, if given, holds budgets over the stacked rows.  The
+ * factor keeps a copy of the stacked matrix; export and srw_apply see the stacked
+ * system. */
+int srw_build_factor_batched(int32_t nmat, const srw_csr* A, int32_t walks_per_row,
+                             double drop_tol, const uint64_t* seeds, const srw_options* opt,
+                             srw_factor** out, void* stream);
+
+/* Number of stacked matrices (0 for a factor of one matrix) and, if row_off is not
+ * NULL, their first rows: row_off int64[nmat + 1] (host). */
+int srw_batch_info(const srw_factor* F, int32_t* nmat, int64_t* row_off);
+
+/* PCG on every (matrix, right-hand side) system of a batched factor at once.  B, X:
+ * device float64 [N][nrhs] row-major over the stacked rows (1 <= nrhs <= 8); each
+ * system (i, j) starts from x0 = 0 and stops when its recurrence residual satisfies
+ * ||r|| <= tol ||b||; then its true residual is computed and a system that misses the
+ * tolerance restarts from it (at most 3 restarts).  Dot products are reduced per
+ * system in a fixed order; the triangular solves carry the nrhs values of a row
+ * together.  use_graph = 1 captures one iteration in a HIP graph and replays it.  On
+ * first use the solve's resident grid is picked by timing 8, 4 and 2 blocks per CU.
+ * Host outputs (may be NULL): iters int32[nmat * nrhs] and rel_residual
+ * float64[nmat * nrhs] (true residuals), system (i, j) at i * nrhs + j.  Returns SRW_OK
+ * or SRW_NOT_CONVERGED (some system missed tol within max_iter). */
+int srw_pcg_solve_batched(srw_factor* F, int32_t nrhs, const double* B, double tol,
+                          int32_t max_iter, double* X, int32_t* iters, double* rel_residual,
+                          int32_t use_graph, void* stream);
+
+/* ---- learned walk budgets (an extension: the paper sets walks per row by a
+ * stopping rule on walk lengths, Section 5.1) ------------------------------------ */
+
+/* Random ordering of Section 5.4 alone: rank int32[n] (device), the same ranks
+ * srw_build_factor computes for this seed with SRW_ORDER_RANDOM. */
+int srw_ordering(int64_t n, uint64_t seed, int32_t* rank, void* stream);
+
+/* Eight float32 features per row (device, row-major [n][8]) from A and the ranks:
+ * 0 degree (off-diagonal entries), 1 log a_k, 2 e_k / a_k (excess e_k = a_k - sum of
+ * the row's conductances w_kj = -A_kj), 3 tau_k (conductance to higher-ranked
+ * neighbours over a_k, Section 5.2), 4 fraction of neighbours ranked above k,
+ * 5 log(max w / min w) over the row, 6 log(n / (rank_k + 1)), 7 mean of e_j / a_j over
+ * the neighbours (0 for the last three quantities without neighbours).  Computed in
+ * float64.  A is not validated here. */
+int srw_row_features(const srw_csr* A, const int32_t* rank, float* features, void* stream);
+
+/* Per-walk variance of each row's estimates from the tallies of F (needs keep >= 1):
+ * label float64[n] (device) = tau^2 sum_i p_i (1 - p_i) + (tau / (1 + tau (m - 1)))^2 s^2
+ * with p_i = H'_{k,i} / M' (Section 3.1, ground excluded), m and s^2 the mean and sample
+ * variance of the stays; the first term is the variance of one walk's contribution to
+ * the entries of eq. newy, the second the first-order relative variance of eq. d.
+ * per_step = 1 divides it by the row's mean walk length (steps per walk): the variance
+ * bought per step.  NaN for rows without walks.  Budgets M_k = label_k / eps give every
+ * row variance eps; M_k proportional to sqrt(label_k) with per_step = 1 minimise the
+ * summed variance at a fixed number of steps. */
+int srw_budget_labels(const srw_factor* F, int32_t per_step, double* label, void* stream);
+
+/* The network: 8 -> 64 -> 64 -> 1, ReLU, one float32 array of SRW_MLP_PARAMS on the
+ * device: W1 [8][64], b1 [64], W2 [64][64], b2 [64], W3 [64], b3 (row-major, x W).
+ * mu_sd float32[16]: per-feature mean then standard deviation; inputs are
+ * (feature - mean) / sd.  Inputs, weights and hidden activations enter the matrix
+ * cores as bfloat16 (nearest, ties to even); sums are float32. */
+#define SRW_MLP_PARAMS 4801
+
+/* out float32[n] = the network's output (predicted log label) for n rows. */
+int srw_mlp_forward(const float* params, const float* mu_sd, const float* features, int64_t n,
+                    float* out, void* stream);
+
+/* One step on the mean squared error over the n rows given (target float32[n]):
+ * gradient by the backward pass (pre-activation gradients rounded to bfloat16 before
+ * each product), summed in a fixed order; then, if adam_m and adam_v (float32
+ * [SRW_MLP_PARAMS], zero before step 1) are not NULL, one Adam update of params
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias correction by step >= 1, learning rate lr).
+ * grad (float32[SRW_MLP_PARAMS]) and loss (float32[1]) are device outputs and may be
+ * NULL.  Work and outputs are ordered on the stream; no synchronisation. */
+int srw_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                       const float* mu_sd, const float* features, const float* target,
+                       int64_t n, float* grad, float* loss, void* stream);
+
+/* walks int32[n] = clamp(ceil(exp(pred) / eps), lo, hi): per-row budgets for
+ * srw_options.walks (rows with tau = 0 take no walks regardless). */
+int srw_mlp_budgets(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi,
+                    int32_t* walks, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* srw_status_string(int status);
 

@@ -18,7 +18,9 @@ row's estimates, and a row's budget is that variance over a target.  Its parts:
   sample variance.  The first term is the variance of one walk's contribution to the
   Y entries of eq. newy (tau_k H / M per entry); the second is the first-order
   relative variance of D_k of eq. d in the mean stays.  A budget M_k = V_k / eps makes
-  every row's estimate variance about eps.
+  every row's estimate variance about eps.  Divided by the row's mean walk length L_k
+  it is the variance bought per step; budgets M_k proportional to sqrt(V_k / L_k)
+  minimise sum_k V_k / M_k at a fixed total sum_k M_k L_k of steps (Lagrange).
 * ``mlp_forward`` / ``mlp_backward``: 8 -> 64 -> 64 -> 1 with ReLU, optional rounding
   of the operands to bfloat16 (round to nearest even) as the GPU kernels use them.
 * ``adam_step``: Adam (Kingma and Ba) on float64 copies of the parameters.
@@ -77,9 +79,10 @@ def features(A, rank: np.ndarray) -> np.ndarray:
     return out
 
 
-def label(tau: float, M: int, J: int, visits_sq: int, h_cnt) -> float:
+def label(tau: float, M: int, J: int, visits_sq: int, h_cnt, steps: int | None = None) -> float:
     """Per-walk variance V_k of one row from its pilot tallies (see module text);
-    h_cnt lists H_ki over the row's home nodes (ground excluded)."""
+    h_cnt lists H_ki over the row's home nodes (ground excluded).  With `steps` (the
+    row's total walk steps) the variance per step: V_k / (steps / M)."""
     M = float(M)
     m = J / M
     s2 = (visits_sq - M * m * m) / (M - 1.0) if M > 1 else 0.0
@@ -90,11 +93,15 @@ def label(tau: float, M: int, J: int, visits_sq: int, h_cnt) -> float:
         p = h / M
         var_y += p * (1.0 - p)
     c = tau / (1.0 + tau * (m - 1.0))
-    return tau * tau * var_y + c * c * s2
+    v = tau * tau * var_y + c * c * s2
+    if steps is not None:
+        v = v / (steps / M)
+    return v
 
 
-def labels(tau: np.ndarray, tallies) -> np.ndarray:
-    """V_k for every row of an all-rows tally (rows without walks give NaN)."""
+def labels(tau: np.ndarray, tallies, per_step: bool = False) -> np.ndarray:
+    """V_k (or V_k per step) for every row of an all-rows tally (rows without walks
+    give NaN)."""
     n = tau.size
     out = np.full(n, np.nan)
     for k in range(n):
@@ -104,7 +111,8 @@ def labels(tau: np.ndarray, tallies) -> np.ndarray:
         a = int(tallies.h_off[k])
         h = [int(c) for c, e in zip(tallies.h_cnt[a:a + int(tallies.hlen[k])],
                                     tallies.h_end[a:a + int(tallies.hlen[k])]) if e >= 0]
-        out[k] = label(float(tau[k]), M, int(tallies.J[k]), int(tallies.visits_sq[k]), h)
+        out[k] = label(float(tau[k]), M, int(tallies.J[k]), int(tallies.visits_sq[k]), h,
+                       int(tallies.steps[k]) if per_step else None)
     return out
 
 

@@ -1,0 +1,753 @@
+// Batched builds and solves (an extension; the paper's factor is independent of b and is
+// reused across right-hand sides, Sections 2.2 and 6): nmat independent R-matrices are
+// stacked block-diagonally and built in one pass -- one walk launch for all of them,
+// each walk keyed by its own matrix's node ids and seed, so block i of the factor is the
+// factor srw_build_factor gives for matrix i alone.  PCG then advances every (matrix,
+// right-hand side) system together: one product with the stacked matrix for all
+// right-hand sides, dot products reduced per system, and triangular solves that carry
+// the nrhs values of a row at once (one dependency chain serves every system).  One
+// iteration is captured in a HIP graph and replayed.
+//
+// Layouts: right-hand sides and solutions are [rows][nrhs] row-major, matrices stacked
+// in order.  A system's scalars (rho, alpha, ...) live on the device; a system stops
+// moving once its recurrence residual meets the tolerance.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "factor.hpp"
+
+namespace srw {
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int MAXR = 8;          // right-hand sides per system group
+constexpr int TILE_ROWS = 1024;  // rows of one reduction tile (never spans two matrices)
+
+// ------------------------------------------------------------------- stacking
+__global__ void k_stack_rowptr(int64_t n, const int64_t* __restrict__ src, int64_t row_off,
+                               int64_t nnz_off, int64_t* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) dst[row_off + i] = src[i] + nnz_off;
+}
+
+__global__ void k_stack_col(int64_t nnz, const int32_t* __restrict__ src, int32_t row_off,
+                            int32_t* __restrict__ dst)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) dst[q] = src[q] + row_off;
+}
+
+__global__ void k_offset_i32(int64_t n, int32_t* __restrict__ x, int32_t add)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += add;
+}
+
+// matrix of every stacked row: the last matrix whose first row is <= the row
+__global__ void k_node_mat(int64_t n, int32_t nmat, const int64_t* __restrict__ off,
+                           int32_t* __restrict__ node_mat)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t lo = 0, hi = nmat - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) / 2;
+        if (off[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    node_mat[v] = lo;
+}
+
+// ------------------------------------------------------------------ reductions
+enum BOp : int { B_BB = 0, B_RHO0, B_ALPHA, B_RR, B_BETA, B_TRUE_RR };
+
+// One system's scalars.
+struct Sys {
+    double rho, pq, alpha, rr, beta, bb;
+    int32_t active, iters;
+};
+
+__device__ __forceinline__ double block_sum(double v, double* lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
+    __syncthreads();
+    return s;
+}
+
+struct Tiles {
+    const int32_t* mat;   // [ntile] matrix of the tile
+    const int64_t* row0;  // [ntile + 1] first row (tiles are contiguous)
+};
+
+// Partials over one tile: q = A p and p . q (OP_PQ), r . z (OP_DOT), r . r after the
+// x / r update (OP_UPD), ||b - A x||^2 (OP_RES, r overwritten), b . b (OP_BB)
+enum TOp : int { T_PQ = 0, T_DOT, T_UPD, T_RES, T_BB };
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_tile(Tiles tl, int nrhs, const int64_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ u,  // p, r, b
+                                                const double* __restrict__ v,  // z, q, x
+                                                double* __restrict__ w,        // q, x, r
+                                                double* __restrict__ r2,       // r (T_UPD)
+                                                const Sys* __restrict__ sys,
+                                                double* __restrict__ partials)
+{
+    __shared__ double lds[BLOCK / 64];
+    const int64_t t = blockIdx.x;
+    const int32_t m = tl.mat[t];
+    const int64_t r0 = tl.row0[t], r1 = tl.row0[t + 1];
+    double acc[MAXR];
+#pragma unroll
+    for (int j = 0; j < MAXR; ++j) acc[j] = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+        if (OP == T_PQ || OP == T_RES) {
+            double s[MAXR];
+#pragma unroll
+            for (int j = 0; j < MAXR; ++j) s[j] = 0.0;
+            const double* src = OP == T_PQ ? u : v;  // p, or x
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                const double a = val[e];
+                const double* pc = src + (int64_t)col[e] * nrhs;
+#pragma unroll
+                for (int j = 0; j < MAXR; ++j)
+                    if (j < nrhs) s[j] += a * pc[j];
+            }
+#pragma unroll
+            for (int j = 0; j < MAXR; ++j) {
+                if (j >= nrhs) continue;
+                if (OP == T_PQ) {
+                    w[i * nrhs + j] = s[j];
+                    acc[j] += u[i * nrhs + j] * s[j];
+                } else {
+                    const double rv = u[i * nrhs + j] - s[j];  // b - A x
+                    w[i * nrhs + j] = rv;
+                    acc[j] += rv * rv;
+                }
+            }
+        } else if (OP == T_DOT || OP == T_BB) {
+#pragma unroll
+            for (int j = 0; j < MAXR; ++j)
+                if (j < nrhs) acc[j] += u[i * nrhs + j] * (OP == T_BB ? u[i * nrhs + j] : v[i * nrhs + j]);
+        } else {  // T_UPD: x += alpha p, r -= alpha q (active systems)
+#pragma unroll
+            for (int j = 0; j < MAXR; ++j) {
+                if (j >= nrhs) continue;
+                const Sys& S = sys[(int64_t)m * nrhs + j];
+                double rv = r2[i * nrhs + j];
+                if (S.active) {
+                    w[i * nrhs + j] = w[i * nrhs + j] + S.alpha * u[i * nrhs + j];
+                    rv = rv - S.alpha * v[i * nrhs + j];
+                    r2[i * nrhs + j] = rv;
+                }
+                acc[j] += rv * rv;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MAXR; ++j) {
+        if (j >= nrhs) continue;
+        const double s = block_sum(acc[j], lds);
+        if (threadIdx.x == 0) partials[t * nrhs + j] = s;
+    }
+}
+
+// One thread per system: sum the partials of its matrix's tiles in order, then the
+// scalar update of `op`.
+__global__ void k_bfinal(int64_t nsys, int nrhs, const int64_t* __restrict__ mat_tile,
+                         const double* __restrict__ partials, Sys* __restrict__ sys, int op,
+                         double tol, int32_t max_iter, int* __restrict__ active_count)
+{
+    const int64_t sidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx >= nsys) return;
+    const int64_t m = sidx / nrhs;
+    const int j = (int)(sidx % nrhs);
+    double s = 0.0;
+    for (int64_t t = mat_tile[m]; t < mat_tile[m + 1]; ++t) s += partials[t * nrhs + j];
+    Sys& S = sys[sidx];
+    switch (op) {
+        case B_BB:
+            S.bb = s;
+            S.active = s > 0.0 ? 1 : 0;
+            S.iters = 0;
+            break;
+        case B_RHO0:
+            if (S.active) S.rho = s;
+            break;
+        case B_ALPHA:
+            if (S.active) {
+                S.pq = s;
+                S.alpha = S.rho / s;
+            }
+            break;
+        case B_RR:
+            if (S.active) {
+                S.rr = s;
+                S.iters += 1;
+                if (sqrt(s) <= tol * sqrt(S.bb) || S.iters >= max_iter || !(s == s)) S.active = 0;
+                else atomicAdd(active_count, 1);
+            }
+            break;
+        case B_BETA:
+            if (S.active) {
+                S.beta = s / S.rho;
+                S.rho = s;
+            }
+            break;
+        case B_TRUE_RR:
+            S.rr = s;
+            // restart a system whose true residual misses the tolerance
+            if (S.bb > 0.0 && sqrt(s) > tol * sqrt(S.bb) && S.iters < max_iter && s == s) {
+                S.active = 1;
+                atomicAdd(active_count, 1);
+            } else {
+                S.active = 0;
+            }
+            break;
+    }
+}
+
+// p = z (restart) or p = z + beta p, active systems only
+__global__ void k_bupdate_p(int64_t n, int nrhs, const int32_t* __restrict__ node_mat,
+                            const double* __restrict__ z, double* __restrict__ p,
+                            const Sys* __restrict__ sys, int restart)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t row = i / nrhs;
+    const int j = (int)(i % nrhs);
+    const Sys& S = sys[(int64_t)node_mat[row] * nrhs + j];
+    if (!S.active) return;
+    p[i] = restart ? z[i] : z[i] + S.beta * p[i];
+}
+
+__global__ void k_copy_d(int64_t n, const double* __restrict__ a, double* __restrict__ b)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+__global__ void k_zero_d(int64_t n, double* __restrict__ a)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+__global__ void k_zero_i(int* a) { *a = 0; }
+
+// --------------------------------------------------- multi right-hand-side solves
+// The substitutions of solve.hip with nrhs values per slot, stored [slot][nrhs]: a
+// row's values are published by lane 0 with one device-scope store each, every value
+// its own ready flag (signalling-NaN sentinel).  A waiting wave polls one address --
+// the last value of its dependency that the order solves last -- then reloads its
+// missing values.  Wave i takes slots i, i + W, ...; the grid is sized so that every
+// wave is resident (occupancy x CUs).
+template <typename T>
+struct MBits;
+template <>
+struct MBits<double> {
+    using U = unsigned long long;
+    static constexpr U sentinel = 0x7FF4DEADBEEF5A5Aull;
+    static __device__ U nan_bits() { return 0x7FF8000000000000ull; }
+};
+template <>
+struct MBits<float> {
+    using U = unsigned int;
+    static constexpr U sentinel = 0x7FA5A5A5u;
+    static __device__ U nan_bits() { return 0x7FC00000u; }
+};
+
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_mfill(int64_t n, T* x)
+{
+    using U = typename MBits<T>::U;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        ((U*)x)[i] = MBits<T>::sentinel;
+}
+
+template <typename U>
+__device__ __forceinline__ U mload(const U* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs,
+                                                      const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const T* __restrict__ val,
+                                                      const T* __restrict__ dslot,
+                                                      const int32_t* __restrict__ slot_node,
+                                                      const double* __restrict__ rhs,
+                                                      const T* __restrict__ w, T* sol,
+                                                      double* __restrict__ out, int* err)
+{
+    using U = typename MBits<T>::U;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
+    const int64_t wid =
+        (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t i = wid; i < n; i += nw) {
+        const int64_t s = FWD ? i : n - 1 - i;
+        const int64_t q0 = ptr[s], q1 = ptr[s + 1];
+        T acc[MAXR];
+#pragma unroll
+        for (int j = 0; j < MAXR; ++j) acc[j] = T(0);
+        for (int64_t qb = q0; qb < q1; qb += 64) {
+            const int64_t q = qb + lane;
+            const bool ok = q < q1;
+            const int32_t c = ok ? col[q] : 0;
+            const T a = ok ? val[q] : T(0);
+            const U* src = (const U*)sol + (int64_t)c * nrhs;
+            U bits[MAXR];
+            bool miss_mine = false;
+#pragma unroll
+            for (int j = 0; j < MAXR; ++j) {
+                bits[j] = (ok && j < nrhs) ? mload(src + j) : U(0);
+                miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
+            }
+            uint64_t miss = ballot(miss_mine);
+            uint32_t spins = 0;
+            while (miss != 0) {
+                // give up at the limit, or at once when another wave already gave up
+                // (a failed solve then drains instead of waiting at every row)
+                const bool failed = (spins & 255u) == 255u &&
+                                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                if (++spins > SPIN_LIMIT || failed) {
+                    if (lane == 0) atomicOr(err, 1);
+#pragma unroll
+                    for (int j = 0; j < MAXR; ++j)
+                        if (bits[j] == MBits<T>::sentinel) bits[j] = MBits<T>::nan_bits();
+                    break;
+                }
+                const bool mine = (miss >> lane) & 1ull;
+                const int key = wave_max_i(mine ? (FWD ? c : -c) : INT_MIN);
+                const int32_t lead = FWD ? key : -key;
+                const U lb = mload((const U*)sol + (int64_t)lead * nrhs + (nrhs - 1));
+                if (lb == MBits<T>::sentinel) {
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
+                miss_mine = false;
+#pragma unroll
+                for (int j = 0; j < MAXR; ++j) {
+                    if (mine && j < nrhs && bits[j] == MBits<T>::sentinel) bits[j] = mload(src + j);
+                    miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
+                }
+                miss = ballot(miss_mine);
+            }
+#pragma unroll
+            for (int j = 0; j < MAXR; ++j) acc[j] += a * __builtin_bit_cast(T, bits[j]);
+        }
+        const int32_t node = slot_node[s];
+#pragma unroll
+        for (int j = 0; j < MAXR; ++j) {
+            if (j >= nrhs) continue;
+            const T sum = wave_sum(acc[j]);
+            if (lane == 0) {
+                const T base = FWD ? w[s * nrhs + j] / dslot[s] : (T)rhs[(int64_t)node * nrhs + j];
+                const T x = base - sum;
+                __hip_atomic_store((U*)sol + s * nrhs + j, __builtin_bit_cast(U, x),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (out) out[(int64_t)node * nrhs + j] = (double)x;
+            }
+        }
+    }
+}
+
+int fill_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(grid_for(n, BLOCK), 1), 2048); }
+
+}  // namespace
+
+// -------------------------------------------------------------------- the build
+int build_batched_impl(int32_t nmat, const srw_csr* A, int32_t walks_per_row, double drop_tol,
+                       const uint64_t* seeds, const srw_options* opt_in, srw_factor** out,
+                       hipStream_t s)
+{
+    std::vector<int64_t> off(nmat + 1, 0), nnz_off(nmat + 1, 0);
+    for (int32_t i = 0; i < nmat; ++i) {
+        off[i + 1] = off[i] + A[i].n;
+        nnz_off[i + 1] = nnz_off[i] + A[i].nnz;
+    }
+    const int64_t N = off[nmat], NNZ = nnz_off[nmat];
+    if (N >= (int64_t)0x7FFFFFFF) return SRW_E_ARG;
+    Arena own;  // arrays the factor keeps
+#define BALLOC(T, cnt) own.alloc<T>((size_t)(cnt))
+    int64_t* rowptr = BALLOC(int64_t, N + 1);
+    int32_t* col = BALLOC(int32_t, std::max<int64_t>(NNZ, 1));
+    double* val = BALLOC(double, std::max<int64_t>(NNZ, 1));
+    int32_t* rank = BALLOC(int32_t, std::max<int64_t>(N, 1));
+    int32_t* node_mat = BALLOC(int32_t, std::max<int64_t>(N, 1));
+    int64_t* mat_off = BALLOC(int64_t, nmat + 1);
+    uint64_t* mat_seed = BALLOC(uint64_t, nmat);
+#undef BALLOC
+    auto fail = [&](int st) {
+        (void)hipStreamSynchronize(s);
+        own.release();
+        return st;
+    };
+    if (!rowptr || !col || !val || !rank || !node_mat || !mat_off || !mat_seed) return fail(SRW_E_NOMEM);
+    hipError_t e = hipSuccess;
+    for (int32_t i = 0; i < nmat && e == hipSuccess; ++i) {
+        const int64_t n = A[i].n, nnz = A[i].nnz;
+        k_stack_rowptr<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, A[i].rowptr, off[i], nnz_off[i], rowptr);
+        if (nnz > 0) {
+            k_stack_col<<<grid_for(nnz, BLOCK), BLOCK, 0, s>>>(nnz, A[i].col, (int32_t)off[i], col + nnz_off[i]);
+            e = hipMemcpyAsync(val + nnz_off[i], A[i].val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s);
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(mat_off, off.data(), (nmat + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(mat_seed, seeds, nmat * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && N > 0) {
+        k_node_mat<<<grid_for(N, BLOCK), BLOCK, 0, s>>>(N, nmat, mat_off, node_mat);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return fail(hip_fail(e, "batched stacking"));
+    // one random ordering per matrix (its own seed), shifted into the stacked order
+    for (int32_t i = 0; i < nmat; ++i) {
+        const int64_t n = A[i].n;
+        if (n == 0) continue;
+        int st = ordering_impl(n, seeds[i], rank + off[i], s);
+        if (st) return fail(st);
+        k_offset_i32<<<grid_for(n, BLOCK), BLOCK, 0, s>>>(n, rank + off[i], (int32_t)off[i]);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return fail(hip_fail(e, "batched ordering"));
+    srw_options opt = *opt_in;
+    opt.ordering = SRW_ORDER_GIVEN;
+    opt.rank = rank;
+    srw_csr cat{N, NNZ, rowptr, col, val};
+    BatchKeys keys{node_mat, mat_off, mat_seed};
+    srw_factor* F = nullptr;
+    const int st = build_factor_impl(&cat, walks_per_row, drop_tol, 0, &opt, &F, s, &keys);
+    if (st != SRW_OK) return fail(st);
+    F->nmat = nmat;
+    F->mat_off_host = off;
+    F->mat_off = mat_off;
+    F->node_mat = node_mat;
+    F->Acat = cat;
+    for (void* p : own.blocks) F->allocations.push_back(p);
+    own.blocks.clear();
+    *out = F;
+    return SRW_OK;
+}
+
+// -------------------------------------------------------------------- the solve
+namespace {
+
+struct BatchWork {
+    int64_t N = 0, nsys = 0, ntile = 0;
+    int nrhs = 0;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *partials = nullptr;
+    void* work = nullptr;  // 2 N nrhs values of the factor's precision
+    Sys* sys = nullptr;
+    int* active = nullptr;
+    int* err = nullptr;
+    Tiles tiles{};
+    int64_t* mat_tile = nullptr;
+};
+
+template <typename K>
+hipError_t resident_launch(K kernel, int64_t rows, int per_cu_cap, void** args, hipStream_t s,
+                           bool cooperative)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
+    int64_t blocks = (int64_t)cus * std::max(1, per_cu);
+    blocks = std::min<int64_t>(blocks, (rows + BLOCK / 64 - 1) / (BLOCK / 64));
+    if (blocks < 1) blocks = 1;
+    if (cooperative)
+        return hipLaunchCooperativeKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK), args, 0, s);
+    return hipLaunchKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK), args, 0, s);
+}
+
+template <typename T>
+hipError_t batch_apply(const srw_factor* F, BatchWork& W, bool cooperative, hipStream_t s)
+{
+    int64_t n = F->n;
+    int nrhs = W.nrhs;
+    T* work = (T*)W.work;
+    T* sol = work + n * nrhs;
+    k_mfill<T><<<fill_grid(n * nrhs), BLOCK, 0, s>>>(n * nrhs, work);
+    k_mfill<T><<<fill_grid(n * nrhs), BLOCK, 0, s>>>(n * nrhs, sol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        const int64_t* ptr = F->bptr;
+        const int32_t* col = F->bcol;
+        const T* val = (const T*)F->bval;
+        const T* dslot = nullptr;
+        const int32_t* sn = F->slot_node;
+        const double* rhs = W.r;
+        const T* w = nullptr;
+        T* o = work;
+        double* out = nullptr;
+        int* err = W.err;
+        void* args[] = {&n, &nrhs, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err};
+        e = resident_launch(k_trsv_multi<T, false>, n, F->batch_per_cu, args, s, cooperative);
+        if (e != hipSuccess) return e;
+    }
+    {
+        const int64_t* ptr = F->fptr;
+        const int32_t* col = F->fcol;
+        const T* val = (const T*)F->fval;
+        const T* dslot = (const T*)F->dslot;
+        const int32_t* sn = F->slot_node;
+        const double* rhs = nullptr;
+        const T* w = work;
+        T* o = sol;
+        double* out = W.z;
+        int* err = W.err;
+        void* args[] = {&n, &nrhs, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err};
+        e = resident_launch(k_trsv_multi<T, true>, n, F->batch_per_cu, args, s, cooperative);
+    }
+    return e;
+}
+
+hipError_t apply_b(const srw_factor* F, BatchWork& W, bool cooperative, hipStream_t s)
+{
+    return F->precision == SRW_FP32 ? batch_apply<float>(F, W, cooperative, s)
+                                    : batch_apply<double>(F, W, cooperative, s);
+}
+
+// z = M^{-1} r, then rho / p for the active systems (restart = 1: p = z)
+hipError_t iteration(const srw_factor* F, BatchWork& W, const double* x_dummy, double* X,
+                     double tol, int32_t max_iter, bool cooperative, hipStream_t s)
+{
+    (void)x_dummy;
+    const srw_csr& A = F->Acat;
+    const int nrhs = W.nrhs;
+    const int sg = (int)((W.nsys + 255) / 256);
+    const int64_t nv = W.N * nrhs;
+    hipError_t e;
+    k_tile<T_PQ><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, A.rowptr, A.col, A.val, W.p,
+                                                     nullptr, W.q, nullptr, W.sys, W.partials);
+    k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_ALPHA, tol, max_iter, W.active);
+    k_zero_i<<<1, 1, 0, s>>>(W.active);
+    k_tile<T_UPD><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.p,
+                                                      W.q, X, W.r, W.sys, W.partials);
+    k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_RR, tol, max_iter, W.active);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = apply_b(F, W, cooperative, s)) != hipSuccess) return e;
+    k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.r,
+                                                      W.z, nullptr, nullptr, W.sys, W.partials);
+    k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_BETA, tol, max_iter, W.active);
+    k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 0);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, int32_t max_iter,
+                     double* X, int32_t* iters, double* rel, int32_t use_graph, hipStream_t s)
+{
+    BatchWork W;
+    W.N = F->n;
+    W.nrhs = nrhs;
+    W.nsys = (int64_t)F->nmat * nrhs;
+    // reduction tiles: TILE_ROWS rows, never across a matrix boundary
+    std::vector<int32_t> tmat;
+    std::vector<int64_t> trow, mtile(F->nmat + 1, 0);
+    for (int32_t m = 0; m < F->nmat; ++m) {
+        mtile[m] = (int64_t)tmat.size();
+        for (int64_t r = F->mat_off_host[m]; r < F->mat_off_host[m + 1]; r += TILE_ROWS) {
+            tmat.push_back(m);
+            trow.push_back(r);
+        }
+    }
+    mtile[F->nmat] = (int64_t)tmat.size();
+    trow.push_back(W.N);
+    W.ntile = (int64_t)tmat.size();
+    const int64_t nv = W.N * nrhs;
+    const size_t vb = F->precision == SRW_FP32 ? sizeof(float) : sizeof(double);
+    size_t bytes = 0;
+    auto take = [&](size_t b) { size_t o = bytes; bytes += (b + 255) & ~(size_t)255; return o; };
+    const size_t o_r = take(nv * 8), o_z = take(nv * 8), o_p = take(nv * 8), o_q = take(nv * 8);
+    const size_t o_work = take(2 * nv * vb);
+    const size_t o_part = take(std::max<int64_t>(W.ntile, 1) * nrhs * 8);
+    const size_t o_sys = take(std::max<int64_t>(W.nsys, 1) * sizeof(Sys));
+    const size_t o_flag = take(64);
+    const size_t o_tm = take(std::max<int64_t>(W.ntile, 1) * 4), o_tr = take((W.ntile + 1) * 8);
+    const size_t o_mt = take((F->nmat + 1) * 8);
+    char* ws = nullptr;
+    SRW_HIP(hipMallocAsync((void**)&ws, bytes, s));
+    W.r = (double*)(ws + o_r);
+    W.z = (double*)(ws + o_z);
+    W.p = (double*)(ws + o_p);
+    W.q = (double*)(ws + o_q);
+    W.work = ws + o_work;
+    W.partials = (double*)(ws + o_part);
+    W.sys = (Sys*)(ws + o_sys);
+    W.active = (int*)(ws + o_flag);
+    W.err = W.active + 1;
+    int32_t* d_tmat = (int32_t*)(ws + o_tm);
+    int64_t* d_trow = (int64_t*)(ws + o_tr);
+    W.mat_tile = (int64_t*)(ws + o_mt);
+    W.tiles = Tiles{d_tmat, d_trow};
+    Sys* host_sys = nullptr;
+    int* host_flag = nullptr;
+    hipError_t e = hipHostMalloc((void**)&host_sys, std::max<int64_t>(W.nsys, 1) * sizeof(Sys), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&host_flag, 2 * sizeof(int), hipHostMallocDefault);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const int sg = (int)((W.nsys + 255) / 256);
+    const srw_csr& A = F->Acat;
+    auto sync_flags = [&]() -> hipError_t {
+        hipError_t ee = hipMemcpyAsync(host_flag, W.active, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (ee == hipSuccess) ee = hipStreamSynchronize(s);
+        return ee;
+    };
+    int status = SRW_OK;
+#define CK(call)                          \
+    do {                                  \
+        if (e == hipSuccess) e = (call);  \
+        if (e == hipSuccess) e = hipGetLastError(); \
+    } while (0)
+    CK(hipMemcpyAsync(d_tmat, tmat.data(), W.ntile * 4, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(d_trow, trow.data(), (W.ntile + 1) * 8, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(W.mat_tile, mtile.data(), (F->nmat + 1) * 8, hipMemcpyHostToDevice, s));
+    if (e == hipSuccess) {
+        k_zero_i<<<1, 1, 0, s>>>(W.err);
+        k_zero_d<<<fill_grid(nv), BLOCK, 0, s>>>(nv, X);
+        k_copy_d<<<fill_grid(nv), BLOCK, 0, s>>>(nv, B, W.r);
+        k_tile<T_BB><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, B,
+                                                         nullptr, nullptr, nullptr, W.sys, W.partials);
+        k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_BB, tol, max_iter, W.active);
+        e = hipGetLastError();
+    }
+    // autotune the resident grid of the solves once per factor: 8, 4 or 2 blocks per CU
+    if (e == hipSuccess && F->batch_per_cu == 0) {
+        float best = 1e30f;
+        int best_cap = 8;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        for (int cap : {8, 4, 2}) {
+            if (e != hipSuccess) break;
+            F->batch_per_cu = cap;
+            CK(apply_b(F, W, true, s));  // warm
+            CK(hipEventRecord(e0, s));
+            CK(apply_b(F, W, true, s));
+            CK(hipEventRecord(e1, s));
+            CK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                best_cap = cap;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        F->batch_per_cu = best_cap;
+        F->batch_apply_ms = best;
+    }
+    // z = M^{-1} r, p = z, rho = r . z
+    CK(apply_b(F, W, true, s));
+    if (e == hipSuccess) {
+        k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 1);
+        k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.r,
+                                                          W.z, nullptr, nullptr, W.sys, W.partials);
+        k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_RHO0, tol, max_iter, W.active);
+        e = hipGetLastError();
+    }
+    // one iteration captured once, replayed CHUNK times between host checks
+    const int CHUNK = 8;
+    // captured on a private stream (the caller's may be the null stream, which cannot
+    // be captured) and replayed on the caller's stream
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess && use_graph) {
+        CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        if (e == hipSuccess) {
+            hipError_t ce = iteration(F, W, nullptr, X, tol, max_iter, false, cs);
+            hipError_t ee = hipStreamEndCapture(cs, &graph);
+            e = ce != hipSuccess ? ce : ee;
+        }
+        CK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    for (int outer = 0; e == hipSuccess && outer < 4; ++outer) {
+        int done_iters = 0;
+        while (e == hipSuccess && done_iters < max_iter) {
+            for (int k = 0; k < CHUNK && e == hipSuccess; ++k) {
+                if (use_graph) e = hipGraphLaunch(exec, s);
+                else e = iteration(F, W, nullptr, X, tol, max_iter, true, s);
+            }
+            done_iters += CHUNK;
+            if (e == hipSuccess) e = sync_flags();
+            if (e == hipSuccess && (host_flag[1] != 0)) break;  // a solve gave up waiting
+            if (e == hipSuccess && host_flag[0] == 0) break;    // every system stopped
+        }
+        if (e != hipSuccess || host_flag[1] != 0) break;
+        // true residuals; systems that miss the tolerance restart from them
+        k_zero_i<<<1, 1, 0, s>>>(W.active);
+        k_tile<T_RES><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, A.rowptr, A.col, A.val, B, X,
+                                                          W.r, nullptr, W.sys, W.partials);
+        k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_TRUE_RR, tol, max_iter, W.active);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = sync_flags();
+        if (e != hipSuccess || host_flag[0] == 0) break;
+        CK(apply_b(F, W, true, s));
+        if (e == hipSuccess) {
+            k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 1);
+            k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr,
+                                                              W.r, W.z, nullptr, nullptr, W.sys, W.partials);
+            k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_RHO0, tol, max_iter, W.active);
+            e = hipGetLastError();
+        }
+    }
+    CK(hipMemcpyAsync(host_sys, W.sys, W.nsys * sizeof(Sys), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (e == hipSuccess) {
+        if (host_flag[1] != 0) e = hipErrorLaunchFailure;  // a triangular solve gave up
+        bool all = true;
+        for (int64_t i = 0; i < W.nsys; ++i) {
+            const Sys& S = host_sys[i];
+            const double r = S.bb > 0.0 ? std::sqrt(S.rr) / std::sqrt(S.bb) : 0.0;
+            if (iters) iters[i] = S.iters;
+            if (rel) rel[i] = r;
+            if (!(r <= tol)) all = false;
+        }
+        if (!all) status = SRW_NOT_CONVERGED;
+    }
+#undef CK
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    (void)hipFreeAsync(ws, s);
+    (void)hipStreamSynchronize(s);
+    if (host_sys) (void)hipHostFree(host_sys);
+    if (host_flag) (void)hipHostFree(host_flag);
+    if (e != hipSuccess) return hip_fail(e, "batched pcg");
+    return status;
+}
+
+}  // namespace srw

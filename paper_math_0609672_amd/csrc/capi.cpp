@@ -25,6 +25,20 @@ int copy_out(T* dst, const void* src, size_t count, hipStream_t s)
     return SRW_OK;
 }
 
+int options_ok(const srw_options* opt, int64_t n)
+{
+    if (!opt) return SRW_OK;
+    if (opt->ordering != SRW_ORDER_RANDOM && opt->ordering != SRW_ORDER_GIVEN) return SRW_E_ARG;
+    if (opt->factor_precision != SRW_FP64 && opt->factor_precision != SRW_FP32) return SRW_E_ARG;
+    if (opt->keep < 0 || opt->keep > 2) return SRW_E_ARG;
+    const int rp = opt->refill_period;
+    if (rp != 0 && rp != 1 && rp != 2 && rp != 4 && rp != 8) return SRW_E_ARG;
+    if (opt->schedule != 0 && opt->schedule != 1) return SRW_E_ARG;
+    if (opt->solve_order != 0 && opt->solve_order != 1) return SRW_E_ARG;
+    if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && n > 0) return SRW_E_ARG;
+    return SRW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -44,6 +58,70 @@ void srw_default_options(srw_options* opt)
     opt->solve_order = 1;
 }
 
+
+int srw_build_factor_batched(int32_t nmat, const srw_csr* A, int32_t walks_per_row,
+                             double drop_tol, const uint64_t* seeds, const srw_options* opt,
+                             srw_factor** out, void* stream)
+{
+    if (!out) return SRW_E_ARG;
+    *out = nullptr;
+    if (nmat < 1 || !A || !seeds) return SRW_E_ARG;
+    int64_t total = 0;
+    for (int32_t i = 0; i < nmat; ++i) {
+        if (!csr_ok(&A[i])) return SRW_E_ARG;
+        total += A[i].n;
+    }
+    if (total >= (int64_t)0x7FFFFFFF) return SRW_E_ARG;
+    if (!(drop_tol >= 0.0) || !std::isfinite(drop_tol)) return SRW_E_ARG;
+    if (options_ok(opt, total) != SRW_OK) return SRW_E_ARG;
+    if (opt && opt->ordering != SRW_ORDER_RANDOM) return SRW_E_ARG;  // one ordering per matrix
+    if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
+    if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
+    srw_options o;
+    srw_default_options(&o);
+    if (opt) o = *opt;
+    try {
+        return srw::build_batched_impl(nmat, A, walks_per_row, drop_tol, seeds, &o, out,
+                                       as_stream(stream));
+    } catch (const std::bad_alloc&) {
+        return SRW_E_NOMEM;
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
+int srw_batch_info(const srw_factor* F, int32_t* nmat, int64_t* row_off)
+{
+    if (!F) return SRW_E_ARG;
+    if (nmat) *nmat = F->nmat;
+    if (row_off)
+        for (int32_t i = 0; i <= F->nmat && F->nmat > 0; ++i) row_off[i] = F->mat_off_host[i];
+    return SRW_OK;
+}
+
+int srw_pcg_solve_batched(srw_factor* F, int32_t nrhs, const double* B, double tol,
+                          int32_t max_iter, double* X, int32_t* iters, double* rel_residual,
+                          int32_t use_graph, void* stream)
+{
+    if (!F || F->nmat < 1 || nrhs < 1 || nrhs > 8) return SRW_E_ARG;
+    if (!(tol >= 0.0) || max_iter < 0) return SRW_E_ARG;
+    const int64_t nsys = (int64_t)F->nmat * nrhs;
+    if (F->n == 0) {
+        for (int64_t i = 0; i < nsys; ++i) {
+            if (iters) iters[i] = 0;
+            if (rel_residual) rel_residual[i] = 0.0;
+        }
+        return SRW_OK;
+    }
+    if (!B || !X) return SRW_E_ARG;
+    try {
+        return srw::pcg_batched_impl(F, nrhs, B, tol, max_iter, X, iters, rel_residual,
+                                     use_graph ? 1 : 0, as_stream(stream));
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
 int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                      const srw_options* opt, srw_factor** out, void* stream)
 {
@@ -51,16 +129,7 @@ int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, u
     *out = nullptr;
     if (!csr_ok(A)) return SRW_E_ARG;
     if (!(drop_tol >= 0.0) || !std::isfinite(drop_tol)) return SRW_E_ARG;
-    if (opt) {
-        if (opt->ordering != SRW_ORDER_RANDOM && opt->ordering != SRW_ORDER_GIVEN) return SRW_E_ARG;
-        if (opt->factor_precision != SRW_FP64 && opt->factor_precision != SRW_FP32) return SRW_E_ARG;
-        if (opt->keep < 0 || opt->keep > 2) return SRW_E_ARG;
-        const int rp = opt->refill_period;
-        if (rp != 0 && rp != 1 && rp != 2 && rp != 4 && rp != 8) return SRW_E_ARG;
-        if (opt->schedule != 0 && opt->schedule != 1) return SRW_E_ARG;
-        if (opt->solve_order != 0 && opt->solve_order != 1) return SRW_E_ARG;
-        if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && A->n > 0) return SRW_E_ARG;
-    }
+    if (options_ok(opt, A->n) != SRW_OK) return SRW_E_ARG;
     if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
     if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
     try {
@@ -220,6 +289,55 @@ int srw_apply(const srw_factor* F, const double* r, double* z, void* stream)
     if (F->n == 0) return SRW_OK;
     if (!r || !z) return SRW_E_ARG;
     return srw::apply_impl(const_cast<srw_factor*>(F), r, z, as_stream(stream));
+}
+
+int srw_ordering(int64_t n, uint64_t seed, int32_t* rank, void* stream)
+{
+    if (n < 0 || n >= (int64_t)0x7FFFFFFF || (n > 0 && !rank)) return SRW_E_ARG;
+    return srw::ordering_impl(n, seed, rank, as_stream(stream));
+}
+
+int srw_row_features(const srw_csr* A, const int32_t* rank, float* features, void* stream)
+{
+    if (!csr_ok(A)) return SRW_E_ARG;
+    if (A->n > 0 && (!rank || !features)) return SRW_E_ARG;
+    return srw::features_impl(A, rank, features, as_stream(stream));
+}
+
+int srw_budget_labels(const srw_factor* F, int32_t per_step, double* label, void* stream)
+{
+    if (!F || F->keep < 1 || (per_step != 0 && per_step != 1)) return SRW_E_ARG;
+    if (F->n > 0 && !label) return SRW_E_ARG;
+    return srw::labels_impl(F, per_step, label, as_stream(stream));
+}
+
+int srw_mlp_forward(const float* params, const float* mu_sd, const float* features, int64_t n,
+                    float* out, void* stream)
+{
+    if (n < 0) return SRW_E_ARG;
+    if (n > 0 && (!params || !mu_sd || !features || !out)) return SRW_E_ARG;
+    return srw::mlp_forward_impl(params, mu_sd, features, n, out, as_stream(stream));
+}
+
+int srw_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                       const float* mu_sd, const float* features, const float* target,
+                       int64_t n, float* grad, float* loss, void* stream)
+{
+    if (n < 0) return SRW_E_ARG;
+    if ((adam_m == nullptr) != (adam_v == nullptr)) return SRW_E_ARG;
+    if (adam_m && (step < 1 || !(lr > 0.0f) || !std::isfinite(lr))) return SRW_E_ARG;
+    if (n > 0 && (!params || !mu_sd || !features || !target)) return SRW_E_ARG;
+    return srw::mlp_train_impl(params, adam_m, adam_v, step, lr, mu_sd, features, target, n, grad,
+                               loss, as_stream(stream));
+}
+
+int srw_mlp_budgets(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi,
+                    int32_t* walks, void* stream)
+{
+    if (n < 0 || !(eps > 0.0) || !std::isfinite(eps) || lo < 1 || hi < lo || hi > 8192)
+        return SRW_E_ARG;
+    if (n > 0 && (!pred || !walks)) return SRW_E_ARG;
+    return srw::budgets_impl(pred, n, eps, lo, hi, walks, as_stream(stream));
 }
 
 const char* srw_status_string(int status)

@@ -41,6 +41,15 @@ struct srw_factor {
     // longest dependency chain of the triangular solves, -1 until srw_factor_depth
     int32_t depth = -1;
 
+    // batched build: nmat matrices stacked block-diagonally (0 = one matrix)
+    int32_t nmat = 0;
+    std::vector<int64_t> mat_off_host;  // [nmat+1] first stacked row of every matrix
+    int64_t* mat_off = nullptr;         // device copy
+    int32_t* node_mat = nullptr;        // [n] matrix of every stacked row
+    srw_csr Acat{0, 0, nullptr, nullptr, nullptr};  // the stacked matrix (owned)
+    int32_t batch_per_cu = 0;           // solve grid picked by the autotuner (0 = not yet)
+    float batch_apply_ms = -1.0f;       // its measured time for one application
+
     // kept on request (srw_options.keep)
     uint2* ent = nullptr;          // [nnz-n] {neighbour, threshold}
     uint32_t* mthr = nullptr;      // [nnz-n]
@@ -95,8 +104,17 @@ struct Arena {
     }
 };
 
+// Walk keys of a batched build: the matrix of every node of the block-diagonal
+// matrix, the first node of every matrix and the matrix's seed.
+struct BatchKeys {
+    const int32_t* node_mat;
+    const int64_t* mat_off;
+    const uint64_t* mat_seed;
+};
+
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
-                      const srw_options* opt, srw_factor** out, hipStream_t s);
+                      const srw_options* opt, srw_factor** out, hipStream_t s,
+                      const BatchKeys* batch = nullptr);
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
@@ -104,5 +122,20 @@ int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);
 // Dependency level of every slot of the plan (lev, caller-allocated [n]) and the depth.
 int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s);
 void free_factor(srw_factor* F);
+int ordering_impl(int64_t n, uint64_t seed, int32_t* rank, hipStream_t s);
+int build_batched_impl(int32_t nmat, const srw_csr* A, int32_t walks_per_row, double drop_tol,
+                       const uint64_t* seeds, const srw_options* opt, srw_factor** out,
+                       hipStream_t s);
+int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, int32_t max_iter,
+                     double* X, int32_t* iters, double* rel, int32_t use_graph, hipStream_t s);
+int features_impl(const srw_csr* A, const int32_t* rank, float* feat, hipStream_t s);
+int labels_impl(const srw_factor* F, int per_step, double* label, hipStream_t s);
+int mlp_forward_impl(const float* P, const float* musd, const float* feat, int64_t n, float* out,
+                     hipStream_t s);
+int mlp_train_impl(float* P, float* m, float* v, int32_t step, float lr, const float* musd,
+                   const float* feat, const float* target, int64_t n, float* grad, float* loss,
+                   hipStream_t s);
+int budgets_impl(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi, int32_t* walks,
+                 hipStream_t s);
 
 }  // namespace srw

@@ -227,7 +227,11 @@ __device__ __forceinline__ void wait_published(typename Bits<T>::U& bits, const 
     uint64_t miss = ballot(valid && bits == Bits<T>::sentinel);
     uint32_t spins = 0;
     while (miss != 0) {
-        if (++spins > SPIN_LIMIT) {
+        // give up at the limit, or at once when another wave already gave up (a failed
+        // solve then drains instead of waiting at every row)
+        const bool failed = (spins & 255u) == 255u &&
+                            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        if (++spins > SPIN_LIMIT || failed) {
             if (lane == 0) atomicOr(err, 1);
             if ((miss >> lane) & 1ull) bits = Bits<T>::nan_bits();
             break;

@@ -71,13 +71,28 @@ _lib.srw_walk_export.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.srw_pcg_solve.argtypes = [ctypes.POINTER(_Csr), _P, _P, _D, _I32, _P, ctypes.POINTER(_I32),
                                ctypes.POINTER(_D), _P]
 _lib.srw_apply.argtypes = [_P, _P, _P, _P]
+_lib.srw_ordering.argtypes = [_I64, _U64, _P, _P]
+_lib.srw_row_features.argtypes = [ctypes.POINTER(_Csr), _P, _P, _P]
+_lib.srw_budget_labels.argtypes = [_P, _I32, _P, _P]
+_lib.srw_mlp_forward.argtypes = [_P, _P, _P, _I64, _P, _P]
+_lib.srw_mlp_train_step.argtypes = [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _I64, _P, _P, _P]
+_lib.srw_mlp_budgets.argtypes = [_P, _I64, _D, _I32, _I32, _P, _P]
+_lib.srw_build_factor_batched.argtypes = [_I32, _P, _I32, _D, _P, ctypes.POINTER(_Options),
+                                          ctypes.POINTER(_P), _P]
+_lib.srw_batch_info.argtypes = [_P, ctypes.POINTER(_I32), _P]
+_lib.srw_pcg_solve_batched.argtypes = [_P, _I32, _P, _D, _I32, _P, _P, _P, _I32, _P]
 _lib.srw_status_string.argtypes = [ctypes.c_int]
 _lib.srw_status_string.restype = ctypes.c_char_p
 
 EXPORTED = ["srw_default_options", "srw_build_factor", "srw_factor_free", "srw_factor_info",
             "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
-            "srw_pcg_solve", "srw_apply", "srw_status_string"]
+            "srw_pcg_solve", "srw_apply", "srw_ordering", "srw_row_features", "srw_budget_labels",
+            "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_budgets", "srw_build_factor_batched",
+            "srw_batch_info", "srw_pcg_solve_batched", "srw_status_string"]
+
+MLP_PARAMS = 4801
+NUM_FEATURES = 8
 
 
 def status_string(status: int) -> str:
@@ -266,3 +281,119 @@ def apply(F: Factor, r: torch.Tensor, stream=None) -> torch.Tensor:
     st = _lib.srw_apply(F.handle, _ptr(r), _ptr(z), _stream(stream))
     _check(st, "srw_apply")
     return z
+
+
+# ------------------------------------------------------------ learned walk budgets
+def ordering(n: int, seed: int, device="cuda", stream=None) -> torch.Tensor:
+    """srw_ordering: the random ordering's rank of every node (int32[n])."""
+    rank = torch.empty(n, dtype=torch.int32, device=device)
+    _check(_lib.srw_ordering(int(n), int(seed) & (2**64 - 1), _ptr(rank), _stream(stream)),
+           "srw_ordering")
+    return rank
+
+
+def row_features(A: Matrix, rank: torch.Tensor, stream=None) -> torch.Tensor:
+    """srw_row_features: float32 [n, 8] per-row features."""
+    f = torch.empty((A.n, NUM_FEATURES), dtype=torch.float32, device=A.rowptr.device)
+    csr = A.c()
+    _check(_lib.srw_row_features(ctypes.byref(csr), _ptr(rank), _ptr(f), _stream(stream)),
+           "srw_row_features")
+    return f
+
+
+def budget_labels(F: Factor, per_step: bool = False, stream=None) -> torch.Tensor:
+    """srw_budget_labels: per-walk variance of each row (float64[n], NaN = no walks),
+    divided by the mean walk length with per_step; F must have been built with
+    keep >= 1."""
+    n = F.info()["n"]
+    out = torch.empty(n, dtype=torch.float64, device=F.device)
+    _check(_lib.srw_budget_labels(F.handle, 1 if per_step else 0, _ptr(out), _stream(stream)),
+           "srw_budget_labels")
+    return out
+
+
+def mlp_forward(params: torch.Tensor, mu_sd: torch.Tensor, features: torch.Tensor,
+                stream=None) -> torch.Tensor:
+    """srw_mlp_forward: predicted log label of every row (float32[n])."""
+    n = features.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=features.device)
+    _check(_lib.srw_mlp_forward(_ptr(params), _ptr(mu_sd), _ptr(features), int(n), _ptr(out),
+                                _stream(stream)), "srw_mlp_forward")
+    return out
+
+
+def mlp_train_step(params: torch.Tensor, mu_sd: torch.Tensor, features: torch.Tensor,
+                   target: torch.Tensor, *, adam_m=None, adam_v=None, step: int = 1,
+                   lr: float = 1e-3, grad=None, loss=None, stream=None) -> None:
+    """srw_mlp_train_step: gradient of the mean squared error on these rows into
+    `grad` / `loss` (if given) and, with adam_m / adam_v, one Adam update of params."""
+    n = features.shape[0]
+    _check(_lib.srw_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+                                   _ptr(mu_sd), _ptr(features), _ptr(target), int(n), _ptr(grad),
+                                   _ptr(loss), _stream(stream)), "srw_mlp_train_step")
+
+
+def mlp_budgets(pred: torch.Tensor, eps: float, lo: int, hi: int, stream=None) -> torch.Tensor:
+    """srw_mlp_budgets: walks per row = clamp(ceil(exp(pred) / eps), lo, hi)."""
+    walks = torch.empty(pred.shape[0], dtype=torch.int32, device=pred.device)
+    _check(_lib.srw_mlp_budgets(_ptr(pred), int(pred.shape[0]), float(eps), int(lo), int(hi),
+                                _ptr(walks), _stream(stream)), "srw_mlp_budgets")
+    return walks
+
+
+# ---------------------------------------------------------------- batched solves
+def build_factor_batched(mats, walks_per_row: int, drop_tol: float, seeds, *, walks=None,
+                         precision: str = "fp64", keep: int = 0, profile: bool = False,
+                         solve_order: int = 1, stream=None) -> Factor:
+    """srw_build_factor_batched: one factor for a list of Matrix objects stacked
+    block-diagonally (matrix i ordered and walked with seeds[i])."""
+    import numpy as np
+
+    arr = (_Csr * len(mats))(*[m.c() for m in mats])
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    opt = _Options()
+    _lib.srw_default_options(ctypes.byref(opt))
+    if walks is not None:
+        opt.walks = _ptr(walks).value
+    opt.factor_precision = FP32 if precision == "fp32" else FP64
+    opt.keep = int(keep)
+    opt.profile = 1 if profile else 0
+    opt.solve_order = int(solve_order)
+    h = ctypes.c_void_p(0)
+    st = _lib.srw_build_factor_batched(len(mats), arr, int(walks_per_row), float(drop_tol),
+                                       sd.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt),
+                                       ctypes.byref(h), _stream(stream))
+    _check(st, "srw_build_factor_batched")
+    return Factor(h.value, mats[0].rowptr.device)
+
+
+def batch_info(F: Factor):
+    """srw_batch_info: (nmat, row offsets as a list of nmat + 1 ints)."""
+    import numpy as np
+
+    nm = ctypes.c_int32(0)
+    _check(_lib.srw_batch_info(F.handle, ctypes.byref(nm), None), "srw_batch_info")
+    off = np.zeros(nm.value + 1, dtype=np.int64)
+    _check(_lib.srw_batch_info(F.handle, ctypes.byref(nm), off.ctypes.data_as(ctypes.c_void_p)),
+           "srw_batch_info")
+    return nm.value, off.tolist()
+
+
+def pcg_solve_batched(F: Factor, B: torch.Tensor, tol: float, max_iter: int = 10000, X=None,
+                      use_graph: bool = True, stream=None):
+    """srw_pcg_solve_batched over B [N, nrhs].  Returns (status, X, iters [nmat, nrhs],
+    rel_residual [nmat, nrhs]) with numpy arrays for the host outputs."""
+    import numpy as np
+
+    nmat, _ = batch_info(F)
+    nrhs = B.shape[1]
+    if X is None:
+        X = torch.empty_like(B)
+    it = np.zeros(nmat * nrhs, dtype=np.int32)
+    rel = np.zeros(nmat * nrhs, dtype=np.float64)
+    st = _lib.srw_pcg_solve_batched(F.handle, int(nrhs), _ptr(B), float(tol), int(max_iter),
+                                    _ptr(X), it.ctypes.data_as(ctypes.c_void_p),
+                                    rel.ctypes.data_as(ctypes.c_void_p), 1 if use_graph else 0,
+                                    _stream(stream))
+    _check(st, "srw_pcg_solve_batched")
+    return st, X, it.reshape(nmat, nrhs), rel.reshape(nmat, nrhs)

@@ -309,3 +309,40 @@ def config_rgg(n: int = 2_000_000, seed: int = 0, return_info=False):
     w = clip(1/dist, 1, 1e3), 0.5% grounded with excess ~ U[0.1, 10]."""
     return rgg(n, 24.0, ground_frac=0.005, excess=("uniform", 0.1, 10.0), w_clip=(1.0, 1e3),
                seed=seed, return_info=return_info)
+
+
+def pruned_grid(n_target: int, *, drop_frac=0.10, g=("uniform", 0.1, 10.0), ground_frac=0.02,
+                excess=("uniform", 0.1, 10.0), seed=0) -> CSR:
+    """2D grid of about n_target nodes (nx = round(sqrt(n)), ny = round(n / nx)) with
+    round(drop_frac * edges) edges removed uniformly among those outside a random
+    spanning tree (minimum spanning tree of i.i.d. uniform edge keys), so the graph
+    stays connected; conductances, grounded nodes and excess drawn as in `grid`."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import minimum_spanning_tree
+
+    rng = np.random.default_rng(seed)
+    nx = max(1, int(round(np.sqrt(n_target))))
+    ny = max(1, int(round(n_target / nx)))
+    n = nx * ny
+    eu, ev = grid_edges((nx, ny))
+    key = rng.random(eu.size) + 1.0  # positive keys: every edge is stored
+    T = minimum_spanning_tree(coo_matrix((key, (eu, ev)), shape=(n, n))).tocoo()
+    tree = np.minimum(T.row, T.col).astype(np.int64) * n + np.maximum(T.row, T.col)
+    in_tree = np.isin(eu * n + ev, tree)
+    cand = np.flatnonzero(~in_tree)
+    n_drop = min(int(round(drop_frac * eu.size)), cand.size)
+    drop = rng.choice(cand, size=n_drop, replace=False)
+    keep = np.ones(eu.size, dtype=bool)
+    keep[drop] = False
+    eu, ev = eu[keep], ev[keep]
+    gv = _draw(rng, g, eu.size)
+    exc = _ground(rng, n, ground_frac, 1, excess)
+    return assemble(n, eu, ev, gv, exc)
+
+
+def config_batch(count: int = 256, lo: float = 1e3, hi: float = 2e5, seed: int = 0):
+    """`count` pruned grids with sizes log-uniform on [lo, hi] (matrix i from seed
+    seed + i; the sizes from seed)."""
+    rng = np.random.default_rng([seed, 0xBA7C])
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), count))
+    return [pruned_grid(int(round(s)), seed=seed + i) for i, s in enumerate(sizes)]

@@ -43,3 +43,33 @@ def test_status_strings_and_argument_checks_without_gpu():
     assert lib.srw_build_factor(None, 64, ctypes.c_double(0.0), ctypes.c_uint64(0), None,
                                 ctypes.byref(out), None) == -1
     assert lib.srw_factor_info(None, None, None, None, None, None, None, None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsrw.so not built")
+def test_budget_entry_points_reject_bad_arguments_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    P, I64, I32, D, F = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_float
+    lib.srw_ordering.argtypes = [I64, ctypes.c_uint64, P, P]
+    lib.srw_mlp_budgets.argtypes = [P, I64, D, I32, I32, P, P]
+    lib.srw_mlp_train_step.argtypes = [P, P, P, I32, F, P, P, P, I64, P, P, P]
+    lib.srw_mlp_forward.argtypes = [P, P, P, I64, P, P]
+    lib.srw_budget_labels.argtypes = [P, I32, P, P]
+    lib.srw_row_features.argtypes = [P, P, P, P]
+    assert lib.srw_ordering(-1, 0, None, None) == -1
+    assert lib.srw_ordering(10, 0, None, None) == -1          # no output
+    assert lib.srw_ordering(0, 0, None, None) == 0            # empty: nothing to do
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its checks first
+    assert lib.srw_mlp_budgets(fake, 4, 0.0, 1, 8, fake, None) == -1   # eps <= 0
+    assert lib.srw_mlp_budgets(fake, 4, 0.1, 0, 8, fake, None) == -1   # lo < 1
+    assert lib.srw_mlp_budgets(fake, 4, 0.1, 9, 8, fake, None) == -1   # hi < lo
+    assert lib.srw_mlp_budgets(fake, 4, 0.1, 1, 9000, fake, None) == -1  # hi > 8192
+    assert lib.srw_mlp_budgets(None, 4, 0.1, 1, 8, fake, None) == -1
+    # Adam moments must come as a pair, with step >= 1 and lr > 0
+    assert lib.srw_mlp_train_step(fake, fake, None, 1, 1e-3, fake, fake, fake, 4, None, None, None) == -1
+    assert lib.srw_mlp_train_step(fake, fake, fake, 0, 1e-3, fake, fake, fake, 4, None, None, None) == -1
+    assert lib.srw_mlp_train_step(fake, fake, fake, 1, 0.0, fake, fake, fake, 4, None, None, None) == -1
+    assert lib.srw_mlp_train_step(fake, None, None, 1, 1e-3, fake, None, fake, 4, None, None, None) == -1
+    assert lib.srw_mlp_forward(fake, fake, fake, -1, fake, None) == -1
+    assert lib.srw_mlp_forward(fake, None, fake, 4, fake, None) == -1
+    assert lib.srw_budget_labels(None, 0, fake, None) == -1
+    assert lib.srw_row_features(None, fake, fake, None) == -1

@@ -1,0 +1,125 @@
+"""Batched builds and solves (through the C ABI).
+
+Bars: block i of a batched factor is bit-exact with the factor of matrix i built alone
+with its seed (same walks, same tallies, same arithmetic).  Batched PCG: every system's
+true residual meets the tolerance, its iteration count is within one of the
+single-system PCG on the same matrix and right-hand side (dot products are reduced in
+another order), and the graph-replayed and directly launched solves agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_math_0609672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def srw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_math_0609672_amd import srw as s
+    return s
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def batch_mats():
+    return [W.pruned_grid(n, seed=20 + i) for i, n in enumerate((1200, 300, 4100, 1, 2500))] + \
+           [W.random_graph(800, 2400, seed=3, ground_frac=0.02)]
+
+
+SEEDS = [11, 12, 13, 14, 15, 16]
+
+
+def export(srw, F, n, nnz, fp32=False):
+    dt = torch.float32 if fp32 else torch.float64
+    yptr = torch.empty(n + 1, dtype=torch.int64, device=DEV)
+    ycol = torch.empty(max(nnz, 1), dtype=torch.int32, device=DEV)
+    yval = torch.empty(max(nnz, 1), dtype=dt, device=DEV)
+    d = torch.empty(n, dtype=dt, device=DEV)
+    rank = torch.empty(n, dtype=torch.int32, device=DEV)
+    import ctypes
+    st = srw._lib.srw_factor_export(F.handle, srw._ptr(yptr), srw._ptr(ycol), srw._ptr(yval),
+                                    srw._ptr(d), srw._ptr(rank), srw._stream(None))
+    assert st == 0
+    torch.cuda.synchronize()
+    return np_(yptr), np_(ycol)[:nnz], np_(yval)[:nnz], np_(d), np_(rank)
+
+
+@pytest.mark.parametrize("precision,walks", [("fp64", 64), ("fp32", 19)])
+def test_batched_factor_equals_single_builds(srw, precision, walks):
+    mats = batch_mats()
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    F = srw.build_factor_batched(Ms, walks, 1e-3, SEEDS, precision=precision)
+    nmat, off = srw.batch_info(F)
+    assert nmat == len(mats) and off[-1] == sum(A.n for A in mats)
+    N = off[-1]
+    info = F.info()
+    yptr, ycol, yval, d, rank = export(srw, F, N, info["nnz_y"], precision == "fp32")
+    for i, (A, M) in enumerate(zip(mats, Ms)):
+        Fi = srw.build_factor(M, walks, 1e-3, SEEDS[i], precision=precision)
+        ii = Fi.info()
+        p1, c1, v1, d1, r1 = export(srw, Fi, A.n, ii["nnz_y"], precision == "fp32")
+        a, b = off[i], off[i + 1]
+        assert np.array_equal(yptr[a:b + 1] - yptr[a], p1)
+        assert np.array_equal(ycol[yptr[a]:yptr[b]] - a, c1)
+        assert np.array_equal(yval[yptr[a]:yptr[b]], v1)
+        assert np.array_equal(d[a:b], d1)
+        assert np.array_equal(rank[a:b] - a, r1)
+        Fi.free()
+    F.free()
+
+
+@pytest.mark.parametrize("nrhs", [8, 3])
+def test_batched_pcg(srw, nrhs):
+    mats = batch_mats()
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    F = srw.build_factor_batched(Ms, 64, 1e-3, SEEDS)
+    _, off = srw.batch_info(F)
+    N = off[-1]
+    rng = np.random.default_rng(nrhs)
+    Bh = rng.standard_normal((N, nrhs))
+    Bh[off[2]:off[3], 1] = 0.0  # one system with b = 0
+    B = torch.as_tensor(Bh, device=DEV)
+    st, X, it, rel = srw.pcg_solve_batched(F, B, 1e-8, 500, use_graph=True)
+    st2, X2, it2, rel2 = srw.pcg_solve_batched(F, B, 1e-8, 500, use_graph=False)
+    assert st == srw.OK and st2 == srw.OK
+    assert np.array_equal(np_(X), np_(X2)) and np.array_equal(it, it2)
+    Xh = np_(X)
+    for i, A in enumerate(mats):
+        S = A.to_scipy()
+        a, b = off[i], off[i + 1]
+        Fi = srw.build_factor(Ms[i], 64, 1e-3, SEEDS[i])
+        for j in range(nrhs):
+            bj = Bh[a:b, j]
+            xj = Xh[a:b, j]
+            if not np.any(bj):
+                assert it[i, j] == 0 and not np.any(xj) and rel[i, j] == 0.0
+                continue
+            true_rel = np.linalg.norm(bj - S @ xj) / np.linalg.norm(bj)
+            assert true_rel <= 1e-8 and abs(true_rel - rel[i, j]) <= 1e-12 + 1e-6 * true_rel
+            st1, x1, it1, rel1 = srw.pcg_solve(Ms[i], Fi, torch.as_tensor(bj, device=DEV), 1e-8, 500)
+            assert abs(int(it[i, j]) - it1) <= 1, (i, j, it[i, j], it1)
+        Fi.free()
+    F.free()
+
+
+def test_batched_rejects_given_ordering_and_bad_nrhs(srw):
+    mats = batch_mats()[:2]
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    F = srw.build_factor_batched(Ms, 16, 0.0, SEEDS[:2])
+    B = torch.zeros((sum(A.n for A in mats), 9), dtype=torch.float64, device=DEV)
+    with pytest.raises(srw.SrwError):
+        srw.pcg_solve_batched(F, B, 1e-8)
+    single = srw.build_factor(Ms[0], 16, 0.0, 1)
+    with pytest.raises(srw.SrwError):
+        srw.pcg_solve_batched(single, B[: mats[0].n, :2], 1e-8)
+    single.free()
+    F.free()

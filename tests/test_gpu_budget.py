@@ -1,0 +1,221 @@
+"""Parity of the learned walk-budget kernels (through the C ABI) with the allocator
+oracle (oracle/budget.py).
+
+Bars: ranks bit-exact.  Features: the oracle's float64 values rounded to float32, within
+one float32 ulp (the logarithms may differ in the last float64 bit).  Labels: 1e-12
+relative (both from bit-identical tallies; the H-list sum runs in another order).
+Network output: the oracle evaluates the same bfloat16-rounded operands exactly, the
+GPU accumulates in float32; with scale_k = sum_h |W3_h H2_kh| + |b3|, rows agree to
+1e-5 scale_k unless a hidden activation lies within float32 error of a bfloat16
+rounding midpoint and rounds the other way, which moves a row by at most 2^-7 scale_k;
+so >= 99% of rows meet 1e-5 and all rows 2^-7.  Gradients: relative L2 error <= 2e-3
+per tensor and loss 1e-4 (float32 sums over the batch, rare rounding flips).  Adam:
+the GPU step applied to its own gradient matches the oracle's step on that gradient
+to float32 rounding.  Budgets: equal, except where exp(pred) / eps lies within 1e-9
+of an integer (then within 1).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import budget as B
+from paper_math_0609672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def srw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_math_0609672_amd import srw as s
+    return s
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def flat(p: dict) -> np.ndarray:
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"], p["b3"]])
+
+
+def unflat(v: np.ndarray) -> dict:
+    v = np.asarray(v, dtype=np.float64)
+    o = 0
+    out = {}
+    for k, shape in (("W1", (8, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64,)),
+                     ("b3", (1,))):
+        size = int(np.prod(shape))
+        out[k] = v[o:o + size].reshape(shape).copy()
+        o += size
+    assert o == 4801
+    return out
+
+
+MATRICES = {
+    "grid3d_12": lambda: W.grid((12, 12, 12), g=("loguniform", 1e-2, 1e2), ground_frac=0.01,
+                                excess=("uniform", 0.01, 1.0), seed=3),
+    "random_3000": lambda: W.random_graph(3000, 9000, seed=7, ground_frac=0.01),
+    "rgg_2000": lambda: W.rgg(2000, 24.0, seed=4),
+}
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (17, 3), (5000, 12345), (300001, 2)])
+def test_ordering_bit_exact(srw, n, seed):
+    assert np.array_equal(np_(srw.ordering(n, seed, DEV)), O.rank(n, seed))
+
+
+@pytest.mark.parametrize("name", sorted(MATRICES))
+def test_features_match_oracle(srw, name):
+    A = MATRICES[name]()
+    M = srw.Matrix.from_host(A, DEV)
+    rank = srw.ordering(A.n, 11, DEV)
+    f = np_(srw.row_features(M, rank))
+    ref = B.features(A, O.rank(A.n, 11)).astype(np.float32)
+    ulp = np.spacing(np.abs(ref))
+    assert np.all(np.abs(f - ref) <= ulp), np.max(np.abs(f - ref) / ulp)
+
+
+@pytest.mark.parametrize("per_step", [False, True])
+@pytest.mark.parametrize("name,walks", [("grid3d_12", 64), ("random_3000", 37), ("rgg_2000", 16)])
+def test_labels_match_oracle(srw, name, walks, per_step):
+    A = MATRICES[name]()
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, 0.0, 5, keep=1)
+    lab = np_(srw.budget_labels(F, per_step=per_step))
+    Fo = O.build_factor(A, walks, 0.0, 5)
+    ref = B.labels(Fo.table.tau, Fo.tallies, per_step=per_step)
+    assert np.array_equal(np.isnan(lab), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.allclose(lab[ok], ref[ok], rtol=1e-12, atol=1e-300)
+    F.free()
+
+
+def random_net(seed):
+    rng = np.random.default_rng(seed)
+    p = B.init_params(seed)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.standard_normal(p[k].shape) * 0.2
+    # parameters as float32 values (what the device holds)
+    return unflat(flat(p).astype(np.float32).astype(np.float64))
+
+
+def random_inputs(n, seed):
+    rng = np.random.default_rng([seed, 1])
+    big = max(n, 4096)  # standardization statistics from a larger draw (n may be 1)
+    X = (rng.standard_normal((big, 8)) * rng.uniform(0.5, 3.0, 8) + rng.uniform(-2, 2, 8))
+    X = X.astype(np.float32)
+    mu = X.mean(axis=0).astype(np.float32)
+    sd = X.std(axis=0).astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    return np.ascontiguousarray(X[:n]), mu, sd, t
+
+
+def oracle_inputs(X, mu, sd):
+    # the GPU standardizes in float32 before rounding to bfloat16
+    return ((X - mu) / sd).astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1, 16, 1009, 20000])
+def test_mlp_forward_matches_oracle(srw, n):
+    p = random_net(2)
+    X, mu, sd, _ = random_inputs(n, 3)
+    P = torch.as_tensor(flat(p).astype(np.float32), device=DEV)
+    musd = torch.as_tensor(np.concatenate([mu, sd]), device=DEV)
+    y = np_(srw.mlp_forward(P, musd, torch.as_tensor(X, device=DEV)))
+    ref, cache = B.mlp_forward(p, oracle_inputs(X, mu, sd), round_bf16=True)
+    scale = np.abs(cache["h2"]) @ np.abs(cache["W3"]) + abs(p["b3"][0])
+    err = np.abs(y - ref) / scale
+    assert np.all(err <= 2.0 ** -7), err.max()
+    assert np.mean(err <= 1e-5) >= 0.99, np.mean(err <= 1e-5)
+
+
+@pytest.mark.parametrize("n", [16, 1009, 20000])
+def test_mlp_gradients_match_oracle(srw, n):
+    p = random_net(5)
+    X, mu, sd, t = random_inputs(n, 6)
+    P = torch.as_tensor(flat(p).astype(np.float32), device=DEV)
+    musd = torch.as_tensor(np.concatenate([mu, sd]), device=DEV)
+    grad = torch.empty(4801, dtype=torch.float32, device=DEV)
+    loss = torch.empty(1, dtype=torch.float32, device=DEV)
+    srw.mlp_train_step(P, musd, torch.as_tensor(X, device=DEV), torch.as_tensor(t, device=DEV),
+                       grad=grad, loss=loss)
+    torch.cuda.synchronize()
+    ref_loss, ref_g = B.loss_and_grads(p, oracle_inputs(X, mu, sd), t.astype(np.float64),
+                                       round_bf16=True)
+    assert abs(float(np_(loss)[0]) - ref_loss) <= 1e-4 * ref_loss
+    g = unflat(np_(grad))
+    for k in ref_g:
+        d = np.linalg.norm(g[k] - ref_g[k])
+        assert d <= 2e-3 * np.linalg.norm(ref_g[k]) + 1e-12, (k, d / np.linalg.norm(ref_g[k]))
+    # parameters untouched without Adam moments
+    assert np.array_equal(np_(P), flat(p).astype(np.float32))
+
+
+def test_adam_steps_match_oracle(srw):
+    p = random_net(8)
+    X, mu, sd, t = random_inputs(3000, 9)
+    P = torch.as_tensor(flat(p).astype(np.float32), device=DEV)
+    m = torch.zeros(4801, dtype=torch.float32, device=DEV)
+    v = torch.zeros(4801, dtype=torch.float32, device=DEV)
+    musd = torch.as_tensor(np.concatenate([mu, sd]), device=DEV)
+    Xd, td = torch.as_tensor(X, device=DEV), torch.as_tensor(t, device=DEV)
+    grad = torch.empty(4801, dtype=torch.float32, device=DEV)
+    st = B.adam_state(p)
+    q = {k: v_.copy() for k, v_ in p.items()}
+    lr = 1e-2
+    for step in (1, 2, 3):
+        before = np_(P).astype(np.float64)
+        srw.mlp_train_step(P, musd, Xd, td, adam_m=m, adam_v=v, step=step, lr=lr, grad=grad)
+        torch.cuda.synchronize()
+        B.adam_step(q, unflat(np_(grad)), st, lr=lr)
+        after = np_(P).astype(np.float64)
+        ref = flat(q)
+        tol = 3e-5 * lr + 2.0 ** -23 * np.abs(before) * 2  # float32 bias corrections: ~1e-5 relative
+        assert np.all(np.abs(after - ref) <= tol), np.max(np.abs(after - ref) - tol)
+        q = unflat(after)  # continue from the device's float32 parameters
+
+
+def test_budgets_match_oracle(srw):
+    rng = np.random.default_rng(4)
+    pred = rng.uniform(-8, 6, 5001).astype(np.float32)
+    pred[:3] = [np.nan, 50.0, -50.0]
+    walks = np_(srw.mlp_budgets(torch.as_tensor(pred, device=DEV), 0.01, 4, 4096))
+    p64 = pred.astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        ref = B.budgets(np.nan_to_num(p64, nan=-np.inf), np.ones(pred.size), 0.01, 4, 4096)
+    q = np.exp(p64) / 0.01
+    near = np.abs(q - np.round(q)) <= 1e-9 * np.maximum(q, 1)
+    assert walks[0] == 4 and walks[1] == 4096 and walks[2] == 4
+    assert np.all((walks == ref) | (near & (np.abs(walks - ref) <= 1)))
+
+
+def test_training_pipeline(srw):
+    """Pilot labels -> features -> training on the GPU -> budgets -> a factor that
+    PCG converges with (small grids of the evaluation family)."""
+    from paper_math_0609672_amd import budget as LB
+    Xs, ys = [], []
+    for seed in (1, 2):
+        A = W.config_grid3d(16, seed)
+        X, y = LB.pilot_rows(srw.Matrix.from_host(A, DEV), seed, 64, 1e-4)
+        Xs.append(X)
+        ys.append(y)
+    X, y = torch.cat(Xs), torch.cat(ys)
+    model = LB.fit(X, y, epochs=20, batch=2048, lr=3e-3, log_every=1)
+    losses = [l for _, l in model.history]
+    var = float(y.var())
+    assert losses[-1] < 0.8 * var, (losses[0], losses[-1], var)
+    A = W.config_grid3d(16, 0)
+    M = srw.Matrix.from_host(A, DEV)
+    walks = LB.budgets(model, M, 0, eps=0.01, lo=8, hi=4096)
+    assert int(walks.min()) >= 8 and int(walks.max()) <= 4096
+    F = srw.build_factor(M, 64, 1e-4, 0, walks=walks)
+    b = torch.as_tensor(W.rhs(A.n, seed=0), device=DEV)
+    st, x, it, rel = srw.pcg_solve(M, F, b, 1e-8, 1000)
+    assert st == srw.OK and rel <= 1e-8
+    F.free()

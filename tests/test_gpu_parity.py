@@ -299,3 +299,11 @@ def test_given_ordering_matches_oracle(srw):
     got = {k: np_(v) for k, v in F.export().items()}
     assert np.array_equal(got["rank"], rk)
     assert np.array_equal(got["yval"], ref.yval) and np.array_equal(got["d"], ref.d)
+
+
+def test_maximum_budget_row(srw):
+    # a row with the largest accepted budget (8192 walks: the tally's 64 KiB of LDS)
+    A = W.config_grid2d_32(1)
+    budget = np.full(A.n, 5, dtype=np.int32)
+    budget[[0, 17, 600]] = [8192, 4097, 8191]
+    compare_walks(srw, A, 5, 3, budget=budget)

@@ -157,3 +157,22 @@ def test_budgets():
     tau = np.array([0.1, 0.2, 0.3, 0.4, 0.0])
     m = B.budgets(pred, tau, eps=0.01, lo=8, hi=4096)
     assert m.tolist() == [50, 100, 3001, 4096, 0]
+
+
+def test_label_per_step_and_allocation_optimum():
+    # per-step label = label / (steps / M)
+    v = B.label(0.5, 1000, 1500, 2900, [300, 200])
+    assert B.label(0.5, 1000, 1500, 2900, [300, 200], steps=40000) == pytest.approx(v / 40.0, rel=1e-15)
+    # M_k ~ sqrt(V_k / L_k) minimises sum V/M at fixed sum M L: any feasible perturbation
+    # of the optimum raises the objective
+    rng = np.random.default_rng(2)
+    V, L = rng.uniform(0.1, 10, 50), rng.uniform(1, 100, 50)
+    budget = 1e5
+    M = np.sqrt(V / L)
+    M *= budget / np.sum(M * L)
+    f0 = np.sum(V / M)
+    for _ in range(200):
+        d = rng.standard_normal(50) * 0.05 * M
+        d -= L * (np.sum(d * L) / np.sum(L * L))  # keep the step budget
+        if np.all(M + d > 0):
+            assert np.sum(V / (M + d)) >= f0 * (1 - 1e-12)

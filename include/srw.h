@@ -297,6 +297,10 @@ int srw_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step
 int srw_mlp_budgets(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi,
                     int32_t* walks, void* stream);
 
+/* The calling thread's last recorded failure: the failing step and HIP error name
+ * (thread-local storage, valid until the thread's next failing call; "" if none). */
+const char* srw_last_error(void);
+
 /* Human-readable name of a status code (static storage). */
 const char* srw_status_string(int status);
 

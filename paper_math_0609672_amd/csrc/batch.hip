@@ -12,6 +12,7 @@
 // in order.  A system's scalars (rho, alpha, ...) live on the device; a system stops
 // moving once its recurrence residual meets the tolerance.
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 
@@ -248,6 +249,11 @@ __global__ void k_zero_d(int64_t n, double* __restrict__ a)
 
 __global__ void k_zero_i(int* a) { *a = 0; }
 
+__global__ void k_zero_n(int* a, int n)
+{
+    if ((int)threadIdx.x < n) a[threadIdx.x] = 0;
+}
+
 // --------------------------------------------------- multi right-hand-side solves
 // The substitutions of solve.hip with nrhs values per slot, stored [slot][nrhs]: a
 // row's values are published by lane 0 with one device-scope store each, every value
@@ -336,7 +342,24 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs,
                 const bool failed = (spins & 255u) == 255u &&
                                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
                 if (++spins > SPIN_LIMIT || failed) {
-                    if (lane == 0) atomicOr(err, 1);
+                    // the slot this wave waited for (every lane takes part in the max)
+                    const bool mine_d = (miss >> lane) & 1ull;
+                    const int key_d = wave_max_i(mine_d ? (FWD ? c : -c) : INT_MIN);
+                    const int32_t lead_d = FWD ? key_d : -key_d;
+                    if (lane == 0) {
+                        atomicOr(err, 1);
+                        // the first wave to reach the limit records where it waited:
+                        // err[2..6] = direction, slot, awaited slot, awaited value still
+                        // absent, waves in the grid
+                        if (!failed && atomicCAS(err + 1, 0, 1) == 0) {
+                            err[2] = FWD ? 1 : 0;
+                            err[3] = (int)s;
+                            err[4] = lead_d;
+                            err[5] = mload((const U*)sol + (int64_t)lead_d * nrhs + (nrhs - 1)) ==
+                                     MBits<T>::sentinel;
+                            err[6] = (int)nw;
+                        }
+                    }
 #pragma unroll
                     for (int j = 0; j < MAXR; ++j)
                         if (bits[j] == MBits<T>::sentinel) bits[j] = MBits<T>::nan_bits();
@@ -471,9 +494,12 @@ struct BatchWork {
     int64_t* mat_tile = nullptr;
 };
 
+// Ordinary (stream-ordered) launch of a grid that fits on the chip at once:
+// occupancy x CUs blocks, capped per CU by the autotuner.  Nothing else runs on the
+// device between this launch's neighbours on the stream, so every block is resident;
+// should one not be, the waits time out, drain, and the solve reports the failure.
 template <typename K>
-hipError_t resident_launch(K kernel, int64_t rows, int per_cu_cap, void** args, hipStream_t s,
-                           bool cooperative)
+hipError_t resident_launch(K kernel, int64_t rows, int per_cu_cap, void** args, hipStream_t s)
 {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -484,13 +510,11 @@ hipError_t resident_launch(K kernel, int64_t rows, int per_cu_cap, void** args, 
     int64_t blocks = (int64_t)cus * std::max(1, per_cu);
     blocks = std::min<int64_t>(blocks, (rows + BLOCK / 64 - 1) / (BLOCK / 64));
     if (blocks < 1) blocks = 1;
-    if (cooperative)
-        return hipLaunchCooperativeKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK), args, 0, s);
     return hipLaunchKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK), args, 0, s);
 }
 
 template <typename T>
-hipError_t batch_apply(const srw_factor* F, BatchWork& W, bool cooperative, hipStream_t s)
+hipError_t batch_apply(const srw_factor* F, BatchWork& W, hipStream_t s)
 {
     int64_t n = F->n;
     int nrhs = W.nrhs;
@@ -512,7 +536,7 @@ hipError_t batch_apply(const srw_factor* F, BatchWork& W, bool cooperative, hipS
         double* out = nullptr;
         int* err = W.err;
         void* args[] = {&n, &nrhs, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err};
-        e = resident_launch(k_trsv_multi<T, false>, n, F->batch_per_cu, args, s, cooperative);
+        e = resident_launch(k_trsv_multi<T, false>, n, F->batch_per_cu, args, s);
         if (e != hipSuccess) return e;
     }
     {
@@ -527,22 +551,20 @@ hipError_t batch_apply(const srw_factor* F, BatchWork& W, bool cooperative, hipS
         double* out = W.z;
         int* err = W.err;
         void* args[] = {&n, &nrhs, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err};
-        e = resident_launch(k_trsv_multi<T, true>, n, F->batch_per_cu, args, s, cooperative);
+        e = resident_launch(k_trsv_multi<T, true>, n, F->batch_per_cu, args, s);
     }
     return e;
 }
 
-hipError_t apply_b(const srw_factor* F, BatchWork& W, bool cooperative, hipStream_t s)
+hipError_t apply_b(const srw_factor* F, BatchWork& W, hipStream_t s)
 {
-    return F->precision == SRW_FP32 ? batch_apply<float>(F, W, cooperative, s)
-                                    : batch_apply<double>(F, W, cooperative, s);
+    return F->precision == SRW_FP32 ? batch_apply<float>(F, W, s) : batch_apply<double>(F, W, s);
 }
 
 // z = M^{-1} r, then rho / p for the active systems (restart = 1: p = z)
-hipError_t iteration(const srw_factor* F, BatchWork& W, const double* x_dummy, double* X,
-                     double tol, int32_t max_iter, bool cooperative, hipStream_t s)
+hipError_t iteration(const srw_factor* F, BatchWork& W, double* X, double tol, int32_t max_iter,
+                     hipStream_t s)
 {
-    (void)x_dummy;
     const srw_csr& A = F->Acat;
     const int nrhs = W.nrhs;
     const int sg = (int)((W.nsys + 255) / 256);
@@ -556,7 +578,7 @@ hipError_t iteration(const srw_factor* F, BatchWork& W, const double* x_dummy, d
                                                       W.q, X, W.r, W.sys, W.partials);
     k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_RR, tol, max_iter, W.active);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = apply_b(F, W, cooperative, s)) != hipSuccess) return e;
+    if ((e = apply_b(F, W, s)) != hipSuccess) return e;
     k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.r,
                                                       W.z, nullptr, nullptr, W.sys, W.partials);
     k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_BETA, tol, max_iter, W.active);
@@ -615,27 +637,34 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     Sys* host_sys = nullptr;
     int* host_flag = nullptr;
     hipError_t e = hipHostMalloc((void**)&host_sys, std::max<int64_t>(W.nsys, 1) * sizeof(Sys), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&host_flag, 2 * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&host_flag, 16 * sizeof(int), hipHostMallocDefault);
+    if (host_flag) std::memset(host_flag, 0, 16 * sizeof(int));
+    int tuning_cap = 0;  // cap being timed when a solve failed (0: not while tuning)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const int sg = (int)((W.nsys + 255) / 256);
     const srw_csr& A = F->Acat;
     auto sync_flags = [&]() -> hipError_t {
-        hipError_t ee = hipMemcpyAsync(host_flag, W.active, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+        hipError_t ee = hipMemcpyAsync(host_flag, W.active, 8 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (ee == hipSuccess) ee = hipStreamSynchronize(s);
         return ee;
     };
     int status = SRW_OK;
-#define CK(call)                          \
-    do {                                  \
-        if (e == hipSuccess) e = (call);  \
-        if (e == hipSuccess) e = hipGetLastError(); \
+    const char* where = "batched pcg";
+    char diag[200] = "";
+#define CK(call)                                    \
+    do {                                            \
+        if (e == hipSuccess) {                      \
+            e = (call);                             \
+            if (e == hipSuccess) e = hipGetLastError(); \
+            if (e != hipSuccess) where = #call;     \
+        }                                           \
     } while (0)
     CK(hipMemcpyAsync(d_tmat, tmat.data(), W.ntile * 4, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(d_trow, trow.data(), (W.ntile + 1) * 8, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(W.mat_tile, mtile.data(), (F->nmat + 1) * 8, hipMemcpyHostToDevice, s));
     if (e == hipSuccess) {
-        k_zero_i<<<1, 1, 0, s>>>(W.err);
+        k_zero_n<<<1, 64, 0, s>>>(W.err, 8);
         k_zero_d<<<fill_grid(nv), BLOCK, 0, s>>>(nv, X);
         k_copy_d<<<fill_grid(nv), BLOCK, 0, s>>>(nv, B, W.r);
         k_tile<T_BB><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, B,
@@ -653,11 +682,16 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         for (int cap : {8, 4, 2}) {
             if (e != hipSuccess) break;
             F->batch_per_cu = cap;
-            CK(apply_b(F, W, true, s));  // warm
+            CK(apply_b(F, W, s));  // warm
             CK(hipEventRecord(e0, s));
-            CK(apply_b(F, W, true, s));
+            CK(apply_b(F, W, s));
             CK(hipEventRecord(e1, s));
             CK(hipEventSynchronize(e1));
+            CK(sync_flags());
+            if (e == hipSuccess && host_flag[1] != 0) {
+                tuning_cap = cap;
+                break;
+            }
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess && ms < best) {
@@ -670,9 +704,13 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         F->batch_per_cu = best_cap;
         F->batch_apply_ms = best;
     }
+    // a solve that failed while tuning stops the call (reported below; the next call
+    // tunes again)
+    const bool stop = host_flag[1] != 0;
+    if (stop) F->batch_per_cu = 0;
     // z = M^{-1} r, p = z, rho = r . z
-    CK(apply_b(F, W, true, s));
-    if (e == hipSuccess) {
+    if (!stop) CK(apply_b(F, W, s));
+    if (e == hipSuccess && !stop) {
         k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 1);
         k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.r,
                                                           W.z, nullptr, nullptr, W.sys, W.partials);
@@ -684,22 +722,22 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     // captured on a private stream (the caller's may be the null stream, which cannot
     // be captured) and replayed on the caller's stream
     hipStream_t cs = nullptr;
-    if (e == hipSuccess && use_graph) {
+    if (e == hipSuccess && use_graph && !stop) {
         CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         if (e == hipSuccess) {
-            hipError_t ce = iteration(F, W, nullptr, X, tol, max_iter, false, cs);
+            hipError_t ce = iteration(F, W, X, tol, max_iter, cs);
             hipError_t ee = hipStreamEndCapture(cs, &graph);
             e = ce != hipSuccess ? ce : ee;
         }
         CK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
-    for (int outer = 0; e == hipSuccess && outer < 4; ++outer) {
+    for (int outer = 0; e == hipSuccess && !stop && outer < 4; ++outer) {
         int done_iters = 0;
         while (e == hipSuccess && done_iters < max_iter) {
             for (int k = 0; k < CHUNK && e == hipSuccess; ++k) {
                 if (use_graph) e = hipGraphLaunch(exec, s);
-                else e = iteration(F, W, nullptr, X, tol, max_iter, true, s);
+                else e = iteration(F, W, X, tol, max_iter, s);
             }
             done_iters += CHUNK;
             if (e == hipSuccess) e = sync_flags();
@@ -715,7 +753,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         e = hipGetLastError();
         if (e == hipSuccess) e = sync_flags();
         if (e != hipSuccess || host_flag[0] == 0) break;
-        CK(apply_b(F, W, true, s));
+        CK(apply_b(F, W, s));
         if (e == hipSuccess) {
             k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 1);
             k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr,
@@ -727,7 +765,18 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     CK(hipMemcpyAsync(host_sys, W.sys, W.nsys * sizeof(Sys), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     if (e == hipSuccess) {
-        if (host_flag[1] != 0) e = hipErrorLaunchFailure;  // a triangular solve gave up
+        if (host_flag[1] != 0) {
+            e = hipErrorLaunchFailure;  // a triangular solve gave up
+            // host_flag[1 + i] = err[i]
+            std::snprintf(diag, sizeof(diag),
+                          "batched %s solve gave up waiting: slot %d for slot %d (value %s), "
+                          "%d waves, cap %d%s",
+                          host_flag[3] ? "forward" : "backward", host_flag[4], host_flag[5],
+                          host_flag[6] ? "absent" : "present", host_flag[7],
+                          tuning_cap ? tuning_cap : F->batch_per_cu,
+                          tuning_cap ? " (while tuning)" : "");
+            where = diag;
+        }
         bool all = true;
         for (int64_t i = 0; i < W.nsys; ++i) {
             const Sys& S = host_sys[i];
@@ -746,7 +795,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     (void)hipStreamSynchronize(s);
     if (host_sys) (void)hipHostFree(host_sys);
     if (host_flag) (void)hipHostFree(host_flag);
-    if (e != hipSuccess) return hip_fail(e, "batched pcg");
+    if (e != hipSuccess) return hip_fail(e, where);
     return status;
 }
 

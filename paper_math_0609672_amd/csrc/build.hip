@@ -13,6 +13,7 @@
 //   plan          Y^T by a stable radix sort of the entries on (column, source rank);
 //                 the rows of Y and Y^T relabelled by solve slot (rank or level order)
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 
@@ -545,9 +546,34 @@ int map_err(int e)
 
 }  // namespace
 
+namespace {
+thread_local char last_error[256] = "";
+}
+
+void set_last_error(const char* msg)
+{
+    std::snprintf(last_error, sizeof(last_error), "%s", msg ? msg : "");
+}
+
+const char* get_last_error() { return last_error; }
+
+void retain_pool_memory()
+{
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+        uint64_t keep_all = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep_all);
+    }
+    done[dev] = true;
+}
+
 int hip_fail(hipError_t e, const char* what)
 {
-    (void)what;
+    std::snprintf(last_error, sizeof(last_error), "%s: %s", what ? what : "HIP call",
+                  hipGetErrorName(e));
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SRW_E_NOMEM;
     return SRW_E_HIP;
 }
@@ -611,7 +637,10 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
     F->precision = opt.factor_precision;
     F->keep = opt.keep;
     Arena keep;  // blocks that end up owned by F
-    Arena tmp;   // build temporaries
+    Arena tmp;   // build temporaries, from the stream-ordered pool
+    retain_pool_memory();
+    tmp.pooled = true;
+    tmp.stream = s;
     int64_t* pinned = nullptr;
     int status = SRW_OK;
     const bool fp32 = opt.factor_precision == SRW_FP32;

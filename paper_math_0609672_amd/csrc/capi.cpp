@@ -340,6 +340,8 @@ int srw_mlp_budgets(const float* pred, int64_t n, double eps, int32_t lo, int32_
     return srw::budgets_impl(pred, n, eps, lo, hi, walks, as_stream(stream));
 }
 
+const char* srw_last_error(void) { return srw::get_last_error(); }
+
 const char* srw_status_string(int status)
 {
     switch (status) {

@@ -17,7 +17,11 @@
 
 namespace srw {
 
+// Records "what: <HIP error name>" as the calling thread's last error; returns
+// SRW_E_NOMEM for allocation failures, SRW_E_HIP otherwise.
 int hip_fail(hipError_t e, const char* what);
+void set_last_error(const char* msg);
+const char* get_last_error();
 
 // Ground and step-limit markers in walk records / end-node lists.
 constexpr uint32_t END_GROUND = 0xFFFFFFFFu;

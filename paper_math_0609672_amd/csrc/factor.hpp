@@ -80,16 +80,20 @@ struct srw_factor {
 
 namespace srw {
 
-// Device allocation tracked by an owner list (freed together).
+// Device allocation tracked by an owner list (freed together).  With a stream the
+// blocks come from the stream-ordered pool (hipMallocAsync / hipFreeAsync), so the
+// temporaries of repeated builds reuse pooled memory instead of being mapped anew.
 struct Arena {
     std::vector<void*> blocks;
     hipError_t last = hipSuccess;
+    hipStream_t stream = nullptr;
+    bool pooled = false;
     template <typename T>
     T* alloc(size_t count)
     {
         void* p = nullptr;
-        const size_t bytes = count ? count * sizeof(T) : sizeof(T);
-        hipError_t e = hipMalloc(&p, (bytes + 255) & ~(size_t)255);
+        const size_t bytes = (((count ? count * sizeof(T) : sizeof(T)) + 255) & ~(size_t)255);
+        hipError_t e = pooled ? hipMallocAsync(&p, bytes, stream) : hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             last = e;
             return nullptr;
@@ -99,10 +103,14 @@ struct Arena {
     }
     void release()
     {
-        for (void* p : blocks) (void)hipFree(p);
+        for (void* p : blocks) (void)(pooled ? hipFreeAsync(p, stream) : hipFree(p));
         blocks.clear();
     }
 };
+
+// Keeps freed stream-ordered allocations in the device's default pool (release
+// threshold raised once per device), so they are reused by the next build.
+void retain_pool_memory();
 
 // Walk keys of a batched build: the matrix of every node of the block-diagonal
 // matrix, the first node of every matrix and the matrix's seed.

@@ -511,6 +511,7 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
         return hip_fail(herr, "hipHostMalloc");
     }
     int status = SRW_NOT_CONVERGED;
+    bool gave_up = false;
     int32_t it = 0;
     double rel = 0.0;
     hipError_t e = hipSuccess;
@@ -562,6 +563,7 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
             if ((e = read_scalar(S_RR, &rr)) != hipSuccess) goto out;
             if (!std::isfinite(rr) || solve_failed()) {
                 e = hipErrorLaunchFailure;  // a triangular solve gave up waiting
+                gave_up = true;
                 goto out;
             }
             if (std::sqrt(rr) <= tol * bnorm) {
@@ -601,6 +603,10 @@ out:
     (void)hipFreeAsync(ws, s);
     (void)hipStreamSynchronize(s);
     (void)hipHostFree(host);
+    if (gave_up) {
+        set_last_error("pcg: a triangular solve gave up waiting, or the residual is not finite");
+        return SRW_E_HIP;
+    }
     if (e != hipSuccess) return hip_fail(e, "pcg");
     if (iters_out) *iters_out = it;
     if (rel_out) *rel_out = rel;

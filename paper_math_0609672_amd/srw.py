@@ -22,9 +22,11 @@ FP64, FP32 = 0, 1
 
 
 class SrwError(RuntimeError):
-    def __init__(self, status: int, what: str):
+    def __init__(self, status: int, what: str, detail: str = ""):
         self.status = status
-        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.detail = detail
+        msg = f"{what}: {status_string(status)} ({status})"
+        super().__init__(msg + (f" [{detail}]" if detail else ""))
 
 
 class _Csr(ctypes.Structure):
@@ -81,6 +83,8 @@ _lib.srw_build_factor_batched.argtypes = [_I32, _P, _I32, _D, _P, ctypes.POINTER
                                           ctypes.POINTER(_P), _P]
 _lib.srw_batch_info.argtypes = [_P, ctypes.POINTER(_I32), _P]
 _lib.srw_pcg_solve_batched.argtypes = [_P, _I32, _P, _D, _I32, _P, _P, _P, _I32, _P]
+_lib.srw_last_error.argtypes = []
+_lib.srw_last_error.restype = ctypes.c_char_p
 _lib.srw_status_string.argtypes = [ctypes.c_int]
 _lib.srw_status_string.restype = ctypes.c_char_p
 
@@ -89,7 +93,7 @@ EXPORTED = ["srw_default_options", "srw_build_factor", "srw_factor_free", "srw_f
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
             "srw_pcg_solve", "srw_apply", "srw_ordering", "srw_row_features", "srw_budget_labels",
             "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_budgets", "srw_build_factor_batched",
-            "srw_batch_info", "srw_pcg_solve_batched", "srw_status_string"]
+            "srw_batch_info", "srw_pcg_solve_batched", "srw_last_error", "srw_status_string"]
 
 MLP_PARAMS = 4801
 NUM_FEATURES = 8
@@ -228,9 +232,14 @@ class Factor:
         return out
 
 
+def last_error() -> str:
+    """srw_last_error: the calling thread's last recorded failure."""
+    return _lib.srw_last_error().decode()
+
+
 def _check(st: int, what: str):
     if st < 0:
-        raise SrwError(st, what)
+        raise SrwError(st, what, last_error() if st in (-5, -6) else "")
 
 
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,

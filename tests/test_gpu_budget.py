@@ -219,3 +219,40 @@ def test_training_pipeline(srw):
     st, x, it, rel = srw.pcg_solve(M, F, b, 1e-8, 1000)
     assert st == srw.OK and rel <= 1e-8
     F.free()
+
+
+def test_learned_budgets_replace_the_pilot(srw):
+    """What the trained network gains: budgets for an unseen matrix without a pilot
+    factor.  They reach the same PCG iteration count (within 2) as the allocation from
+    the matrix's own measured labels at the same eps, and reach the tolerance with fewer
+    walk steps than the uniform 256 walks per row."""
+    from paper_math_0609672_amd import budget as LB
+    Xs, ys = [], []
+    for seed in (1, 2, 3):
+        A = W.config_grid3d(20, seed)
+        X, y = LB.pilot_rows(srw.Matrix.from_host(A, DEV), seed, 256, 1e-4, rule="equal")
+        Xs.append(X)
+        ys.append(y)
+    model = LB.fit(torch.cat(Xs), torch.cat(ys), epochs=40, batch=4096, lr=3e-3)
+    A = W.config_grid3d(20, 0)
+    M = srw.Matrix.from_host(A, DEV)
+    b = torch.as_tensor(W.rhs(A.n, seed=0), device=DEV)
+
+    def solve(walks=None):
+        F = srw.build_factor(M, 256, 1e-4, 0, walks=walks)
+        st, _, it, rel = srw.pcg_solve(M, F, b, 1e-8, 1000)
+        steps = F.stats()["walk_steps"]
+        F.free()
+        assert st == srw.OK and rel <= 1e-8
+        return it, steps
+
+    it_u, steps_u = solve()
+    F = srw.build_factor(M, 256, 1e-4, 0, keep=1)
+    lab = srw.budget_labels(F)
+    F.free()
+    eps = 0.01
+    label_walks = torch.clamp(torch.ceil(torch.nan_to_num(lab, nan=1.0) / eps), 8, 8192).to(torch.int32)
+    it_l, steps_l = solve(label_walks)
+    it_n, steps_n = solve(LB.budgets(model, M, 0, eps, lo=8, hi=8192))
+    assert abs(it_n - it_l) <= 2, (it_n, it_l)
+    assert steps_n < steps_u, (steps_n, steps_u)

@@ -13,6 +13,7 @@ drop (Section 4), then PCG (Section 6).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -267,3 +268,49 @@ def pcg(A, F: Factor | None, b: np.ndarray, tol: float, max_iter: int = 10000):
                         _p(_c(A.val, np.float64)), *y, _p(bb), float(tol), int(max_iter),
                         _p(x), ctypes.byref(iters), ctypes.byref(rel))
     return int(st), x[:n], int(iters.value), float(rel.value)
+
+
+# ---------------------------------------------------------- Section 5.1 stopping rule
+def length_criterion(S1: int, S2: int, M: int, delta: float, z: float) -> bool:
+    """Section 5.1: the relative error of the mean walk length is below delta with
+    confidence alpha, tested as delta * mean * sqrt(M) / sigma > z with z the standard
+    normal quantile Q^{-1}((1 - alpha) / 2).  S1, S2: sums of the first M lengths and
+    of their squares; sigma the sample standard deviation (a zero sigma passes)."""
+    mean = float(S1) / M
+    var = (float(S2) - M * mean * mean) / (M - 1)
+    if not var > 0.0:
+        return True
+    return delta * mean * math.sqrt(M) / math.sqrt(var) > z
+
+
+def adaptive_budgets(A, rk, tb: Table, seed: int, delta: float, z: float, min_walks: int = 20,
+                     max_walks: int = 8192) -> np.ndarray:
+    """Walks per row by the Section 5.1 rule: walks run from row k one after another
+    (walk w keyed as always by (row, w, step)) until the first M >= min_walks whose
+    lengths satisfy `length_criterion`, or max_walks.  Rows with tau = 0 run none.
+    The lengths come from walk_rows, which reruns walks 0 .. target-1 with a doubling
+    target, so the first satisfying prefix is found exactly."""
+    out = np.zeros(A.n, np.int32)
+    for k in range(A.n):
+        if tb.tau[k] <= 0.0:
+            continue
+        target = min_walks
+        while True:
+            wk = walk_rows(A, rk, tb, seed, np.array([k]), target)
+            L = wk.length.astype(np.int64)
+            S1 = S2 = 0
+            found = 0
+            for M in range(1, target + 1):
+                S1 += int(L[M - 1])
+                S2 += int(L[M - 1]) ** 2
+                if M >= min_walks and length_criterion(S1, S2, M, delta, z):
+                    found = M
+                    break
+            if found:
+                out[k] = found
+                break
+            if target >= max_walks:
+                out[k] = max_walks
+                break
+            target = min(2 * target, max_walks)
+    return out

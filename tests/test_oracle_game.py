@@ -259,3 +259,39 @@ def test_single_node_and_all_grounded():
     assert F.yptr[-1] == 0 and F.d[0] == 2.5
     st, x, it, rr = O.pcg(A, F, np.array([5.0]), 1e-12)
     assert st == 0 and it == 1 and x[0] == 2.0
+
+
+def test_length_criterion_against_its_statement():
+    # delta * mean * sqrt(M) / sigma > z, sigma the sample standard deviation
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        L = rng.integers(2, 50, rng.integers(2, 60))
+        M = L.size
+        mean, sd = L.mean(), L.std(ddof=1)
+        delta, z = rng.uniform(0.01, 0.5), rng.uniform(1.0, 3.0)
+        expect = True if sd == 0 else delta * mean * np.sqrt(M) / sd > z
+        assert O.length_criterion(int(L.sum()), int((L * L).sum()), M, delta, z) == expect
+    assert O.length_criterion(5 * 20, 25 * 20, 20, 0.01, 3.0)  # equal lengths pass
+
+
+def test_adaptive_budgets_match_the_exact_length_variance():
+    """Section 5.1 on a two-node game: the walk length from node 0 has exact mean and
+    variance from the absorbing chain; the first M with delta*mean*sqrt(M)/sigma > z
+    concentrates near M* = z^2 var / (delta mean)^2."""
+    g, e0, e1 = 1.0, 0.05, 0.02
+    A = W.assemble(2, np.array([0]), np.array([1]), np.array([g]), np.array([e0, e1]))
+    a = np.array([g + e0, g + e1])
+    # walks from node 0 (rank 0): first step to node 1, then node 1 -> ground w.p.
+    # e1/a1 or -> node 0 (stay, the walk continues), node 0 -> ground w.p. e0/a0
+    P = np.array([[0.0, g / a[0]], [g / a[1], 0.0]])
+    N = np.linalg.inv(np.eye(2) - P)
+    t = N @ np.ones(2)                      # expected steps to absorption
+    t2 = (2 * N - np.eye(2)) @ t            # second moment of the absorption time
+    mean = 1.0 + t[1]                       # first step, then from node 1
+    var = t2[1] - t[1] ** 2
+    delta, z = 0.05, 2.5758293035489004     # alpha = 99 %
+    Mstar = z * z * var / (delta * mean) ** 2
+    rk = np.array([0, 1], np.int32)
+    tb = O.table(A, rk)
+    Ms = [int(O.adaptive_budgets(A, rk, tb, seed, delta, z)[0]) for seed in range(24)]
+    assert abs(np.median(Ms) / Mstar - 1.0) < 0.15, (np.median(Ms), Mstar)

@@ -30,13 +30,19 @@ METRIC = "build+PCG seconds to rel. residual 1e-8 vs plain GPU method; walk step
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    # name: (generator, walks_per_row, drop_tol, tol)
+    # name: (generator, generator args, walks_per_row, drop_tol, tol); right-hand side
+    # N(0, 1) unless listed in ONES_RHS
     "grid3d_128": ("config_grid3d", dict(m=128), 256, 1e-4, 1e-8),
     "grid3d_64": ("config_grid3d", dict(m=64), 256, 1e-4, 1e-8),
     "grid2d_32": ("config_grid2d_32", dict(), 64, 1e-3, 1e-8),
     # 3D random geometric graph, n = 2,000,000, mean degree 24 (generation ~1 min on a host core)
     "rgg_2m": ("config_rgg", dict(), 512, 1e-4, 1e-10),
 }
+# the 3D Dirichlet Laplacians of the paper's Table 1 (m1-m6), right-hand side all ones,
+# tolerance 1e-6; 24 walks per row give the table's factor size
+for _m in (50, 60, 70, 80, 90, 100):
+    WORKLOADS[f"laplace3d_{_m}"] = ("laplace3d_dirichlet", dict(m=_m), 24, 0.0, 1e-6)
+ONES_RHS = {k for k in WORKLOADS if k.startswith("laplace3d_")}
 
 
 def parse():
@@ -139,8 +145,11 @@ def main():
     from paper_math_0609672_amd import metrics, srw, workloads
 
     gen, gkw, walks, drop, tol = WORKLOADS[args.workload]
-    A = getattr(workloads, gen)(seed=args.seed, **gkw)
-    b_host = workloads.rhs(A.n, seed=args.seed)
+    if gen == "laplace3d_dirichlet":
+        A = workloads.laplace3d_dirichlet(**gkw)
+    else:
+        A = getattr(workloads, gen)(seed=args.seed, **gkw)
+    b_host = np.ones(A.n) if args.workload in ONES_RHS else workloads.rhs(A.n, seed=args.seed)
     dev = torch.device("cuda:0")
     M = srw.Matrix.from_host(A, dev)
     b = torch.as_tensor(b_host, device=dev)
@@ -221,7 +230,9 @@ def main():
         "rel_residual": runs[-1]["rel"],
         "converged": all(r["status"] == srw.OK for r in runs),
         "factor_C": C,
+        "C_over_N": round(C / N, 3),
         "M1": metrics.m1(C, E, N),
+        "M2": metrics.m1(C, E, N) * iters,
         "solve_depth": depth,
         "phase_ms": phases,
         "roofline": {

@@ -208,6 +208,21 @@ int srw_pcg_solve(const srw_csr* A, const srw_factor* F, const double* b, double
  * each; r is not modified). */
 int srw_apply(const srw_factor* F, const double* r, double* z, void* stream);
 
+/* Walks per row by the stopping rule of Section 5.1: walks run from row k one after
+ * another until the relative error of their mean length is within delta at confidence
+ * alpha, tested as delta * mean * sqrt(M) / sigma > z with z = Q^{-1}((1 - alpha) / 2)
+ * (2.5758 for alpha = 99 %; sigma the sample standard deviation of the M lengths,
+ * sigma = 0 passes), with at least min_walks (>= 2) and at most max_walks (<= 8192)
+ * walks.  Walk w of row k is the walk srw_build_factor would run as walk w, so the
+ * budget is exactly the sequential rule's.  walks int32[n] (device output): the budget
+ * of every row, 0 for rows whose factor row is exact (no higher-ranked neighbour);
+ * pass it as srw_options.walks to build with it.  opt as for srw_build_factor (the
+ * ordering and the step cap matter; keep and profile are ignored).  Internally: rounds
+ * of walks with doubling per-row targets and a prefix scan of their lengths. */
+int srw_adaptive_budgets(const srw_csr* A, uint64_t seed, const srw_options* opt, double delta,
+                         double z, int32_t min_walks, int32_t max_walks, int32_t* walks,
+                         void* stream);
+
 /* ---- batched builds and solves (an extension: the factor does not depend on b and
  * serves every right-hand side, Sections 2.2 and 6) --------------------------------- */
 

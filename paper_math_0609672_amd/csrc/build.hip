@@ -264,6 +264,56 @@ __global__ void k_seg_bounds(int64_t n, int64_t nlong, int64_t nslab_rows,
 // ----------------------------------------------------------------------- walks
 #include "walk.hpp"
 
+// ----------------------------------------------------------- stopping rule
+// Section 5.1: the first M >= min_walks whose walk lengths (walks 0 .. M-1 of the
+// row, in walk order) satisfy delta * mean * sqrt(M) / sigma > z (sigma the sample
+// standard deviation; sigma = 0 passes); 0 if none of the row's walks does, -1 for a
+// row without walks.  One wave per row: exact integer prefix sums of the lengths and
+// their squares, the test in float64 in the oracle's operation order.
+__global__ __launch_bounds__(64) void k_length_rule(int64_t n, const int32_t* __restrict__ budget,
+                                                    const int64_t* __restrict__ rec_off,
+                                                    const uint32_t* __restrict__ rec_len,
+                                                    double delta, double z, int32_t min_walks,
+                                                    int32_t* __restrict__ found)
+{
+    const int64_t k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t m = budget[k];
+    if (m == 0) {
+        if (lane == 0) found[k] = -1;
+        return;
+    }
+    const int64_t base = rec_off[k];
+    uint64_t s1 = 0, s2 = 0;  // sums over the walks before this chunk
+    int32_t hit = 0;
+    for (int32_t c0 = 0; c0 < m && hit == 0; c0 += 64) {
+        const int32_t w = c0 + lane;
+        const uint64_t len = w < m ? (uint64_t)rec_len[base + w] : 0;
+        uint64_t p1 = len, p2 = len * len;  // inclusive prefix sums within the chunk
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t a = __shfl_up(p1, off, 64), b = __shfl_up(p2, off, 64);
+            if (lane >= off) {
+                p1 += a;
+                p2 += b;
+            }
+        }
+        bool ok = false;
+        const int32_t M = w + 1;
+        if (w < m && M >= min_walks) {
+            const uint64_t S1 = s1 + p1, S2 = s2 + p2;
+            const double mean = (double)S1 / (double)M;
+            const double var = ((double)S2 - (double)M * mean * mean) / (double)(M - 1);
+            ok = !(var > 0.0) || delta * mean * sqrt((double)M) / sqrt(var) > z;
+        }
+        const uint64_t mask = ballot(ok);
+        if (mask) hit = c0 + __ffsll((long long)mask);  // lowest satisfying walk count
+        s1 += __shfl(p1, 63, 64);
+        s2 += __shfl(p2, 63, 64);
+    }
+    if (lane == 0) found[k] = hit;
+}
+
 // --------------------------------------------------------------------- tallies
 // One wave per row.  LDS: P sort keys (P = power of two >= budget) + P run heads.
 __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restrict__ budget,
@@ -557,6 +607,78 @@ void set_last_error(const char* msg)
 
 const char* get_last_error() { return last_error; }
 
+__global__ void k_rule_round(int64_t n, const int32_t* __restrict__ found, int32_t* __restrict__ target,
+                             int32_t* __restrict__ walks, int32_t max_walks, int* __restrict__ open)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || walks[k] >= 0) return;  // decided before this round
+    const int32_t f = found[k];
+    if (f < 0) walks[k] = 0;                       // exact row: no walks
+    else if (f > 0) walks[k] = f;                  // the rule is met after f walks
+    else if (target[k] >= max_walks) walks[k] = max_walks;
+    else {
+        target[k] = min(2 * target[k], max_walks);
+        atomicAdd(open, 1);
+    }
+}
+
+__global__ void k_rule_budgets(int64_t n, const int32_t* __restrict__ walks,
+                               const int32_t* __restrict__ target, int32_t* __restrict__ budget)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) budget[k] = walks[k] >= 0 ? 1 : target[k];  // decided rows: one cheap walk
+}
+
+__global__ void k_fill_i32v(int64_t n, int32_t* x, int32_t v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[k] = v;
+}
+
+int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt_in, double delta,
+                  double z, int32_t min_walks, int32_t max_walks, int32_t* walks, hipStream_t s)
+{
+    const int64_t n = A->n;
+    if (n == 0) return SRW_OK;
+    int32_t *target = nullptr, *budget = nullptr, *found = nullptr;
+    int* open = nullptr;
+    int* host_open = nullptr;
+    hipError_t e = hipMallocAsync((void**)&target, 3 * n * sizeof(int32_t) + 256, s);
+    if (e != hipSuccess) return hip_fail(e, "adaptive budgets: workspace");
+    budget = target + n;
+    found = budget + n;
+    open = (int*)(found + n);
+    e = hipHostMalloc((void**)&host_open, sizeof(int), hipHostMallocDefault);
+    const int g = grid_for(n, BLOCK);
+    int status = SRW_OK;
+    if (e == hipSuccess) {
+        k_fill_i32v<<<g, BLOCK, 0, s>>>(n, target, min_walks);
+        k_fill_i32v<<<g, BLOCK, 0, s>>>(n, walks, -1);
+        e = hipGetLastError();
+    }
+    srw_options opt = *opt_in;
+    opt.walks = budget;
+    opt.keep = 0;
+    opt.profile = 0;
+    for (int round = 0; e == hipSuccess && status == SRW_OK; ++round) {
+        k_rule_budgets<<<g, BLOCK, 0, s>>>(n, walks, target, budget);
+        LengthRule rule{delta, z, min_walks, found};
+        srw_factor* none = nullptr;
+        status = build_factor_impl(A, 1, 0.0, seed, &opt, &none, s, nullptr, &rule);
+        if (status != SRW_OK) break;
+        k_fill_i32v<<<1, 1, 0, s>>>(1, (int32_t*)open, 0);
+        k_rule_round<<<g, BLOCK, 0, s>>>(n, found, target, walks, max_walks, open);
+        e = hipMemcpyAsync(host_open, open, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess || *host_open == 0) break;
+    }
+    (void)hipFreeAsync(target, s);
+    (void)hipStreamSynchronize(s);
+    if (host_open) (void)hipHostFree(host_open);
+    if (e != hipSuccess) return hip_fail(e, "adaptive budgets");
+    return status;
+}
+
 void retain_pool_memory()
 {
     static bool done[64] = {};
@@ -621,7 +743,7 @@ int ordering_impl(int64_t n, uint64_t seed, int32_t* rank, hipStream_t s)
 
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                       const srw_options* opt_in, srw_factor** out, hipStream_t s,
-                      const BatchKeys* batch)
+                      const BatchKeys* batch, const LengthRule* rule)
 {
     srw_options opt;
     srw_default_options(&opt);
@@ -888,6 +1010,14 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         std::memcpy(&herr, &pinned[0], sizeof(int));
         if (herr) FAIL(map_err(herr));
         F->deg_sum = pinned[5];
+        if (rule) {  // walks only: the stopping rule's verdict per row, no factor
+            k_length_rule<<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
+                n, budget, rec_off, rec_len, rule->delta, rule->z, rule->min_walks, rule->found);
+            CHECK_HIP(hipGetLastError());
+            CHECK_HIP(hipStreamSynchronize(s));
+            status = SRW_WALKS_ONLY;
+            goto done;
+        }
 
         // ---- 5. tallies
         uint64_t* tJ = ALLOC(keep, uint64_t, n);
@@ -1100,7 +1230,7 @@ done:
     if (status != SRW_OK) {
         keep.release();
         delete F;
-        return status;
+        return status == SRW_WALKS_ONLY ? SRW_OK : status;
     }
     if (opt.keep < 1) {
         // drop what only export needs

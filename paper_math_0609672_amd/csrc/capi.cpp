@@ -291,6 +291,27 @@ int srw_apply(const srw_factor* F, const double* r, double* z, void* stream)
     return srw::apply_impl(const_cast<srw_factor*>(F), r, z, as_stream(stream));
 }
 
+int srw_adaptive_budgets(const srw_csr* A, uint64_t seed, const srw_options* opt, double delta,
+                         double z, int32_t min_walks, int32_t max_walks, int32_t* walks,
+                         void* stream)
+{
+    if (!csr_ok(A) || (A->n > 0 && !walks)) return SRW_E_ARG;
+    if (!(delta > 0.0) || !std::isfinite(delta) || !(z > 0.0) || !std::isfinite(z)) return SRW_E_ARG;
+    if (min_walks < 2 || max_walks < min_walks || max_walks > 8192) return SRW_E_ARG;
+    if (options_ok(opt, A->n) != SRW_OK) return SRW_E_ARG;
+    srw_options o;
+    srw_default_options(&o);
+    if (opt) o = *opt;
+    try {
+        return srw::adaptive_impl(A, seed, &o, delta, z, min_walks, max_walks, walks,
+                                  as_stream(stream));
+    } catch (const std::bad_alloc&) {
+        return SRW_E_NOMEM;
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
 int srw_ordering(int64_t n, uint64_t seed, int32_t* rank, void* stream)
 {
     if (n < 0 || n >= (int64_t)0x7FFFFFFF || (n > 0 && !rank)) return SRW_E_ARG;

@@ -120,9 +120,22 @@ struct BatchKeys {
     const uint64_t* mat_seed;
 };
 
+// Walks-only build: apply the Section 5.1 stopping rule to every row's walks and
+// write the verdict to found (see k_length_rule); no factor is made.
+struct LengthRule {
+    double delta, z;
+    int32_t min_walks;
+    int32_t* found;
+};
+
+// Internal status of a walks-only build (never returned by the C ABI).
+constexpr int SRW_WALKS_ONLY = 100;
+
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                       const srw_options* opt, srw_factor** out, hipStream_t s,
-                      const BatchKeys* batch = nullptr);
+                      const BatchKeys* batch = nullptr, const LengthRule* rule = nullptr);
+int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt, double delta,
+                  double z, int32_t min_walks, int32_t max_walks, int32_t* walks, hipStream_t s);
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);

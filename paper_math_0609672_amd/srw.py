@@ -74,6 +74,8 @@ _lib.srw_pcg_solve.argtypes = [ctypes.POINTER(_Csr), _P, _P, _D, _I32, _P, ctype
                                ctypes.POINTER(_D), _P]
 _lib.srw_apply.argtypes = [_P, _P, _P, _P]
 _lib.srw_ordering.argtypes = [_I64, _U64, _P, _P]
+_lib.srw_adaptive_budgets.argtypes = [ctypes.POINTER(_Csr), _U64, ctypes.POINTER(_Options), _D, _D,
+                                      _I32, _I32, _P, _P]
 _lib.srw_row_features.argtypes = [ctypes.POINTER(_Csr), _P, _P, _P]
 _lib.srw_budget_labels.argtypes = [_P, _I32, _P, _P]
 _lib.srw_mlp_forward.argtypes = [_P, _P, _P, _I64, _P, _P]
@@ -91,7 +93,7 @@ _lib.srw_status_string.restype = ctypes.c_char_p
 EXPORTED = ["srw_default_options", "srw_build_factor", "srw_factor_free", "srw_factor_info",
             "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
-            "srw_pcg_solve", "srw_apply", "srw_ordering", "srw_row_features", "srw_budget_labels",
+            "srw_pcg_solve", "srw_apply", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
             "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_budgets", "srw_build_factor_batched",
             "srw_batch_info", "srw_pcg_solve_batched", "srw_last_error", "srw_status_string"]
 
@@ -290,6 +292,28 @@ def apply(F: Factor, r: torch.Tensor, stream=None) -> torch.Tensor:
     st = _lib.srw_apply(F.handle, _ptr(r), _ptr(z), _stream(stream))
     _check(st, "srw_apply")
     return z
+
+
+def adaptive_budgets(A: Matrix, seed: int, delta: float, alpha: float = 0.99, min_walks: int = 20,
+                     max_walks: int = 8192, rank=None, max_steps: int = 0,
+                     stream=None) -> torch.Tensor:
+    """srw_adaptive_budgets: walks per row by the Section 5.1 stopping rule (int32[n]),
+    z = Q^{-1}((1 - alpha) / 2) from the standard normal distribution."""
+    import statistics
+
+    z = statistics.NormalDist().inv_cdf(1.0 - (1.0 - alpha) / 2.0)
+    opt = _Options()
+    _lib.srw_default_options(ctypes.byref(opt))
+    if rank is not None:
+        opt.ordering = ORDER_GIVEN
+        opt.rank = _ptr(rank).value
+    opt.max_steps = int(max_steps)
+    walks = torch.empty(A.n, dtype=torch.int32, device=A.rowptr.device)
+    csr = A.c()
+    _check(_lib.srw_adaptive_budgets(ctypes.byref(csr), int(seed) & (2**64 - 1), ctypes.byref(opt),
+                                     float(delta), float(z), int(min_walks), int(max_walks),
+                                     _ptr(walks), _stream(stream)), "srw_adaptive_budgets")
+    return walks
 
 
 # ------------------------------------------------------------ learned walk budgets

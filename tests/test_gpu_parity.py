@@ -307,3 +307,30 @@ def test_maximum_budget_row(srw):
     budget = np.full(A.n, 5, dtype=np.int32)
     budget[[0, 17, 600]] = [8192, 4097, 8191]
     compare_walks(srw, A, 5, 3, budget=budget)
+
+
+@pytest.mark.parametrize("name,delta,max_walks", [("grid2d_32", 0.2, 8192), ("random_3000", 0.3, 8192),
+                                                  ("grid2d_37x29", 0.02, 100)])
+def test_adaptive_budgets_bit_exact(srw, name, delta, max_walks):
+    """Section 5.1 stopping rule: the GPU's walks per row equal the oracle's
+    sequential rule (same z), including rows capped at max_walks and exact rows."""
+    import statistics
+    A, _ = CASES[name]
+    alpha = 0.99
+    z = statistics.NormalDist().inv_cdf(1.0 - (1.0 - alpha) / 2.0)
+    M = srw.Matrix.from_host(A, DEV)
+    walks = np_(srw.adaptive_budgets(M, 7, delta, alpha=alpha, max_walks=max_walks))
+    rk = O.rank(A.n, 7)
+    tb = O.table(A, rk)
+    ref = O.adaptive_budgets(A, rk, tb, 7, delta, z, 20, max_walks)
+    assert np.array_equal(walks, ref)
+    assert np.all((walks == 0) == (tb.tau <= 0))
+    # and a factor built with them is the oracle's, bit for bit
+    F = srw.build_factor(M, 1, 1e-3, 7, walks=torch.as_tensor(walks, device=DEV))
+    ex = {k: np_(v) for k, v in F.export().items()}
+    Fo = O.build_factor(A, np.maximum(walks, 1), 1e-3, 7)
+    assert np.array_equal(ex["yptr"], Fo.yptr)
+    assert np.array_equal(ex["ycol"], Fo.ycol)
+    assert np.array_equal(ex["yval"], Fo.yval)
+    assert np.array_equal(ex["d"], Fo.d)
+    F.free()

@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--solve-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--adaptive", type=float, default=0.0, metavar="DELTA",
+                    help="walks per row by the Section 5.1 stopping rule with relative margin "
+                         "DELTA at 99%% confidence (at least 20 walks), decided inside each "
+                         "timed step, instead of the workload's uniform budget")
     ap.add_argument("--compare-precision", action="store_true",
                     help="after the timed steps, run one step with the other factor precision "
                          "(fp32 <-> fp64) and report it under ext_precision")
@@ -158,9 +162,12 @@ def main():
 
     def step():
         t0 = time.perf_counter()
+        budgets = None
+        if args.adaptive > 0:
+            budgets = srw.adaptive_budgets(M, args.seed, args.adaptive, alpha=0.99)
         F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
                              refill_period=args.refill, schedule=args.schedule,
-                             solve_order=args.solve_order, profile=True)
+                             solve_order=args.solve_order, profile=True, walks=budgets)
         t1 = time.perf_counter()
         st, _, it, rel = srw.pcg_solve(M, F, b, tol, 10000, x=x)
         t2 = time.perf_counter()
@@ -216,8 +223,10 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 (fp32 factor)",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {gen}{gkw or ''}, n={N}, nnz={E}, {walks} walks/row, "
-                        f"drop {drop}, tol {tol}, seed {args.seed}",
+            "workload": f"{args.workload}: {gen}{gkw or ''}, n={N}, nnz={E}, "
+                        + (f"Section 5.1 walks (delta {args.adaptive}, alpha 0.99)" if args.adaptive > 0
+                           else f"{walks} walks/row")
+                        + f", drop {drop}, tol {tol}, seed {args.seed}",
             "global_batch": 1,
             "parallelism": "single GPU",
         },

@@ -230,22 +230,6 @@ __global__ void k_read_last(const int64_t* scan, const int32_t* last_in, int64_t
     out[0] = n > 0 ? scan[n - 1] + (int64_t)last_in[n - 1] : 0;
 }
 
-// chunk descriptor: x = row, y = first walk | (walk count << 16)
-__global__ void k_chunks(int64_t norder, const int32_t* __restrict__ order,
-                         const int64_t* __restrict__ chunk_off, const int32_t* __restrict__ budget,
-                         uint2* __restrict__ cdesc)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= norder) return;
-    const int32_t v = order[j];
-    const int32_t b = budget[v];
-    for (int64_t c = chunk_off[j]; c < chunk_off[j + 1]; ++c) {
-        const uint32_t w0 = (uint32_t)(c - chunk_off[j]) * SRW_WAVE;
-        const uint32_t cnt = min((uint32_t)SRW_WAVE, (uint32_t)b - w0);
-        cdesc[c] = make_uint2((uint32_t)v, w0 | (cnt << 16));
-    }
-}
-
 // bounds[0..NSEG]: first chunk of each segment (bounds[NSEG] = all chunks)
 __global__ void k_seg_bounds(int64_t n, int64_t nlong, int64_t nslab_rows,
                              const int64_t* __restrict__ pos_slab,
@@ -660,7 +644,7 @@ int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt_in, do
     opt.walks = budget;
     opt.keep = 0;
     opt.profile = 0;
-    for (int round = 0; e == hipSuccess && status == SRW_OK; ++round) {
+    while (e == hipSuccess && status == SRW_OK) {
         k_rule_budgets<<<g, BLOCK, 0, s>>>(n, walks, target, budget);
         LengthRule rule{delta, z, min_walks, found};
         srw_factor* none = nullptr;
@@ -872,17 +856,15 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipMemcpyAsync(&pinned[0], ltot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipStreamSynchronize(s));
         const int64_t n_lines = pinned[0];
-        if (n_lines >= (int64_t)UINT32_MAX) FAIL(SRW_E_ARG);  // line indices are 32-bit
-        uint4* recs = ALLOC(tmp, uint4, n_lines * 4);
+        if (2 * n_lines >= (int64_t)UINT32_MAX) FAIL(SRW_E_ARG);  // line indices are 32-bit
+        // walk records, then start records of the same shape
+        uint4* recs = ALLOC(tmp, uint4, 2 * n_lines * 4);
         uint2* ent = opt.keep >= 1 ? ALLOC(keep, uint2, nnz_off) : nullptr;  // export only
         uint32_t* mthr = ALLOC(keep, uint32_t, nnz_off);
-        uint4* desc = ALLOC(tmp, uint4, n);
-        uint32_t* lastm = ALLOC(tmp, uint32_t, n);
         double* tau = ALLOC(keep, double, n);
         int32_t* budget = ALLOC(keep, int32_t, n);
         int32_t* maxb = ALLOC(tmp, int32_t, 1);
-        if (!recs || (opt.keep >= 1 && !ent) || !mthr || !desc || !lastm || !tau || !budget ||
-            !maxb)
+        if (!recs || (opt.keep >= 1 && !ent) || !mthr || !tau || !budget || !maxb)
             FAIL(SRW_E_NOMEM);
         F->ent = ent;
         F->mthr = mthr;
@@ -891,7 +873,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         mark(2);
         CHECK_HIP(hipMemsetAsync(maxb, 0, sizeof(int32_t), s));
         k_table<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, grounded, walks_per_row,
-                                    opt.walks, rline, (uint32_t*)recs, ent, mthr, desc, lastm, tau,
+                                    opt.walks, rline, n_lines, (uint32_t*)recs, ent, mthr, tau,
                                     budget, maxb);
         CHECK_HIP(hipGetLastError());
 
@@ -940,10 +922,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipStreamSynchronize(s));
         const int64_t n_chunks = pinned[4];
         F->walks_total = total_walks;
-        uint2* cdesc = ALLOC(tmp, uint2, n_chunks);
+        ChunkDesc* cdesc = ALLOC(tmp, ChunkDesc, n_chunks);
         if (!cdesc) FAIL(SRW_E_NOMEM);
         k_set_last<<<1, 1, 0, s>>>(chunk_off, norder, n_chunks);
-        k_chunks<<<grid_for(norder, BLOCK), BLOCK, 0, s>>>(norder, order, chunk_off, budget, cdesc);
+        k_chunks<<<grid_for(norder, BLOCK), BLOCK, 0, s>>>(
+            norder, order, chunk_off, budget, rline, n_lines, F->rank, rec_off, seed,
+            batch ? batch->node_mat : nullptr, batch ? batch->mat_off : nullptr,
+            batch ? batch->mat_seed : nullptr, cdesc);
         k_seg_bounds<<<1, 1, 0, s>>>(n, nlong, nslab_rows, pos2, chunk_off, bounds);
         CHECK_HIP(hipGetLastError());
 
@@ -962,14 +947,9 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         mark(4);
         if (n_chunks > 0) {
             WalkArgs wa{};
-            wa.desc = desc;
-            wa.lastm = lastm;
             wa.recs = recs;
-            wa.mthr = mthr;
             wa.chunks = cdesc;
             wa.bounds = bounds;
-            wa.rec_off = rec_off;
-            wa.seed = seed;
             wa.max_steps = opt.max_steps;
             wa.rec_end = rec_end;
             wa.rec_vis = rec_vis;
@@ -982,18 +962,11 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             // persistent grid: as many blocks as fit on the chip at once
             void (*kern)(WalkArgs) = nullptr;
-            if (batch) {
-                wa.node_mat = batch->node_mat;
-                wa.mat_off = batch->mat_off;
-                wa.mat_seed = batch->mat_seed;
-                kern = opt.refill_period == 8 ? k_walk<8, true> : k_walk<1, true>;
-            } else {
-                switch (opt.refill_period) {
-                    case 2: kern = k_walk<2, false>; break;
-                    case 4: kern = k_walk<4, false>; break;
-                    case 8: kern = k_walk<8, false>; break;
-                    default: kern = k_walk<1, false>; break;
-                }
+            switch (opt.refill_period) {
+                case 2: kern = k_walk<2>; break;
+                case 4: kern = k_walk<4>; break;
+                case 8: kern = k_walk<8>; break;
+                default: kern = k_walk<1>; break;
             }
             int per_cu = 0;
             CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));

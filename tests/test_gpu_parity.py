@@ -334,3 +334,29 @@ def test_adaptive_budgets_bit_exact(srw, name, delta, max_walks):
     assert np.array_equal(ex["yval"], Fo.yval)
     assert np.array_equal(ex["d"], Fo.d)
     F.free()
+
+
+def test_walks_bit_exact_with_hub_nodes(srw):
+    # nodes of degree > 96: the record's line summaries cover twelve lines and the
+    # step scans on from the thirteenth; degrees 7..96 use the summaries
+    rng = np.random.default_rng(11)
+    n = 900
+    base = W.random_graph(n, 2500, seed=11, ground_frac=0.02)
+    S = base.to_scipy().tocoo()
+    eu, ev = S.row[S.row < S.col], S.col[S.row < S.col]
+    hubs = {0: 200, 1: 97, 2: 96, 3: 40}
+    extra = []
+    for h, d in hubs.items():
+        others = rng.choice(np.arange(4, n), size=d, replace=False)
+        extra += [(h, int(o)) for o in others]
+    pairs = set(zip(eu.tolist(), ev.tolist()))
+    for a_, b_ in extra:
+        pairs.add((min(a_, b_), max(a_, b_)))
+    e = np.array(sorted(pairs))
+    g = rng.uniform(0.1, 10.0, e.shape[0])
+    excess = np.zeros(n)
+    excess[rng.choice(n, 20, replace=False)] = rng.uniform(0.1, 1.0, 20)
+    A = W.assemble(n, e[:, 0], e[:, 1], g, excess)
+    deg = np.diff(A.rowptr) - 1
+    assert deg.max() > 96
+    compare_walks(srw, A, 48, 13)

@@ -8,7 +8,8 @@ one row and one walk at a time) and in ``dense.py`` (numpy closed forms used as 
 ``build_factor`` and ``pcg`` follow Algorithm 1 of the paper: random ordering
 (Section 5.4), walks with rank homes and the exact one-step treatment (Sections 2.2.1
 and 5.2), tallies (Section 3.1), factor entries by eqs. newy / newz / d, the optional
-drop (Section 4), then PCG (Section 6).
+drop (Section 4), then PCG (Section 6).  With ``reuse=True`` the walks also feed the
+walks Algorithm "reuse" extracts from them into the tallies (Section 5.3).
 """
 from __future__ import annotations
 
@@ -54,6 +55,12 @@ def lib():
         L.srwo_table.argtypes = [i64, P, P, P, P, P, P, P, P, P, P]
         L.srwo_walk_rows.argtypes = [i64, P, P, P, P, P, P, P, u64, i64, P, P, P, P, P, P]
         L.srwo_tally_rows.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.srwo_reuse_sequence.argtypes = [i64, P, P, i64, P, P, P, P]
+        L.srwo_reuse_sequence.restype = i64
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.srwo_walk_rows_reuse.argtypes = [i64, P, P, P, P, P, P, P, u64, i64, P, P, PP, PP, PP, PP]
+        L.srwo_walk_rows_reuse.restype = i64
+        L.srwo_free.argtypes = [P]
         L.srwo_factor.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, dbl, P, P, P, P]
         L.srwo_apply.argtypes = [i64, P, P, P, P, P, P, P, P]
         L.srwo_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, dbl, i32, P, P, P]
@@ -147,6 +154,63 @@ def walk_rows(A, rk, tb: Table, seed: int, rows, budget) -> Walks:
     return Walks(rows, budget, rec_off, end[:n], vis[:n], ln[:n])
 
 
+# ------------------------------------------------------------------ walk reuse
+@dataclass
+class Records:
+    """Walks counted in the tallies when walks are reused (Section 5.3): start node
+    (row), end node (-1 = ground), stays at the start (start included), steps."""
+    row: np.ndarray       # int32
+    end: np.ndarray       # int32
+    visits: np.ndarray    # uint32
+    length: np.ndarray    # uint32
+
+
+def reuse_sequence(keys, nodes) -> Records:
+    """Algorithm "reuse" of Section 5.3 on one legal sequence: position l = 1..len holds
+    nodes[l-1] with ordering key keys[l-1] (ground: key -1, node -1).  Returns every
+    walk the algorithm counts (the sequence itself included), in counting order."""
+    k = _c(keys, np.int64)
+    nd = _c(nodes, np.int32)
+    cap = max(k.size, 1)
+    out = [np.zeros(cap, np.int32), np.zeros(cap, np.int32), np.zeros(cap, np.uint32),
+           np.zeros(cap, np.uint32)]
+    m = lib().srwo_reuse_sequence(k.size, _p(k), _p(nd), cap, *(_p(a) for a in out))
+    assert m >= 0, m
+    return Records(*(a[:m] for a in out))
+
+
+def walk_rows_reuse(A, rk, tb: Table, seed: int, rows, budget) -> Records:
+    """The walks of `rows` (as walk_rows, same draws) with walk reuse: every simulated
+    walk and every walk extracted from it, as records."""
+    rows = _c(rows, np.int64)
+    budget = np.broadcast_to(np.asarray(budget, np.int32), rows.shape).copy()
+    ptrs = [ctypes.c_void_p() for _ in range(4)]
+    m = lib().srwo_walk_rows_reuse(A.n, _p(_c(A.rowptr, np.int64)), _p(tb.nbr), _p(tb.thr),
+                                   _p(tb.mthr), _p(tb.tau), _p(tb.grounded),
+                                   _p(_c(rk, np.int32)), seed, rows.size, _p(rows), _p(budget),
+                                   *(ctypes.byref(q) for q in ptrs))
+    assert m >= 0, m
+    out = []
+    for q, dt in zip(ptrs, (np.int32, np.int32, np.uint32, np.uint32)):
+        a = np.ctypeslib.as_array(ctypes.cast(q, ctypes.POINTER(np.ctypeslib.as_ctypes_type(dt))),
+                                  shape=(max(m, 1),))
+        out.append(a[:m].copy())
+        lib().srwo_free(q)
+    return Records(*out)
+
+
+def records_to_walks(n: int, rec: Records) -> Walks:
+    """Groups records by their start node (stable) into the per-row layout of Walks
+    over all nodes, for `tally`."""
+    order = np.argsort(rec.row, kind="stable")
+    count = np.bincount(rec.row, minlength=n).astype(np.int32)[:n] if rec.row.size else \
+        np.zeros(n, np.int32)
+    rec_off = np.zeros(n + 1, np.int64)
+    np.cumsum(count, out=rec_off[1:])
+    return Walks(np.arange(n, dtype=np.int64), count, rec_off, rec.end[order].astype(np.int32),
+                 rec.visits[order].astype(np.uint32), rec.length[order].astype(np.uint32))
+
+
 @dataclass
 class Tallies:
     walks: np.ndarray     # uint32[r] M'
@@ -229,13 +293,19 @@ def assemble(A, rk, tb: Table, tl: Tallies, rows: np.ndarray, drop_tol: float) -
     return Factor(n, np.asarray(rk, np.int32), yptr, ycol[:nnz], yval[:nnz], d[:n], tb)
 
 
-def build_factor(A, walks_per_row, drop_tol: float, seed: int, rk=None) -> Factor:
+def build_factor(A, walks_per_row, drop_tol: float, seed: int, rk=None,
+                 reuse: bool = False) -> Factor:
     """The whole preconditioning phase of Algorithm 1 on the CPU.  `walks_per_row` is
-    an int (uniform) or an int array over nodes (per-row budgets, each >= 1)."""
+    an int (uniform) or an int array over nodes (per-row budgets, each >= 1).  With
+    reuse, every walk also contributes the walks Algorithm "reuse" extracts from it
+    (Section 5.3) to the tallies of their start nodes."""
     rk = rank(A.n, seed) if rk is None else np.asarray(rk, np.int32)
     tb = table(A, rk)
     rows = np.arange(A.n, dtype=np.int64)
-    wk = walk_rows(A, rk, tb, seed, rows, walks_per_row)
+    if reuse:
+        wk = records_to_walks(A.n, walk_rows_reuse(A, rk, tb, seed, rows, walks_per_row))
+    else:
+        wk = walk_rows(A, rk, tb, seed, rows, walks_per_row)
     tl = tally(wk)
     F = assemble(A, rk, tb, tl, rows, drop_tol)
     F.walks, F.tallies = wk, tl

@@ -17,6 +17,8 @@
  *   - tallies M_k, H_{k,i} and J_{k,k} (Section 3.1) collected with the exact
  *     one-step treatment: the first step is drawn among the not-yet-processed
  *     neighbours only (Section 5.2);
+ *   - optionally, walk reuse: every walk also feeds the walks that Algorithm "reuse"
+ *     extracts from it to the tallies of their start nodes (Section 5.3);
  *   - factor entries by eqs. newy and newz, the diagonal by eq. d (Sections 3.3 and
  *     5.2), then the optional drop of small entries (Section 4, footnote);
  *   - the hybrid solver: PCG with the preconditioner (L D L^T)^{-1} (Algorithm 1),
@@ -333,6 +335,235 @@ int srwo_walk_rows(int64_t n, const int64_t* rowptr, const int32_t* nbr, const u
     }
     return SRWO_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Walk reuse (Section 5.3, Algorithm "reuse").                              */
+/* ------------------------------------------------------------------------- */
+
+/* One walk counted in the tallies: its start node (the row it belongs to), end node
+ * (-1 = ground), stays at the start (start included) and number of steps. */
+typedef struct {
+    int32_t row, end;
+    uint32_t visits, length;
+} srwo_rec;
+
+typedef struct {
+    srwo_rec* r;
+    int64_t n, cap;
+} srwo_recs;
+
+static int recs_push(srwo_recs* o, int32_t row, int32_t end, uint32_t visits, uint32_t length)
+{
+    if (o->n == o->cap) {
+        int64_t c = o->cap ? 2 * o->cap : 64;
+        srwo_rec* q = (srwo_rec*)realloc(o->r, sizeof(srwo_rec) * (size_t)c);
+        if (!q) return SRWO_E_NOMEM;
+        o->r = q;
+        o->cap = c;
+    }
+    o->r[o->n].row = row;
+    o->r[o->n].end = end;
+    o->r[o->n].visits = visits;
+    o->r[o->n].length = length;
+    o->n++;
+    return SRWO_OK;
+}
+
+/* The two stacks of the algorithm: stack1 holds node keys (position in the
+ * ordering; ground is below every node), stack2 the positions l at which they were
+ * pushed (the start is position 1).  `node` and `visits` ride along with each entry:
+ * the node id (for the records) and the stays at that node while it is the top (the
+ * J_{k',k'} increments of the algorithm, start included). */
+typedef struct {
+    int64_t* key;
+    int64_t* pos;
+    int32_t* node;
+    uint32_t* visits;
+    int64_t top, cap;  /* top = number of entries */
+} srwo_stacks;
+
+static int stacks_push(srwo_stacks* s, int64_t key, int64_t pos, int32_t node)
+{
+    if (s->top == s->cap) {
+        int64_t c = s->cap ? 2 * s->cap : 16;
+        int64_t* k = (int64_t*)realloc(s->key, sizeof(int64_t) * (size_t)c);
+        if (!k) return SRWO_E_NOMEM;
+        s->key = k;
+        int64_t* p = (int64_t*)realloc(s->pos, sizeof(int64_t) * (size_t)c);
+        if (!p) return SRWO_E_NOMEM;
+        s->pos = p;
+        int32_t* nd = (int32_t*)realloc(s->node, sizeof(int32_t) * (size_t)c);
+        if (!nd) return SRWO_E_NOMEM;
+        s->node = nd;
+        uint32_t* v = (uint32_t*)realloc(s->visits, sizeof(uint32_t) * (size_t)c);
+        if (!v) return SRWO_E_NOMEM;
+        s->visits = v;
+        s->cap = c;
+    }
+    s->key[s->top] = key;
+    s->pos[s->top] = pos;
+    s->node[s->top] = node;
+    s->visits[s->top] = 1;
+    s->top++;
+    return SRWO_OK;
+}
+
+static void stacks_free(srwo_stacks* s)
+{
+    free(s->key);
+    free(s->pos);
+    free(s->node);
+    free(s->visits);
+}
+
+/* Position l of the walk holds node `node` with key `key`.  While key is below the
+ * top of stack1, the top is popped; if the top was pushed more than one position
+ * before l, the segment from it to l is a legal walk of at least two steps: M, H
+ * and J of its start node take it (one record).  Then key is pushed if it is above
+ * the new top, else (equal) it is a stay at the top's node.  Returns the number of
+ * entries left (0 once the walk has dropped below its start). */
+static int reuse_position(srwo_stacks* s, int64_t l, int64_t key, int32_t node, srwo_recs* out,
+                          int* err)
+{
+    while (s->top > 0 && key < s->key[s->top - 1]) {
+        const int64_t t = s->top - 1;
+        if (l > s->pos[t] + 1) {
+            int e = recs_push(out, s->node[t], node, s->visits[t], (uint32_t)(l - s->pos[t]));
+            if (e) *err = e;
+        }
+        s->top--;
+    }
+    if (s->top == 0) return 0;
+    if (key > s->key[s->top - 1]) {
+        int e = stacks_push(s, key, l, node);
+        if (e) *err = e;
+    } else {
+        s->visits[s->top - 1]++;
+    }
+    return (int)s->top;
+}
+
+/* Algorithm "reuse" on a given legal sequence: positions 1..len hold nodes node[i]
+ * with keys key[i] (i = 0..len-1; ground as key -1, node -1).  Writes the records of
+ * every walk the algorithm counts, in the order it counts them, to rows/ends/visits/
+ * lengths (capacity cap) and returns their number, or a negative status. */
+int64_t srwo_reuse_sequence(int64_t len, const int64_t* key, const int32_t* node, int64_t cap,
+                            int32_t* rows, int32_t* ends, uint32_t* visits, uint32_t* lengths)
+{
+    if (len < 1) return 0;
+    srwo_stacks st = {0};
+    srwo_recs out = {0};
+    int err = stacks_push(&st, key[0], 1, node[0]);
+    for (int64_t i = 1; i < len && !err; i++)
+        if (reuse_position(&st, i + 1, key[i], node[i], &out, &err) == 0) break;
+    stacks_free(&st);
+    if (err) {
+        free(out.r);
+        return err;
+    }
+    int64_t n = out.n;
+    if (n > cap) n = cap;
+    for (int64_t i = 0; i < n; i++) {
+        rows[i] = out.r[i].row;
+        ends[i] = out.r[i].end;
+        visits[i] = out.r[i].visits;
+        lengths[i] = out.r[i].length;
+    }
+    n = out.n;
+    free(out.r);
+    return n;
+}
+
+/* Walk w of row k as in srwo_walk, fed position by position (the start is position
+ * 1, the node reached by step t is position t + 2) to the two stacks, with the rank
+ * as key: the walk itself and every walk extracted from it go to `out`. */
+static int srwo_walk_reuse(const int64_t* rowptr, const int32_t* nbr, const uint32_t* thr,
+                           const uint32_t* mthr, const unsigned char* grounded,
+                           const int32_t* rank, uint64_t seed, int64_t k, int64_t w,
+                           srwo_stacks* st, srwo_recs* out)
+{
+    int err = SRWO_OK;
+    st->top = 0;
+    err = stacks_push(st, rank[k], 1, (int32_t)k);
+    if (err) return err;
+    /* first step: among motel neighbours of k (always a higher rank) */
+    int64_t base = rowptr[k] - k;
+    int64_t deg = rowptr[k + 1] - rowptr[k] - 1;
+    uint32_t u = srwo_draw(seed, k, w, 0);
+    int64_t chosen = -1, last_motel = -1;
+    for (int64_t m = 0; m < deg; m++) {
+        if (rank[nbr[base + m]] > rank[k]) last_motel = m;
+        if (chosen < 0 && u < mthr[base + m]) chosen = m;
+    }
+    if (chosen < 0) chosen = last_motel;
+    int64_t cur = nbr[base + chosen];
+    reuse_position(st, 2, rank[cur], (int32_t)cur, out, &err);
+    for (uint64_t t = 1; !err; t++) {
+        u = srwo_draw(seed, k, w, t);
+        base = rowptr[cur] - cur;
+        deg = rowptr[cur + 1] - rowptr[cur] - 1;
+        int64_t next = -2;
+        for (int64_t m = 0; m < deg; m++)
+            if (u < thr[base + m]) { next = nbr[base + m]; break; }
+        if (next == -2) next = grounded[cur] ? -1 : nbr[base + deg - 1];
+        const int64_t key = next < 0 ? -1 : rank[next];
+        if (reuse_position(st, (int64_t)t + 2, key, (int32_t)next, out, &err) == 0) break;
+        cur = next;
+    }
+    return err;
+}
+
+/* The walks of a list of rows (as srwo_walk_rows) with walk reuse: returns the
+ * number of records (each walk simulated plus each walk extracted from one) and
+ * hands the record array to the caller through *recs (free with srwo_free), or a
+ * negative status. */
+int64_t srwo_walk_rows_reuse(int64_t n, const int64_t* rowptr, const int32_t* nbr,
+                             const uint32_t* thr, const uint32_t* mthr, const double* tau,
+                             const unsigned char* grounded, const int32_t* rank, uint64_t seed,
+                             int64_t nrows, const int64_t* rows, const int32_t* budget,
+                             int32_t** rec_rows, int32_t** rec_ends, uint32_t** rec_visits,
+                             uint32_t** rec_lengths)
+{
+    srwo_stacks st = {0};
+    srwo_recs out = {0};
+    int err = SRWO_OK;
+    for (int64_t r = 0; r < nrows && !err; r++) {
+        int64_t k = rows[r];
+        if (k < 0 || k >= n) { err = SRWO_E_ARG; break; }
+        if (!(tau[k] > 0.0)) continue;
+        for (int64_t w = 0; w < budget[r] && !err; w++)
+            err = srwo_walk_reuse(rowptr, nbr, thr, mthr, grounded, rank, seed, k, w, &st, &out);
+    }
+    stacks_free(&st);
+    if (err) {
+        free(out.r);
+        return err;
+    }
+    const int64_t m = out.n;
+    const size_t cnt = (size_t)(m > 0 ? m : 1);
+    int32_t* a = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    int32_t* b = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    uint32_t* c = (uint32_t*)malloc(sizeof(uint32_t) * cnt);
+    uint32_t* d = (uint32_t*)malloc(sizeof(uint32_t) * cnt);
+    if (!a || !b || !c || !d) {
+        free(a); free(b); free(c); free(d); free(out.r);
+        return SRWO_E_NOMEM;
+    }
+    for (int64_t i = 0; i < m; i++) {
+        a[i] = out.r[i].row;
+        b[i] = out.r[i].end;
+        c[i] = out.r[i].visits;
+        d[i] = out.r[i].length;
+    }
+    free(out.r);
+    *rec_rows = a;
+    *rec_ends = b;
+    *rec_visits = c;
+    *rec_lengths = d;
+    return m;
+}
+
+void srwo_free(void* p) { free(p); }
 
 /* ------------------------------------------------------------------------- */
 /* Tallies (Section 3.1, reduced journey record of Section 3.1/3.3).         */

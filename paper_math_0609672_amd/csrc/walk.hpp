@@ -8,7 +8,7 @@
 // first line: [0] rank, [1] degree | grounded flag, [2] node id, [3] the line of the
 // record of the neighbour taken when the draw passes every threshold (the last one).
 // Every off-diagonal entry m (CSR order) is a pair: the threshold floor(2^32 c_m / a_v)
-// and the line of the neighbour's record.
+// and the line of the neighbour's record.  Unused words of a record's lines are 0.
 //   degree <= 6: the pairs sit in words 4 + 2m, 5 + 2m of the first line.  The record
 //     is one line, so a walk step is one dependent 64-byte load: the next node's
 //     record, whose header holds the rank for the home test and the node id to record
@@ -105,6 +105,10 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
     if (wide) {
         wide_summary(rec, m);
         wide_summary(srec, m);
+        for (uint32_t q = 16 + 2 * m; q % REC_WORDS != 0; ++q) {
+            rec[q] = 0u;
+            srec[q] = 0u;
+        }
     } else {
         for (uint32_t q = 4 + 2 * m; q < REC_WORDS; ++q) {
             rec[q] = 0u;

@@ -86,6 +86,15 @@ typedef struct {
     int32_t solve_order;       /* order in which the triangular solves take rows:
                                   0 = rank; 1 (default) = dependency level, then rank
                                   (the build computes the levels once)              */
+    int32_t reuse;             /* 1 = walk reuse (Section 5.3, Algorithm "reuse"):
+                                  every walk also counts, for their start nodes, the
+                                  walks its two stacks extract (disjoint segments of
+                                  at least two steps that end below their start);
+                                  the tallies of a row then hold its own walks plus
+                                  those.  Needs refill_period 0 or 8 and keep <= 1;
+                                  not for batched builds.  A walk keeps at most 64
+                                  open segments (else SRW_E_WALK_LIMIT, see
+                                  srw_last_error).  0 (default) = off               */
 } srw_options;
 
 void srw_default_options(srw_options* opt);
@@ -148,6 +157,9 @@ typedef struct {
     int32_t levels_fwd, levels_bwd; /* dependency depth, -1 until srw_factor_depth  */
     int32_t precision, keep;
     double phase_ms[SRW_NUM_PHASES]; /* milliseconds, -1 when not profiled           */
+    int64_t tallied_walks; /* walks in the tallies: = walks, or with walk reuse the
+                              simulated walks plus the extracted ones              */
+    int32_t reuse;         /* srw_options.reuse of the build                        */
 } srw_stats;
 
 /* Counters and (if profiled) phase times of a factor; host output. */
@@ -178,7 +190,8 @@ int srw_table_export(const srw_factor* F, int32_t* nbr, uint32_t* thr, uint32_t*
  * included), G uint32[n] (walks ended at ground), steps uint64[n], visits_sq
  * uint64[n], h_off int64[n] and hlen int32[n]: the distinct end nodes of row k and
  * their counts H'_{k,i} sit at h_end / h_cnt[h_off[k] .. h_off[k] + hlen[k]) in
- * ascending node id; h_end / h_cnt hold `walks` entries in total (see info).
+ * ascending node id; h_end / h_cnt hold srw_stats.tallied_walks entries in total.
+ * With walk reuse, `walks` counts the row's own walks and the extracted ones.
  * Any pointer may be NULL. */
 int srw_tally_export(const srw_factor* F, uint32_t* walks, uint64_t* J, uint32_t* G,
                      uint64_t* steps, uint64_t* visits_sq, int64_t* h_off, int32_t* hlen,

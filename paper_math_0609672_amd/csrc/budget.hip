@@ -480,7 +480,7 @@ int labels_impl(const srw_factor* F, int per_step, double* label, hipStream_t s)
 {
     if (F->n == 0) return SRW_OK;
     k_labels<<<(unsigned)F->n, 64, 0, s>>>(F->n, F->tau, F->budget, F->tJ, F->tvsq, F->tsteps,
-                                           per_step, F->rec_off, F->hlen, F->h_cnt, label);
+                                           per_step, F->h_off, F->hlen, F->h_cnt, label);
     SRW_HIP(hipGetLastError());
     SRW_HIP(hipStreamSynchronize(s));
     return SRW_OK;

@@ -25,7 +25,7 @@ namespace {
 
 constexpr int BLOCK = 256;
 
-enum : int { ERR_ARG = 1, ERR_NOT_R = 2, ERR_SINGULAR = 4, ERR_LIMIT = 8 };
+enum : int { ERR_ARG = 1, ERR_NOT_R = 2, ERR_SINGULAR = 4, ERR_LIMIT = 8, ERR_STACK = 16 };
 
 // ------------------------------------------------------------------- validation
 __global__ void k_check_structure(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
@@ -196,6 +196,7 @@ __global__ void k_rank_given(int64_t n, const int32_t* __restrict__ given, int32
 // remaining rows by node id into eight slabs, one per XCD, so the walks in flight on
 // one XCD share a compact part of the graph and of that XCD's L2.
 constexpr int NSLAB = 8;
+constexpr uint32_t REUSE_STACK = 64;  // walk reuse: stack entries per lane
 constexpr int NSEG = NSLAB + 1;
 
 __global__ void k_flag_long(int64_t n, int64_t long_rank, const int32_t* __restrict__ by_rank,
@@ -381,6 +382,107 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
         h_cnt[base + j] = (j + 1 < run ? head[j + 1] : (uint32_t)nb) - head[j];
     }
     if (lane == 0) {
+        J[k] = jv;
+        G[k] = g;
+        steps[k] = sl;
+        vsq[k] = vq;
+        hlen[k] = run;
+    }
+}
+
+// ------------------------------------------------------- tallies, walk reuse
+// With walk reuse every counted walk is a record {start node << 32 | end node, stays,
+// steps}; the records are sorted by key, so a row's records are contiguous with
+// ascending end node (ground last).
+__global__ void k_iota_u32(int64_t n, uint32_t* x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (uint32_t)i;
+}
+
+// beg[k] = first record of row k (k = 0..n; beg[n] = m), by binary search
+__global__ void k_row_begin(int64_t n, const uint64_t* __restrict__ key, int64_t m,
+                            int64_t* __restrict__ beg)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n) return;
+    const uint64_t want = (uint64_t)k << 32;
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (key[mid] < want) lo = mid + 1;
+        else hi = mid;
+    }
+    beg[k] = lo;
+}
+
+__global__ void k_row_count(int64_t n, const int64_t* __restrict__ beg, int32_t* __restrict__ cnt)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) cnt[k] = (int32_t)(beg[k + 1] - beg[k]);
+}
+
+// One wave per row over its sorted records: the sums of k_tally and the H list
+// (distinct end nodes, ascending, with counts) written from beg[k] on.  A run of equal
+// end nodes starts at a head; the count of a run is the distance from its head to
+// the next head (or to the first ground record).
+__global__ __launch_bounds__(64) void k_tally_sorted(
+    int64_t n, const int64_t* __restrict__ beg, const uint64_t* __restrict__ key,
+    const uint32_t* __restrict__ idx, const uint2* __restrict__ vl, uint64_t* __restrict__ J,
+    uint32_t* __restrict__ G, uint64_t* __restrict__ steps, uint64_t* __restrict__ vsq,
+    int32_t* __restrict__ hlen, uint32_t* __restrict__ h_end, uint32_t* __restrict__ h_cnt)
+{
+    const int64_t k = blockIdx.x;
+    if (k >= n) return;
+    const int lane = threadIdx.x;
+    const uint64_t lt = lanemask_lt();
+    const int64_t b = beg[k], e = beg[k + 1];
+    uint64_t jv = 0, sl = 0, vq = 0;
+    uint32_t g = 0;
+    int run = 0;             // runs so far
+    int last_head = -1;      // offset of the last head so far
+    uint32_t prev_end = 0;   // end node of the record before this chunk
+    for (int64_t i0 = b; i0 < e; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const bool in = i < e;
+        uint32_t en = END_GROUND;
+        if (in) {
+            en = (uint32_t)key[i];
+            const uint2 x = vl[idx[i]];
+            jv += x.x;
+            vq += (uint64_t)x.x * x.x;
+            sl += x.y;
+            g += (en == END_GROUND);
+        }
+        uint32_t pe = (uint32_t)__shfl_up((int)en, 1);
+        if (lane == 0) pe = prev_end;
+        const bool head = in && en != END_GROUND && (i == b || en != pe);
+        const uint64_t mask = ballot(head);
+        // offset of the nearest head at or below each lane (inclusive running max)
+        int hv = head ? (int)(i - b) : -1;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(hv, d);
+            if (lane >= d) hv = max(hv, o);
+        }
+        int below = __shfl_up(hv, 1);
+        if (lane == 0) below = -1;
+        below = max(below, last_head);
+        if (head) {
+            const int r = run + (int)__popcll(mask & lt);
+            h_end[b + r] = en;
+            if (r > 0) h_cnt[b + r - 1] = (uint32_t)((int)(i - b) - below);
+        }
+        run += (int)__popcll(mask);
+        last_head = max(last_head, __shfl(hv, 63));
+        prev_end = (uint32_t)__shfl((int)en, 63);
+    }
+    jv = wave_sum(jv);
+    vq = wave_sum(vq);
+    sl = wave_sum(sl);
+    g = wave_sum(g);
+    if (lane == 0) {
+        const int nb = (int)(e - b) - (int)g;
+        if (run > 0) h_cnt[b + run - 1] = (uint32_t)(nb - last_head);
         J[k] = jv;
         G[k] = g;
         steps[k] = sl;
@@ -575,6 +677,10 @@ int map_err(int e)
     if (e & ERR_NOT_R) return SRW_E_NOT_RMATRIX;
     if (e & ERR_SINGULAR) return SRW_E_SINGULAR;
     if (e & ERR_LIMIT) return SRW_E_WALK_LIMIT;
+    if (e & ERR_STACK) {
+        set_last_error("walk reuse: a walk's stack of open walks grew past its capacity");
+        return SRW_E_WALK_LIMIT;
+    }
     return SRW_OK;
 }
 
@@ -644,6 +750,7 @@ int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt_in, do
     opt.walks = budget;
     opt.keep = 0;
     opt.profile = 0;
+    opt.reuse = 0;
     while (e == hipSuccess && status == SRW_OK) {
         k_rule_budgets<<<g, BLOCK, 0, s>>>(n, walks, target, budget);
         LengthRule rule{delta, z, min_walks, found};
@@ -734,10 +841,16 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
     if (opt_in) opt = *opt_in;
     if (opt.max_steps == 0) opt.max_steps = 1ull << 22;
     if (opt.refill_period == 0) opt.refill_period = 8;
+    // walk reuse: one instance of the walk kernel (refill period 8); its records
+    // replace the per-walk records, which it cannot export; not for batches or
+    // walks-only builds
+    const bool reuse = opt.reuse != 0;
+    if (reuse && (opt.refill_period != 8 || opt.keep >= 2 || batch || rule)) return SRW_E_ARG;
     const int64_t n = A->n, nnz = A->nnz;
     const int64_t nnz_off = nnz - n;
 
     srw_factor* F = new srw_factor();
+    F->reuse = reuse ? 1 : 0;
     F->n = n;
     F->nnz_a = nnz;
     F->precision = opt.factor_precision;
@@ -933,12 +1046,23 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipGetLastError());
 
         // ---- 4. walks
-        uint32_t* rec_end = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
-        uint32_t* rec_vis = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
-        uint32_t* rec_len = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
-        unsigned long long* queue = ALLOC(tmp, unsigned long long, NSEG + 1);
-        if (!rec_end || !rec_vis || !rec_len || !queue) FAIL(SRW_E_NOMEM);
-        CHECK_HIP(hipMemsetAsync(queue, 0, (NSEG + 1) * sizeof(unsigned long long), s));
+        // per-walk records (not with walk reuse, whose records are the counted walks)
+        uint32_t* rec_end = nullptr;
+        uint32_t* rec_vis = nullptr;
+        uint32_t* rec_len = nullptr;
+        if (!reuse) {
+            rec_end = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
+            rec_vis = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
+            rec_len = ALLOC((opt.keep >= 2 ? keep : tmp), uint32_t, total_walks);
+            if (!rec_end || !rec_vis || !rec_len) FAIL(SRW_E_NOMEM);
+        }
+        // segment queues, degree sum, then (walk reuse) record count and step sum
+        unsigned long long* queue = ALLOC(tmp, unsigned long long, NSEG + 3);
+        if (!queue) FAIL(SRW_E_NOMEM);
+        CHECK_HIP(hipMemsetAsync(queue, 0, (NSEG + 3) * sizeof(unsigned long long), s));
+        uint64_t* out_key = nullptr;
+        uint2* out_vl = nullptr;
+        int64_t n_slots = 0;  // walk reuse: record slots taken (records and unused slots)
         if (opt.keep >= 2) {
             F->rec_end = rec_end;
             F->rec_vis = rec_vis;
@@ -962,19 +1086,62 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             // persistent grid: as many blocks as fit on the chip at once
             void (*kern)(WalkArgs) = nullptr;
-            switch (opt.refill_period) {
-                case 2: kern = k_walk<2>; break;
-                case 4: kern = k_walk<4>; break;
-                case 8: kern = k_walk<8>; break;
-                default: kern = k_walk<1>; break;
+            if (reuse) {
+                kern = k_walk_reuse;
+            } else {
+                switch (opt.refill_period) {
+                    case 2: kern = k_walk<2>; break;
+                    case 4: kern = k_walk<4>; break;
+                    case 8: kern = k_walk<8>; break;
+                    default: kern = k_walk<1>; break;
+                }
             }
             int per_cu = 0;
             CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
             int64_t blocks = (int64_t)cus * std::max(1, per_cu);
             blocks = std::min<int64_t>(blocks, (n_chunks + BLOCK / 64 - 1) / (BLOCK / 64));
             if (blocks < 1) blocks = 1;
-            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, wa);
-            CHECK_HIP(hipGetLastError());
+            if (!reuse) {
+                hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, wa);
+                CHECK_HIP(hipGetLastError());
+            } else {
+                wa.stack_depth = REUSE_STACK;
+                wa.stack = ALLOC(tmp, uint4, blocks * BLOCK * REUSE_STACK);
+                wa.nrec = queue + NSEG + 1;
+                wa.steps_sum = queue + NSEG + 2;
+                if (!wa.stack) FAIL(SRW_E_NOMEM);
+                // record buffers sized by a first guess; if the walks take more slots,
+                // they run again (same draws, same records) into larger buffers
+                const int64_t slack = 2 * blocks * (BLOCK / 64) * (int64_t)REUSE_CHUNK;
+                int64_t cap = 12 * total_walks + slack;
+                for (int pass = 0;; ++pass) {
+                    out_key = ALLOC(tmp, uint64_t, cap);
+                    out_vl = ALLOC(tmp, uint2, cap);
+                    if (!out_key || !out_vl) FAIL(SRW_E_NOMEM);
+                    wa.out_key = out_key;
+                    wa.out_vl = out_vl;
+                    wa.out_cap = (unsigned long long)cap;
+                    if (pass > 0)
+                        CHECK_HIP(hipMemsetAsync(queue, 0, (NSEG + 3) * sizeof(unsigned long long), s));
+                    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, wa);
+                    CHECK_HIP(hipGetLastError());
+                    CHECK_HIP(hipMemcpyAsync(&pinned[6], queue + NSEG + 1, 2 * sizeof(int64_t),
+                                             hipMemcpyDeviceToHost, s));
+                    CHECK_HIP(hipMemcpyAsync(&pinned[0], err, sizeof(int), hipMemcpyDeviceToHost, s));
+                    CHECK_HIP(hipStreamSynchronize(s));
+                    std::memcpy(&herr, &pinned[0], sizeof(int));
+                    if (herr) FAIL(map_err(herr));
+                    n_slots = pinned[6];
+                    if (n_slots <= cap) break;
+                    if (pass >= 2) {
+                        set_last_error("walk reuse: record slots kept outgrowing their buffer");
+                        FAIL(SRW_E_HIP);
+                    }
+                    cap = n_slots + slack;
+                }
+                if (n_slots >= (int64_t)UINT32_MAX) FAIL(SRW_E_ARG);  // slot indices are 32-bit
+                F->steps_total = pinned[7];
+            }
         }
         mark(5);
         CHECK_HIP(hipMemcpyAsync(&pinned[5], queue + NSEG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1002,11 +1169,39 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         // records or the lists outlive the build
         uint32_t* h_end = rec_end;
         uint32_t* h_cnt = rec_vis;
-        if (opt.keep >= 1) {
-            h_end = ALLOC(keep, uint32_t, total_walks);
-            h_cnt = ALLOC(keep, uint32_t, total_walks);
+        int64_t* h_off = rec_off;
+        int64_t tallied = total_walks;
+        uint64_t* ko = out_key;
+        uint32_t* vo = nullptr;
+        if (reuse) {
+            // sort the record slots by (start node, end node), unused slots last; the
+            // first slot of every row, and so the number of records, by binary search
+            h_off = ALLOC(keep, int64_t, n + 1);
+            uint64_t* key2 = ALLOC(tmp, uint64_t, n_slots);
+            uint32_t* idx = ALLOC(tmp, uint32_t, n_slots);
+            uint32_t* idx2 = ALLOC(tmp, uint32_t, n_slots);
+            void* rt = ALLOC(tmp, char, radix_tmp_bytes(n_slots));
+            if (!h_off || !key2 || !idx || !idx2 || !rt) FAIL(SRW_E_NOMEM);
+            int rbits = 1;  // 2^rbits > n: a record's key stays below an unused slot's
+            while (rbits < 31 && ((int64_t)1 << rbits) <= n) ++rbits;
+            vo = idx;
+            if (n_slots > 0) {
+                k_iota_u32<<<grid_for(n_slots, BLOCK), BLOCK, 0, s>>>(n_slots, idx);
+                CHECK_HIP(radix_sort_u64(out_key, idx, key2, idx2, n_slots, 32 + rbits, rt, &ko,
+                                         &vo, s));
+            }
+            k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, n_slots, h_off);
+            CHECK_HIP(hipMemcpyAsync(&pinned[0], h_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            tallied = pinned[0];
+        }
+        if (opt.keep >= 1 || reuse) {
+            h_end = ALLOC((opt.keep >= 1 ? keep : tmp), uint32_t, tallied);
+            h_cnt = ALLOC((opt.keep >= 1 ? keep : tmp), uint32_t, tallied);
         }
         if (!tJ || !tG || !tsteps || !tvsq || !hlen || !h_end || !h_cnt) FAIL(SRW_E_NOMEM);
+        F->h_off = h_off;
+        F->tallied_total = tallied;
         F->tJ = tJ;
         F->tG = tG;
         F->tsteps = tsteps;
@@ -1014,7 +1209,14 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         F->hlen = hlen;
         F->h_end = h_end;
         F->h_cnt = h_cnt;
-        if (max_budget > 0) {
+        if (reuse) {
+            // one wave per row over its sorted records; the walks per row become the
+            // counted walks
+            k_row_count<<<g, BLOCK, 0, s>>>(n, h_off, budget);
+            k_tally_sorted<<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
+                n, h_off, ko, vo, out_vl, tJ, tG, tsteps, tvsq, hlen, h_end, h_cnt);
+            CHECK_HIP(hipGetLastError());
+        } else if (max_budget > 0) {
             int P = 64;
             while (P < max_budget) P <<= 1;
             const size_t lds = (size_t)(2 * P) * sizeof(uint32_t);
@@ -1041,7 +1243,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (!ynnz) FAIL(SRW_E_NOMEM);
         mark(6);
         k_factor<double, false><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
-                                                    budget, tJ, rec_off, hlen, h_end, h_cnt,
+                                                    budget, tJ, h_off, hlen, h_end, h_cnt,
                                                     drop_tol, ynnz, nullptr, nullptr, nullptr,
                                                     nullptr);
         CHECK_HIP(exclusive_scan_i32_to_i64(ynnz, F->yptr, n, st, s));
@@ -1049,7 +1251,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipStreamSynchronize(s));
         const int64_t nnz_y = pinned[0];
-        F->steps_total = pinned[4];
+        if (!reuse) F->steps_total = pinned[4];
         F->nnz_y = nnz_y;
         if (nnz_y >= (int64_t)0xFFFFFFFFll) FAIL(SRW_E_ARG);
         k_set_last<<<1, 1, 0, s>>>(F->yptr, n, nnz_y);
@@ -1059,12 +1261,12 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (!F->ycol || !F->yval || !F->d) FAIL(SRW_E_NOMEM);
         if (fp32)
             k_factor<float, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
-                                                     budget, tJ, rec_off, hlen, h_end, h_cnt,
+                                                     budget, tJ, h_off, hlen, h_end, h_cnt,
                                                      drop_tol, nullptr, F->yptr, F->ycol,
                                                      (float*)F->yval, (float*)F->d);
         else
             k_factor<double, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
-                                                      budget, tJ, rec_off, hlen, h_end, h_cnt,
+                                                      budget, tJ, h_off, hlen, h_end, h_cnt,
                                                       drop_tol, nullptr, F->yptr, F->ycol,
                                                       (double*)F->yval, (double*)F->d);
         CHECK_HIP(hipGetLastError());
@@ -1207,8 +1409,8 @@ done:
     }
     if (opt.keep < 1) {
         // drop what only export needs
-        void* drop[] = {F->ent, F->mthr, F->tau, F->grounded, F->budget, F->rec_off, F->tJ, F->tG,
-                        F->tsteps, F->tvsq, F->hlen};
+        void* drop[] = {F->ent, F->mthr, F->tau, F->grounded, F->budget, F->rec_off, F->h_off,
+                        F->tJ, F->tG, F->tsteps, F->tvsq, F->hlen};
         for (void* p : drop) {
             auto it = std::find(keep.blocks.begin(), keep.blocks.end(), p);
             if (it != keep.blocks.end()) {
@@ -1217,7 +1419,8 @@ done:
             }
         }
         F->ent = nullptr; F->mthr = nullptr; F->tau = nullptr; F->grounded = nullptr;
-        F->budget = nullptr; F->rec_off = nullptr; F->tJ = nullptr; F->tG = nullptr;
+        F->budget = nullptr; F->rec_off = nullptr; F->h_off = nullptr; F->tJ = nullptr;
+        F->tG = nullptr;
         F->tsteps = nullptr; F->tvsq = nullptr; F->hlen = nullptr;
         F->h_end = nullptr; F->h_cnt = nullptr;
     }

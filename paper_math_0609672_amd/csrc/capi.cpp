@@ -36,6 +36,8 @@ int options_ok(const srw_options* opt, int64_t n)
     if (opt->schedule != 0 && opt->schedule != 1) return SRW_E_ARG;
     if (opt->solve_order != 0 && opt->solve_order != 1) return SRW_E_ARG;
     if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && n > 0) return SRW_E_ARG;
+    if (opt->reuse != 0 && opt->reuse != 1) return SRW_E_ARG;
+    if (opt->reuse && (opt->keep == 2 || (rp != 0 && rp != 8))) return SRW_E_ARG;
     return SRW_OK;
 }
 
@@ -56,6 +58,7 @@ void srw_default_options(srw_options* opt)
     opt->profile = 0;
     opt->schedule = 1;
     opt->solve_order = 1;
+    opt->reuse = 0;
 }
 
 
@@ -173,6 +176,8 @@ int srw_factor_stats(const srw_factor* F, srw_stats* out)
     out->precision = F->precision;
     out->keep = F->keep;
     for (int i = 0; i < SRW_NUM_PHASES; ++i) out->phase_ms[i] = F->phase_ms[i];
+    out->tallied_walks = F->tallied_total;
+    out->reuse = F->reuse;
     return SRW_OK;
 }
 
@@ -235,14 +240,14 @@ int srw_tally_export(const srw_factor* F, uint32_t* walks, uint64_t* J, uint32_t
     if (!F) return SRW_E_ARG;
     if (F->keep < 1) return SRW_E_ARG;
     hipStream_t s = as_stream(stream);
-    const size_t n = (size_t)F->n, W = (size_t)F->walks_total;
+    const size_t n = (size_t)F->n, W = (size_t)F->tallied_total;
     int st;
     if ((st = copy_out((int32_t*)walks, F->budget, n, s))) return st;
     if ((st = copy_out(J, F->tJ, n, s))) return st;
     if ((st = copy_out(G, F->tG, n, s))) return st;
     if ((st = copy_out(steps, F->tsteps, n, s))) return st;
     if ((st = copy_out(visits_sq, F->tvsq, n, s))) return st;
-    if ((st = copy_out(h_off, F->rec_off, n, s))) return st;
+    if ((st = copy_out(h_off, F->h_off, n, s))) return st;
     if ((st = copy_out(hlen, F->hlen, n, s))) return st;
     if ((st = copy_out((uint32_t*)h_end, F->h_end, W, s))) return st;
     if ((st = copy_out(h_cnt, F->h_cnt, W, s))) return st;

@@ -15,8 +15,11 @@ struct srw_factor {
     int32_t precision = SRW_FP64;
     int32_t keep = 0;
     int64_t nnz_y = 0;
-    int64_t walks_total = 0;
-    int64_t steps_total = 0;
+    int64_t walks_total = 0;       // simulated walks
+    int64_t steps_total = 0;       // their steps
+    int64_t tallied_total = 0;     // walks in the tallies (with walk reuse, the simulated
+                                   // walks plus those extracted from them)
+    int32_t reuse = 0;
     int64_t deg_sum = 0;
     double phase_ms[SRW_NUM_PHASES] = {-1, -1, -1, -1, -1, -1, -1, -1};
 
@@ -55,15 +58,16 @@ struct srw_factor {
     uint32_t* mthr = nullptr;      // [nnz-n]
     double* tau = nullptr;         // [n]
     uint8_t* grounded = nullptr;   // [n]
-    int32_t* budget = nullptr;     // [n] walks per row (0 = exact row)
-    int64_t* rec_off = nullptr;    // [n]
+    int32_t* budget = nullptr;     // [n] walks per row in the tallies (0 = exact row)
+    int64_t* rec_off = nullptr;    // [n] first walk record of each row
+    int64_t* h_off = nullptr;      // [n] first H-list entry of each row
     uint64_t* tJ = nullptr;        // [n]
     uint32_t* tG = nullptr;        // [n]
     uint64_t* tsteps = nullptr;    // [n]
     uint64_t* tvsq = nullptr;      // [n]
     int32_t* hlen = nullptr;       // [n]
-    uint32_t* h_end = nullptr;     // [walks_total]
-    uint32_t* h_cnt = nullptr;     // [walks_total]
+    uint32_t* h_end = nullptr;     // [tallied_total]
+    uint32_t* h_cnt = nullptr;     // [tallied_total]
     uint32_t* rec_end = nullptr;   // [walks_total]
     uint32_t* rec_vis = nullptr;   // [walks_total]
     uint32_t* rec_len = nullptr;   // [walks_total]

@@ -181,7 +181,75 @@ struct WalkArgs {
     unsigned long long* queue;
     unsigned long long* deg_sum;
     int* err;
+    // walk reuse: per-lane stacks of stack_depth entries {rank, node, position,
+    // stays}; counted walks go to out_key (start node << 32 | end node, END_GROUND for
+    // ground) and out_vl (stays, steps).  A wave takes slots in blocks of REUSE_CHUNK
+    // from *nrec and fills the slots it leaves unused with the key ~0 (sorts last);
+    // slots at or beyond out_cap are only counted.  *steps_sum collects the simulated
+    // steps.
+    uint4* stack;
+    uint32_t stack_depth;
+    uint64_t* out_key;
+    uint2* out_vl;
+    unsigned long long* nrec;
+    unsigned long long out_cap;
+    unsigned long long* steps_sum;
 };
+
+constexpr uint32_t REUSE_CHUNK = 4096;
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Emission of counted walks by the lanes currently executing (walk reuse).  The wave's
+// slot block [*next, *end) is the same in every lane that runs this; a lane with
+// `em` set writes one record.
+__device__ __forceinline__ void emit_walks(const WalkArgs& a, bool em, uint32_t row, uint32_t end,
+                                           uint32_t stays, uint32_t steps, uint64_t& next,
+                                           uint64_t& bend)
+{
+    const int lane = __lane_id();
+    const uint64_t lt = lanemask_lt();
+    const uint64_t act = ballot(true);
+    const uint64_t m = ballot(em);
+    if (m == 0) return;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    if (next + cnt > bend) {
+        // the rest of the block stays unused: mark it, then take a new block
+        const uint32_t na = (uint32_t)__popcll(act), me = (uint32_t)__popcll(act & lt);
+        for (uint64_t q = next + me; q < bend; q += na)
+            if (q < a.out_cap) a.out_key[q] = ~0ull;
+        const int leader = __ffsll((long long)act) - 1;
+        unsigned long long c = 0;
+        if (lane == leader) c = atomicAdd(a.nrec, (unsigned long long)REUSE_CHUNK);
+        c = shfl_u64(c, leader);
+        next = c;
+        bend = c + REUSE_CHUNK;
+    }
+    if (em) {
+        const uint64_t slot = next + (uint64_t)__popcll(m & lt);
+        if (slot < a.out_cap) {
+            a.out_key[slot] = ((uint64_t)row << 32) | end;
+            a.out_vl[slot] = make_uint2(stays, steps);
+        }
+    }
+    next += cnt;
+}
 
 // Persistent walk kernel.  Every wave owns up to 64 walks at a time, one per lane.
 // Every R steps the idle lanes of a wave take the next walks of the current chunk;
@@ -192,11 +260,20 @@ struct WalkArgs {
 // line of its current record in registers (at the start of a walk, the row's start
 // record); a step selects the entry from it (a wide record loads one more line),
 // then loads the next node's record line: one dependent 64-byte load per step.
+//
+// REUSE (Section 5.3, Algorithm "reuse"): a lane also keeps the two stacks of the
+// algorithm for its walk, as one stack of entries {rank, node, position, stays} whose
+// top lives in registers and the rest in the lane's own region of a.stack.  The start
+// is position 1 and the node reached by step t is position t + 2.  A node ranked
+// below the top pops it, and a popped entry pushed more than one position earlier is
+// a walk of at least two steps from its node: it is emitted as a record.  A node
+// ranked above the top is pushed, one equal to it is a stay.  The walk ends exactly
+// when the stack empties; the walk itself is the bottom entry's record.
 #ifndef SRW_WALK_WAVES
 #define SRW_WALK_WAVES 6  // waves per SIMD the register budget is cut for
 #endif
-template <int R>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_WAVES))) void k_walk(WalkArgs a)
+template <int R, bool REUSE>
+__device__ __forceinline__ void walk_body(const WalkArgs& a)
 {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
@@ -213,6 +290,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_
     uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;  // its words
     uint64_t t = 0, rec = 0, degsum = 0, seedw = 0;
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0, q7 = 0;
+    // REUSE: stack top, depth below it, the lane's stack region, simulated steps
+    uint32_t top_rank = 0, top_node = 0, top_pos = 0, top_vis = 0, depth = 0;
+    uint4* const my_stack =
+        REUSE ? a.stack + ((size_t)blockIdx.x * BLOCK + threadIdx.x) * a.stack_depth : nullptr;
+    uint64_t steps_acc = 0;
+    uint64_t blk_next = 0, blk_end = 0;  // the wave's block of record slots
 
     for (uint32_t iter = 0;; ++iter) {
         if ((iter % R) == 0 && !done) {
@@ -255,6 +338,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_
                     seedw = cd.seed;
                     rec = cd.rec + w;
                     cline = cd.sline;
+                    if constexpr (REUSE) {
+                        top_rank = cd.rank;
+                        top_node = cd.key;
+                        top_pos = 1;
+                        top_vis = 1;
+                        depth = 0;
+                    }
                     const uint4* lp = a.recs + (size_t)cline * 4;
                     r0 = lp[0];
                     r1 = lp[1];
@@ -341,6 +431,43 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_
         bool fin = to_ground || r0.x < rank_k;
         uint32_t endv = to_ground ? END_GROUND : r0.z;
         visits += (!fin && r0.x == rank_k);
+        if constexpr (REUSE) {
+            const uint32_t l = (uint32_t)t + 2;  // position of the node just reached
+            bool below = to_ground || r0.x < top_rank;
+            bool empty = false;
+            while (below) {
+                emit_walks(a, l > top_pos + 1, top_node, endv, top_vis, l - top_pos, blk_next,
+                           blk_end);
+                if (depth == 0) {
+                    empty = true;
+                    break;
+                }
+                --depth;
+                const uint4 e = my_stack[depth];
+                top_rank = e.x;
+                top_node = e.y;
+                top_pos = e.z;
+                top_vis = e.w;
+                below = to_ground || r0.x < top_rank;
+            }
+            if (!empty) {
+                if (r0.x > top_rank) {
+                    if (depth == a.stack_depth) {
+                        atomicOr(a.err, ERR_STACK);
+                        fin = true;
+                    } else {
+                        my_stack[depth] = make_uint4(top_rank, top_node, top_pos, top_vis);
+                        ++depth;
+                        top_rank = r0.x;
+                        top_node = r0.z;
+                        top_pos = l;
+                        top_vis = 1;
+                    }
+                } else {
+                    ++top_vis;
+                }
+            }
+        }
         ++t;
         if (!fin && t >= a.max_steps) {
             fin = true;
@@ -348,13 +475,41 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_
             atomicOr(a.err, ERR_LIMIT);
         }
         if (fin) {
-            a.rec_end[rec] = endv;
-            a.rec_vis[rec] = visits;
-            a.rec_len[rec] = (uint32_t)t;
+            if constexpr (REUSE) {
+                steps_acc += t;
+            } else {
+                a.rec_end[rec] = endv;
+                a.rec_vis[rec] = visits;
+                a.rec_len[rec] = (uint32_t)t;
+            }
             active = false;
         }
         }  // active
+        if constexpr (REUSE) {  // lanes that emitted moved the block on: agree again
+            blk_next = wave_max_u64(blk_next);
+            blk_end = wave_max_u64(blk_end);
+        }
+    }
+    if constexpr (REUSE) {
+        for (uint64_t q = blk_next + lane; q < blk_end; q += 64)
+            if (q < a.out_cap) a.out_key[q] = ~0ull;
     }
     degsum = wave_sum(degsum);
     if (lane == 0 && degsum) atomicAdd(a.deg_sum, (unsigned long long)degsum);
+    if constexpr (REUSE) {
+        steps_acc = wave_sum(steps_acc);
+        if (lane == 0 && steps_acc) atomicAdd(a.steps_sum, (unsigned long long)steps_acc);
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_WAVES))) void k_walk(WalkArgs a)
+{
+    walk_body<R, false>(a);
+}
+
+// walk reuse keeps the stack top in registers as well: a larger register budget
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_reuse(WalkArgs a)
+{
+    walk_body<8, true>(a);
 }

@@ -39,7 +39,7 @@ class _Options(ctypes.Structure):
                 ("factor_precision", ctypes.c_int32), ("max_steps", ctypes.c_uint64),
                 ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("solve_order", ctypes.c_int32)]
+                ("solve_order", ctypes.c_int32), ("reuse", ctypes.c_int32)]
 
 
 NUM_PHASES = 8
@@ -51,7 +51,8 @@ class _Stats(ctypes.Structure):
                 ("walks", ctypes.c_int64), ("walk_steps", ctypes.c_int64),
                 ("walk_deg_sum", ctypes.c_int64), ("levels_fwd", ctypes.c_int32),
                 ("levels_bwd", ctypes.c_int32), ("precision", ctypes.c_int32), ("keep", ctypes.c_int32),
-                ("phase_ms", ctypes.c_double * NUM_PHASES)]
+                ("phase_ms", ctypes.c_double * NUM_PHASES), ("tallied_walks", ctypes.c_int64),
+                ("reuse", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -208,8 +209,7 @@ class Factor:
         return out
 
     def tallies(self, stream=None) -> dict:
-        i = self.info()
-        n, W = i["n"], i["walks"]
+        n, W = self.info()["n"], self.stats()["tallied_walks"]
         kw = dict(device=self.device)
         out = dict(walks=torch.empty(n, dtype=torch.int32, **kw), J=torch.empty(n, dtype=torch.int64, **kw),
                    G=torch.empty(n, dtype=torch.int32, **kw), steps=torch.empty(n, dtype=torch.int64, **kw),
@@ -247,8 +247,9 @@ def _check(st: int, what: str):
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
                  profile: bool = False, schedule: int = 1, solve_order: int = 1,
-                 stream=None) -> Factor:
-    """srw_build_factor: the random-walk incomplete LDL^T factor of A."""
+                 reuse: bool = False, stream=None) -> Factor:
+    """srw_build_factor: the random-walk incomplete LDL^T factor of A (with reuse, the
+    walks extracted by Algorithm "reuse" of Section 5.3 join the tallies)."""
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
     if rank is not None:
@@ -263,6 +264,7 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
     opt.profile = 1 if profile else 0
     opt.schedule = int(schedule)
     opt.solve_order = int(solve_order)
+    opt.reuse = 1 if reuse else 0
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),

@@ -73,3 +73,30 @@ def test_budget_entry_points_reject_bad_arguments_without_gpu():
     assert lib.srw_mlp_forward(fake, None, fake, 4, fake, None) == -1
     assert lib.srw_budget_labels(None, 0, fake, None) == -1
     assert lib.srw_row_features(None, fake, fake, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsrw.so not built")
+def test_walk_reuse_options_rejected_without_gpu():
+    """srw_options.reuse: only 0 or 1, and not with per-walk records (keep = 2) or a
+    refill period other than 8; checked before any device call."""
+    from paper_math_0609672_amd import srw
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+
+    class Csr(ctypes.Structure):
+        _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", P), ("col", P),
+                    ("val", P)]
+
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the option checks fail first
+    A = Csr(4, 4, fake, fake, fake)
+    out = ctypes.c_void_p(0)
+    for fields in (dict(reuse=2), dict(reuse=-1), dict(reuse=1, keep=2),
+                   dict(reuse=1, refill_period=4), dict(reuse=1, refill_period=1)):
+        opt = srw._Options()
+        lib.srw_default_options(ctypes.byref(opt))
+        assert opt.reuse == 0
+        for k, v in fields.items():
+            setattr(opt, k, v)
+        st = lib.srw_build_factor(ctypes.byref(A), 8, ctypes.c_double(0.0), ctypes.c_uint64(0),
+                                  ctypes.byref(opt), ctypes.byref(out), None)
+        assert st == -1, fields

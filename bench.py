@@ -65,6 +65,11 @@ def parse():
     ap.add_argument("--compare-precision", action="store_true",
                     help="after the timed steps, run one step with the other factor precision "
                          "(fp32 <-> fp64) and report it under ext_precision")
+    ap.add_argument("--walks", type=int, default=0,
+                    help="walks per row instead of the workload's (0 keeps the workload's)")
+    ap.add_argument("--reuse", action="store_true",
+                    help="walk reuse (Section 5.3): the walks extracted from every walk join "
+                         "the tallies of their start rows")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, copy a buffer of this many MiB three times with an "
                          "elementwise kernel (known traffic, for scaling hardware byte counters)")
@@ -149,6 +154,8 @@ def main():
     from paper_math_0609672_amd import metrics, srw, workloads
 
     gen, gkw, walks, drop, tol = WORKLOADS[args.workload]
+    if args.walks > 0:
+        walks = args.walks
     if gen == "laplace3d_dirichlet":
         A = workloads.laplace3d_dirichlet(**gkw)
     else:
@@ -167,7 +174,8 @@ def main():
             budgets = srw.adaptive_budgets(M, args.seed, args.adaptive, alpha=0.99)
         F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
                              refill_period=args.refill, schedule=args.schedule,
-                             solve_order=args.solve_order, profile=True, walks=budgets)
+                             solve_order=args.solve_order, profile=True, walks=budgets,
+                             reuse=args.reuse)
         t1 = time.perf_counter()
         st, _, it, rel = srw.pcg_solve(M, F, b, tol, 10000, x=x)
         t2 = time.perf_counter()
@@ -195,12 +203,14 @@ def main():
     s0 = runs[-1]["stats"]
     F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
                          refill_period=args.refill, schedule=args.schedule,
-                         solve_order=args.solve_order)
+                         solve_order=args.solve_order, reuse=args.reuse)
     depth = F.depth()  # reported only; outside the timed steps
     F.free()
     walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in runs) / K
     steps_per_build = s0["walk_steps"]
     walk_bytes = 12.0 * steps_per_build + 8.0 * s0["walk_deg_sum"]
+    if args.reuse:  # plus one 16-byte record per counted walk
+        walk_bytes += 16.0 * s0["tallied_walks"]
     achieved = walk_bytes / (walk_ms * 1e-3) / 1e9
     build_s = sum(r["build_s"] for r in runs) / K
     pcg_s = sum(r["pcg_s"] for r in runs) / K
@@ -226,6 +236,7 @@ def main():
             "workload": f"{args.workload}: {gen}{gkw or ''}, n={N}, nnz={E}, "
                         + (f"Section 5.1 walks (delta {args.adaptive}, alpha 0.99)" if args.adaptive > 0
                            else f"{walks} walks/row")
+                        + (", walk reuse (Section 5.3)" if args.reuse else "")
                         + f", drop {drop}, tol {tol}, seed {args.seed}",
             "global_batch": 1,
             "parallelism": "single GPU",
@@ -233,6 +244,7 @@ def main():
         "walk_steps_per_s": round(steps_per_build / (walk_ms * 1e-3), 1),
         "walk_steps": steps_per_build,
         "walks": s0["walks"],
+        "tallied_walks": s0["tallied_walks"],
         "build_s": round(build_s, 4),
         "pcg_s": round(pcg_s, 4),
         "pcg_iters": iters,
@@ -245,7 +257,7 @@ def main():
         "solve_depth": depth,
         "phase_ms": phases,
         "roofline": {
-            "kernel": "k_walk",
+            "kernel": "k_walk_reuse" if args.reuse else "k_walk",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -289,7 +301,10 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 x {args.copy_calibration} MiB read + written by one kernel")
         del src, dst
-    out["roofline"]["traffic"] = measured_traffic(args.workload, args.precision)
+    # counters were taken on the workload's own walk budget
+    default_walks = not (args.reuse or args.walks or args.adaptive > 0)
+    out["roofline"]["traffic"] = (measured_traffic(args.workload, args.precision)
+                                  if default_walks else None)
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(A, walks, args.seed, args.cpu_seconds)

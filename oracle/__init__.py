@@ -10,6 +10,9 @@ one row and one walk at a time) and in ``dense.py`` (numpy closed forms used as 
 and 5.2), tallies (Section 3.1), factor entries by eqs. newy / newz / d, the optional
 drop (Section 4), then PCG (Section 6).  With ``reuse=True`` the walks also feed the
 walks Algorithm "reuse" extracts from them into the tallies (Section 5.3).
+``build_factor_ldu``, ``apply_ldu`` and ``bicgstab`` are the asymmetric case of Section
+7.1: the games of A and of A^T with one ordering give the LDU of rev(A), used as the
+preconditioner of BiCGSTAB (Barrett et al., Templates).
 """
 from __future__ import annotations
 
@@ -61,6 +64,9 @@ def lib():
         L.srwo_walk_rows_reuse.argtypes = [i64, P, P, P, P, P, P, P, u64, i64, P, P, PP, PP, PP, PP]
         L.srwo_walk_rows_reuse.restype = i64
         L.srwo_free.argtypes = [P]
+        L.srwo_validate_asym.argtypes = [i64, P, P, P]
+        L.srwo_apply_ldu.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P]
+        L.srwo_bicgstab.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, dbl, i32, P, P, P]
         L.srwo_factor.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, dbl, P, P, P, P]
         L.srwo_apply.argtypes = [i64, P, P, P, P, P, P, P, P]
         L.srwo_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, dbl, i32, P, P, P]
@@ -384,3 +390,82 @@ def adaptive_budgets(A, rk, tb: Table, seed: int, delta: float, z: float, min_wa
                 break
             target = min(2 * target, max_walks)
     return out
+
+
+# ------------------------------------------------------- asymmetric A (Section 7.1)
+@dataclass
+class Csr:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.size)
+
+
+def transpose(A) -> Csr:
+    """A^T in CSR with sorted columns (scipy's transpose)."""
+    import scipy.sparse as sp
+
+    T = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n)).T.tocsr()
+    T.sort_indices()
+    return Csr(A.n, T.indptr.astype(np.int64), T.indices.astype(np.int32), T.data.astype(np.float64))
+
+
+def validate_asym(A) -> int:
+    return int(lib().srwo_validate_asym(A.n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)),
+                                        _p(_c(A.val, np.float64))))
+
+
+@dataclass
+class LduFactor:
+    """Preconditioner of an asymmetric A from two games with one ordering: `a` from the
+    game of A (Y_A, D: eqs. y2 and d), `t` from the game of A^T (Y_T: eq. y3).  In rank
+    order A ~ Y_T^T D Y_A, the reversed LDU of rev(A)."""
+    a: Factor
+    t: Factor
+
+    @property
+    def n(self) -> int:
+        return self.a.n
+
+
+def build_factor_ldu(A, walks_per_row, drop_tol: float, seed: int, rk=None,
+                     reuse: bool = False) -> LduFactor:
+    """Both games of Section 7.1 with the ordering of `seed` (or `rk`) and the same walk
+    draws (so for a symmetric A the two factors coincide)."""
+    rk = rank(A.n, seed) if rk is None else np.asarray(rk, np.int32)
+    Fa = build_factor(A, walks_per_row, drop_tol, seed, rk=rk, reuse=reuse)
+    Ft = build_factor(transpose(A), walks_per_row, drop_tol, seed, rk=rk, reuse=reuse)
+    return LduFactor(Fa, Ft)
+
+
+def _ldu_ptrs(F: LduFactor):
+    def nz(a, dt):
+        return a if a.size else np.zeros(1, dt)
+    return (_p(F.a.yptr), _p(nz(F.a.ycol, np.int32)), _p(nz(F.a.yval, np.float64)), _p(F.a.d),
+            _p(F.t.yptr), _p(nz(F.t.ycol, np.int32)), _p(nz(F.t.yval, np.float64)),
+            _p(F.a.by_rank))
+
+
+def apply_ldu(F: LduFactor, r: np.ndarray) -> np.ndarray:
+    z = np.zeros(max(F.n, 1))
+    work = np.zeros(max(F.n, 1))
+    lib().srwo_apply_ldu(F.n, *_ldu_ptrs(F), _p(_c(r, np.float64)), _p(z), _p(work))
+    return z[: F.n]
+
+
+def bicgstab(A, F: LduFactor | None, b: np.ndarray, tol: float, max_iter: int = 10000):
+    """Preconditioned BiCGSTAB; returns (status, x, iters, rel_res); F = None runs it
+    unpreconditioned."""
+    n = A.n
+    x = np.zeros(max(n, 1))
+    iters = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    y = (None,) * 8 if F is None else _ldu_ptrs(F)
+    st = lib().srwo_bicgstab(n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)),
+                             _p(_c(A.val, np.float64)), *y, _p(_c(b, np.float64)), float(tol),
+                             int(max_iter), _p(x), ctypes.byref(iters), ctypes.byref(rel))
+    return int(st), x[:n], int(iters.value), float(rel.value)

@@ -22,7 +22,9 @@
  *   - factor entries by eqs. newy and newz, the diagonal by eq. d (Sections 3.3 and
  *     5.2), then the optional drop of small entries (Section 4, footnote);
  *   - the hybrid solver: PCG with the preconditioner (L D L^T)^{-1} (Algorithm 1),
- *     stopped on ||b - Ax||_2 < tol ||b||_2 (Section 6).
+ *     stopped on ||b - Ax||_2 < tol ||b||_2 (Section 6);
+ *   - asymmetric A (Section 7.1): the games of A and of A^T with one ordering give the
+ *     LDU of rev(A) (eqs. y2, y3, d), the preconditioner of BiCGSTAB.
  *
  * Readings where the paper is silent (random-number generator, its key layout,
  * the uniform-to-neighbour map, ties, zero excess) are the library's documented
@@ -803,6 +805,208 @@ int srwo_pcg(int64_t n, const int64_t* rowptr, const int32_t* col, const double*
         double beta = rho_new / rho;
         rho = rho_new;
         for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+    }
+#undef APPLY
+    spmv(n, rowptr, col, val, x, q);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+    *rel_res = sqrt(dot(n, r, r)) / bnorm;
+    *iters = it;
+    free(r);
+    return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Asymmetric matrices: two games, LDU of rev(A) (Section 7.1).              */
+/* ------------------------------------------------------------------------- */
+
+/* Asymmetric R-matrix check for the two-game construction: the CSR structure as in
+ * srwo_validate; a positive diagonal and strictly negative off-diagonal entries; the
+ * pattern symmetric (A_jk stored exactly when A_kj is; the values may differ); the
+ * off-diagonal row sums and column sums both at most the diagonal (the game of A and
+ * the game of A^T are both defined, Section 2.1); and in every connected component a
+ * node with positive row excess and a node with positive column excess (a path to
+ * ground in both games). */
+int srwo_validate_asym(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val)
+{
+    if (n < 0 || rowptr[0] != 0) return SRWO_E_ARG;
+    for (int64_t k = 0; k < n; k++) {
+        if (rowptr[k + 1] < rowptr[k]) return SRWO_E_ARG;
+        int ndiag = 0;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++) {
+            int32_t j = col[p];
+            if (j < 0 || j >= n) return SRWO_E_ARG;
+            if (p > rowptr[k] && col[p - 1] >= j) return SRWO_E_ARG;
+            if (j == k) ndiag++;
+        }
+        if (ndiag != 1) return SRWO_E_ARG;
+    }
+    double* colsum = (double*)calloc((size_t)(n ? n : 1), sizeof(double));
+    double* diag = (double*)calloc((size_t)(n ? n : 1), sizeof(double));
+    if (!colsum || !diag) { free(colsum); free(diag); return SRWO_E_NOMEM; }
+    int status = SRWO_OK;
+    for (int64_t k = 0; k < n && status == SRWO_OK; k++) {
+        double a = 0.0, sum_w = 0.0;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++)
+            if (col[p] == k) a = val[p];
+        if (!(a > 0.0)) { status = SRWO_E_NOT_RMATRIX; break; }
+        diag[k] = a;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++) {
+            int32_t j = col[p];
+            if (j == k) continue;
+            if (!(val[p] < 0.0)) { status = SRWO_E_NOT_RMATRIX; break; }
+            sum_w = sum_w + (-val[p]);
+            /* structural symmetry */
+            int64_t lo = rowptr[j], hi = rowptr[j + 1] - 1, found = -1;
+            while (lo <= hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (col[mid] == k) { found = mid; break; }
+                if (col[mid] < k) lo = mid + 1; else hi = mid - 1;
+            }
+            if (found < 0) { status = SRWO_E_NOT_RMATRIX; break; }
+        }
+        if (status == SRWO_OK && a - sum_w < -EPS_EXCESS * a) status = SRWO_E_NOT_RMATRIX;
+    }
+    if (status == SRWO_OK) {
+        for (int64_t k = 0; k < n; k++)
+            for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++)
+                if (col[p] != k) colsum[col[p]] = colsum[col[p]] + (-val[p]);
+        for (int64_t k = 0; k < n; k++)
+            if (diag[k] - colsum[k] < -EPS_EXCESS * diag[k]) { status = SRWO_E_NOT_RMATRIX; break; }
+    }
+    if (status != SRWO_OK) { free(colsum); free(diag); return status; }
+    int64_t* parent = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    unsigned char* gr = (unsigned char*)calloc((size_t)(n ? n : 1), 1);
+    unsigned char* gc = (unsigned char*)calloc((size_t)(n ? n : 1), 1);
+    if (!parent || !gr || !gc) {
+        free(parent); free(gr); free(gc); free(colsum); free(diag);
+        return SRWO_E_NOMEM;
+    }
+    for (int64_t v = 0; v < n; v++) parent[v] = v;
+    for (int64_t k = 0; k < n; k++)
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++) {
+            int64_t ra = uf_find(parent, k), rb = uf_find(parent, col[p]);
+            if (ra != rb) parent[ra > rb ? ra : rb] = ra < rb ? ra : rb;
+        }
+    for (int64_t k = 0; k < n; k++) {
+        double sum_w = 0.0;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++)
+            if (col[p] != k) sum_w = sum_w + (-val[p]);
+        if (diag[k] - sum_w > EPS_EXCESS * diag[k]) gr[uf_find(parent, k)] = 1;
+        if (diag[k] - colsum[k] > EPS_EXCESS * diag[k]) gc[uf_find(parent, k)] = 1;
+    }
+    for (int64_t v = 0; v < n; v++)
+        if (uf_find(parent, v) == v && (!gr[v] || !gc[v])) status = SRWO_E_SINGULAR;
+    free(parent); free(gr); free(gc); free(colsum); free(diag);
+    return status;
+}
+
+/* z = (Y_T^T D Y_A)^{-1} r: the preconditioner of an asymmetric A from the factor of
+ * the game of A (Y_A, D; eqs. y2 and d) and the factor of the game of A^T (Y_T;
+ * eq. y3), both strictly lower in rank.  In rank order Y_A is the unit lower factor
+ * of the reversed LDU of eq. y2 and Y_T^T the unit upper factor of eq. y3.  The solve
+ * with Y_T^T runs first (ranks descending), then D, then the solve with Y_A. */
+void srwo_apply_ldu(int64_t n, const int64_t* yptr, const int32_t* ycol, const double* yval,
+                    const double* d, const int64_t* tptr, const int32_t* tcol,
+                    const double* tval, const int32_t* by_rank, const double* r, double* z,
+                    double* work)
+{
+    double* w = work;
+    for (int64_t v = 0; v < n; v++) w[v] = r[v];
+    for (int64_t p = n - 1; p >= 0; p--) {
+        int64_t k = by_rank[p];
+        for (int64_t q = tptr[k]; q < tptr[k + 1]; q++) w[tcol[q]] = w[tcol[q]] - tval[q] * w[k];
+    }
+    for (int64_t v = 0; v < n; v++) z[v] = w[v] / d[v];
+    for (int64_t p = 0; p < n; p++) {
+        int64_t k = by_rank[p];
+        double s = z[k];
+        for (int64_t q = yptr[k]; q < yptr[k + 1]; q++) s = s - yval[q] * z[ycol[q]];
+        z[k] = s;
+    }
+}
+
+/* Preconditioned BiCGSTAB (Barrett et al., Templates, Section 2.3.8, preconditioned
+ * BiCGSTAB) from x0 = 0 with r~ = r0 and M^{-1} = srwo_apply_ldu (the identity when
+ * yptr == NULL).  Each iteration: rho = r~.r; p = r (first) or r + beta (p - omega v)
+ * with beta = (rho / rho_prev)(alpha / omega); p^ = M^{-1} p; v = A p^; alpha =
+ * rho / r~.v; s = r - alpha v; if ||s|| <= tol ||b||, x += alpha p^ and the iteration
+ * ends there; else s^ = M^{-1} s, t = A s^, omega = t.s / t.t, x += alpha p^ + omega s^,
+ * r = s - omega t, test ||r|| <= tol ||b||.  A passed test is confirmed on the true
+ * residual b - Ax; if it fails, the method restarts from it (r~ = r).  rho = 0,
+ * r~.v = 0, t.t = 0 or omega = 0 is a breakdown: SRWO_NOT_CONVERGED with the current
+ * x.  *iters counts iterations (a half iteration that meets the test counts as one). */
+int srwo_bicgstab(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                  const int64_t* yptr, const int32_t* ycol, const double* yval, const double* d,
+                  const int64_t* tptr, const int32_t* tcol, const double* tval,
+                  const int32_t* by_rank, const double* b, double tol, int32_t max_iter,
+                  double* x, int32_t* iters, double* rel_res)
+{
+    double* r = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1) * 10);
+    if (!r) return SRWO_E_NOMEM;
+    double *rt = r + n, *p = r + 2 * n, *v = r + 3 * n, *ph = r + 4 * n, *s = r + 5 * n;
+    double *sh = r + 6 * n, *t = r + 7 * n, *q = r + 8 * n, *work = r + 9 * n;
+    for (int64_t i = 0; i < n; i++) { x[i] = 0.0; r[i] = b[i]; rt[i] = b[i]; }
+    double bnorm = sqrt(dot(n, b, b));
+    int32_t it = 0;
+    int status = SRWO_NOT_CONVERGED;
+    if (bnorm == 0.0) {
+        *iters = 0; *rel_res = 0.0; free(r);
+        return SRWO_OK;
+    }
+#define APPLY(src, dst)                                                                    \
+    do {                                                                                   \
+        if (yptr) srwo_apply_ldu(n, yptr, ycol, yval, d, tptr, tcol, tval, by_rank, src, dst, \
+                                 work);                                                    \
+        else for (int64_t i_ = 0; i_ < n; i_++) dst[i_] = src[i_];                         \
+    } while (0)
+    int first = 1;
+    double rho_prev = 0.0, alpha = 0.0, omega = 0.0;
+    while (it < max_iter) {
+        double rho = dot(n, rt, r);
+        if (rho == 0.0) break;
+        if (first) {
+            for (int64_t i = 0; i < n; i++) p[i] = r[i];
+            first = 0;
+        } else {
+            double beta = (rho / rho_prev) * (alpha / omega);
+            for (int64_t i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        APPLY(p, ph);
+        spmv(n, rowptr, col, val, ph, v);
+        it++;
+        double rtv = dot(n, rt, v);
+        if (rtv == 0.0) break;
+        alpha = rho / rtv;
+        for (int64_t i = 0; i < n; i++) s[i] = r[i] - alpha * v[i];
+        int converged = 0;
+        if (sqrt(dot(n, s, s)) <= tol * bnorm) {
+            for (int64_t i = 0; i < n; i++) x[i] = x[i] + alpha * ph[i];
+            converged = 1;
+        } else {
+            APPLY(s, sh);
+            spmv(n, rowptr, col, val, sh, t);
+            double tt = dot(n, t, t);
+            if (tt == 0.0) break;
+            omega = dot(n, t, s) / tt;
+            for (int64_t i = 0; i < n; i++) {
+                x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            rho_prev = rho;
+            if (sqrt(dot(n, r, r)) <= tol * bnorm) converged = 1;
+            else if (omega == 0.0) break;
+        }
+        if (converged) {
+            spmv(n, rowptr, col, val, x, q);
+            for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+            if (sqrt(dot(n, r, r)) <= tol * bnorm) {
+                status = SRWO_OK;
+                break;
+            }
+            /* restart from the true residual */
+            for (int64_t i = 0; i < n; i++) rt[i] = r[i];
+            first = 1;
+        }
     }
 #undef APPLY
     spmv(n, rowptr, col, val, x, q);

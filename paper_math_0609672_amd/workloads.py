@@ -68,6 +68,58 @@ def assemble(n: int, eu: np.ndarray, ev: np.ndarray, g: np.ndarray, excess: np.n
     return CSR(n, rowptr, cols.astype(np.int32), vals.astype(np.float64))
 
 
+def assemble_directed(n: int, eu: np.ndarray, ev: np.ndarray, g_uv: np.ndarray, g_vu: np.ndarray,
+                      excess: np.ndarray) -> CSR:
+    """Structurally symmetric CSR with asymmetric values: A_uv = -g_uv, A_vu = -g_vu for
+    every undirected edge (eu[e], ev[e]); the diagonal is the larger of the node's
+    off-diagonal row and column sums plus its excess, so the matrix is diagonally
+    dominant by rows and by columns (both walk games of the matrix and of its transpose
+    are defined), with strict dominance at the nodes of positive excess."""
+    eu = np.asarray(eu, dtype=np.int64)
+    ev = np.asarray(ev, dtype=np.int64)
+    g_uv = np.asarray(g_uv, dtype=np.float64)
+    g_vu = np.asarray(g_vu, dtype=np.float64)
+    excess = np.asarray(excess, dtype=np.float64)
+    if eu.size and (np.any(eu == ev) or np.any(g_uv <= 0) or np.any(g_vu <= 0)):
+        raise ValueError("edges must join distinct nodes with positive weights")
+    rowsum = np.bincount(eu, g_uv, minlength=n) + np.bincount(ev, g_vu, minlength=n)
+    colsum = np.bincount(ev, g_uv, minlength=n) + np.bincount(eu, g_vu, minlength=n)
+    diag = np.maximum(rowsum, colsum) + excess
+    rows = np.concatenate([eu, ev, np.arange(n, dtype=np.int64)])
+    cols = np.concatenate([ev, eu, np.arange(n, dtype=np.int64)])
+    vals = np.concatenate([-g_uv, -g_vu, diag])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    if rows.size > 1:
+        dup = (rows[1:] == rows[:-1]) & (cols[1:] == cols[:-1])
+        if np.any(dup):
+            raise ValueError("duplicate edge")
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return CSR(n, rowptr, cols.astype(np.int32), vals.astype(np.float64))
+
+
+def grid_asym(dims, *, g=("uniform", 0.5, 1.5), skew=0.5, ground_frac=0.05, min_ground=1,
+              excess=("uniform", 0.1, 1.0), seed=0) -> CSR:
+    """Grid with asymmetric couplings: each edge's conductance g is split into
+    g(1 + t) one way and g(1 - t) the other, t ~ U[-skew, skew] per edge (skew < 1);
+    grounded nodes and excess as in `grid`."""
+    rng = np.random.default_rng(seed)
+    eu, ev = grid_edges(dims)
+    n = int(np.prod(dims))
+    gv = _draw(rng, g, eu.size)
+    t = rng.uniform(-skew, skew, eu.size)
+    exc = _ground(rng, n, ground_frac, min_ground, excess)
+    return assemble_directed(n, eu, ev, gv * (1.0 + t), gv * (1.0 - t), exc)
+
+
+def transpose(A: CSR) -> CSR:
+    """CSR of A^T (columns sorted per row)."""
+    T = A.to_scipy().T.tocsr()
+    T.sort_indices()
+    return CSR(A.n, T.indptr.astype(np.int64), T.indices.astype(np.int32), T.data.astype(np.float64))
+
+
 def _draw(rng, spec, size):
     kind, lo, hi = spec
     if kind == "uniform":
@@ -184,6 +236,13 @@ def config_grid3d(m: int = 128, seed: int = 0) -> CSR:
     grounded with excess ~ U[0.01, 1]; m = 128 gives n = 2,097,152."""
     return grid((m, m, m), g=("loguniform", 1e-2, 1e2), ground_frac=0.01,
                 excess=("uniform", 0.01, 1.0), seed=seed)
+
+
+def config_grid3d_asym(m: int = 128, seed: int = 0) -> CSR:
+    """3D 7-point m^3 grid with asymmetric couplings: g log-uniform on [1e-2, 1e2] per
+    edge split (1 + t, 1 - t), t ~ U[-0.5, 0.5]; 1% grounded with excess ~ U[0.01, 1]."""
+    return grid_asym((m, m, m), g=("loguniform", 1e-2, 1e2), skew=0.5, ground_frac=0.01,
+                     excess=("uniform", 0.01, 1.0), seed=seed)
 
 
 def rgg_connect_probability(r: float) -> float:

@@ -160,6 +160,7 @@ typedef struct {
     int64_t tallied_walks; /* walks in the tallies: = walks, or with walk reuse the
                               simulated walks plus the extracted ones              */
     int32_t reuse;         /* srw_options.reuse of the build                        */
+    int32_t two_game;      /* 1 for a factor of srw_build_factor_ldu                */
 } srw_stats;
 
 /* Counters and (if profiled) phase times of a factor; host output. */
@@ -202,6 +203,44 @@ int srw_tally_export(const srw_factor* F, uint32_t* walks, uint64_t* J, uint32_t
  * Any pointer may be NULL. */
 int srw_walk_export(const srw_factor* F, int64_t* rec_off, int32_t* end, uint32_t* visits,
                     uint32_t* length, void* stream);
+
+/* ---- asymmetric matrices (Section 7.1) -------------------------------------------- */
+
+/* Builds the preconditioner of an asymmetric A from two walk games with one ordering:
+ * the game of A gives Y_A and D (eqs. y2 and d), the game of A^T gives Y_T (eq. y3),
+ * and in rank order A ~ Y_T^T D Y_A (the reversed LDU of rev(A)).  A must have a
+ * positive diagonal, negative off-diagonal entries, a symmetric pattern (values may
+ * differ: A_kj != A_jk), off-diagonal row sums and column sums both at most the
+ * diagonal, and in every connected component a node with positive row excess and a
+ * node with positive column excess; else SRW_E_NOT_RMATRIX / SRW_E_SINGULAR.  The
+ * game of A^T is built from A^T (formed on the device) with the ordering of the game
+ * of A (srw_options.ordering ignored for it) and the same seed, so for a symmetric A
+ * both games give the same factor.  Options, limits and errors as srw_build_factor
+ * (both builds honour keep, precision and reuse).  The handle owns both factors;
+ * srw_factor_export / srw_*_export read the game of A, srw_factor_transpose_game gives
+ * the other; srw_apply applies z = (Y_T^T D Y_A)^{-1} r.  Solve with
+ * srw_bicgstab_solve (srw_pcg_solve rejects it: the preconditioner is not
+ * symmetric). */
+int srw_build_factor_ldu(const srw_csr* A, int32_t walks_per_row, double drop_tol,
+                         uint64_t seed, const srw_options* opt, srw_factor** out,
+                         void* stream);
+
+/* The factor of the game of A^T inside a two-game handle (owned by F: do not free).
+ * SRW_E_ARG if F is not a two-game factor. */
+int srw_factor_transpose_game(const srw_factor* F, const srw_factor** G);
+
+/* Preconditioned BiCGSTAB (Barrett et al., Templates) on A x = b from x0 = 0, with
+ * the preconditioner of F (any factor of A: two-game or symmetric) or none (F NULL).
+ * r~ = r0; each iteration applies the preconditioner twice.  Stops when a residual
+ * (the half step's s or the full step's r) has ||.||_2 <= tol ||b||_2, then
+ * recomputes b - Ax and restarts from it (r~ = r) if the test fails.  Breakdowns
+ * (r~.r = 0, r~.v = 0, t.t = 0, omega = 0) return SRW_NOT_CONVERGED with the last
+ * iterate.  b, x: device float64[n] (x overwritten); host outputs iters (iterations,
+ * a converged half step counting as one) and rel_residual = ||b - Ax||_2 / ||b||_2;
+ * either may be NULL.  Returns SRW_OK, SRW_NOT_CONVERGED, SRW_E_ARG, SRW_E_HIP. */
+int srw_bicgstab_solve(const srw_csr* A, const srw_factor* F, const double* b, double tol,
+                       int32_t max_iter, double* x, int32_t* iters, double* rel_residual,
+                       void* stream);
 
 /* ---- the solve ---------------------------------------------------------------- */
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrw.so")
-SOURCES = ["scan_sort.hip", "build.hip", "solve.hip", "budget.hip", "batch.hip", "capi.cpp"]
+SOURCES = ["scan_sort.hip", "build.hip", "solve.hip", "budget.hip", "batch.hip", "ldu.hip", "capi.cpp"]
 ARCH = os.environ.get("SRW_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

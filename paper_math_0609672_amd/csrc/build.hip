@@ -55,9 +55,12 @@ __global__ void k_check_structure(int64_t n, int64_t nnz, const int64_t* __restr
 
 // Needs a valid structure.  diag[k] = A_kk, grounded[k] = (e_k > eps a_k) with the
 // excess summed in CSR order.
+// values: positive diagonal, negative off-diagonal entries, row dominance; the
+// mirrored entry must exist, with the same value unless `sym_values` is 0 (the game
+// of an asymmetric A, Section 7.1)
 __global__ void k_check_values(int64_t n, const int64_t* __restrict__ rowptr,
                                const int32_t* __restrict__ col, const double* __restrict__ val,
-                               uint8_t* __restrict__ grounded, int* err)
+                               int sym_values, uint8_t* __restrict__ grounded, int* err)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -88,7 +91,7 @@ __global__ void k_check_values(int64_t n, const int64_t* __restrict__ rowptr,
             if (c < (int32_t)k) lo = mid + 1;
             else hi = mid - 1;
         }
-        if (found < 0 || val[found] != v) bad = 1;
+        if (found < 0 || (sym_values && val[found] != v)) bad = 1;
     }
     if (!bad) {
         const double e = a - sum_w;
@@ -794,6 +797,7 @@ int hip_fail(hipError_t e, const char* what)
 void free_factor(srw_factor* F)
 {
     if (!F) return;
+    free_factor(F->tgame);
     for (void* p : F->allocations) (void)hipFree(p);
     if (F->host_scalars) (void)hipHostFree(F->host_scalars);
     delete F;
@@ -834,7 +838,7 @@ int ordering_impl(int64_t n, uint64_t seed, int32_t* rank, hipStream_t s)
 
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                       const srw_options* opt_in, srw_factor** out, hipStream_t s,
-                      const BatchKeys* batch, const LengthRule* rule)
+                      const BatchKeys* batch, const LengthRule* rule, bool asym)
 {
     srw_options opt;
     srw_default_options(&opt);
@@ -912,7 +916,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         std::memcpy(&herr, &pinned[0], sizeof(int));
         if (herr) FAIL(map_err(herr));
         if (nnz_off >= (int64_t)0xFFFFFFFFll) FAIL(SRW_E_ARG);
-        k_check_values<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, grounded, err);
+        k_check_values<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, asym ? 0 : 1, grounded,
+                                           err);
         k_cc_init<<<g, BLOCK, 0, s>>>(n, label);
         for (int it = 0; it < 64 * 64; ++it) {
             CHECK_HIP(hipMemsetAsync(changed, 0, sizeof(int), s));

@@ -146,6 +146,51 @@ int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, u
 
 void srw_factor_free(srw_factor* F) { srw::free_factor(F); }
 
+int srw_build_factor_ldu(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
+                         const srw_options* opt, srw_factor** out, void* stream)
+{
+    if (!out) return SRW_E_ARG;
+    *out = nullptr;
+    if (!csr_ok(A)) return SRW_E_ARG;
+    if (!(drop_tol >= 0.0) || !std::isfinite(drop_tol)) return SRW_E_ARG;
+    if (options_ok(opt, A->n) != SRW_OK) return SRW_E_ARG;
+    if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
+    if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
+    try {
+        return srw::build_ldu_impl(A, walks_per_row, drop_tol, seed, opt, out, as_stream(stream));
+    } catch (const std::bad_alloc&) {
+        return SRW_E_NOMEM;
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
+int srw_factor_transpose_game(const srw_factor* F, const srw_factor** G)
+{
+    if (!F || !G) return SRW_E_ARG;
+    *G = F->tgame;
+    return F->tgame ? SRW_OK : SRW_E_ARG;
+}
+
+int srw_bicgstab_solve(const srw_csr* A, const srw_factor* F, const double* b, double tol,
+                       int32_t max_iter, double* x, int32_t* iters, double* rel_residual,
+                       void* stream)
+{
+    if (!csr_ok(A)) return SRW_E_ARG;
+    if (F && (A->n != F->n || A->nnz != F->nnz_a || F->nmat > 0)) return SRW_E_ARG;
+    if (A->n > 0 && (!b || !x)) return SRW_E_ARG;
+    if (!(tol >= 0.0) || max_iter < 0) return SRW_E_ARG;
+    if (iters) *iters = 0;
+    if (rel_residual) *rel_residual = 0.0;
+    if (A->n == 0) return SRW_OK;
+    try {
+        return srw::bicgstab_impl(A, const_cast<srw_factor*>(F), b, tol, max_iter, x, iters,
+                                  rel_residual, as_stream(stream));
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
 int srw_factor_info(const srw_factor* F, int64_t* n, int64_t* nnz_y, int64_t* walks,
                     int64_t* walk_steps, int32_t* levels_fwd, int32_t* levels_bwd,
                     int32_t* precision, int32_t* keep)
@@ -178,6 +223,7 @@ int srw_factor_stats(const srw_factor* F, srw_stats* out)
     for (int i = 0; i < SRW_NUM_PHASES; ++i) out->phase_ms[i] = F->phase_ms[i];
     out->tallied_walks = F->tallied_total;
     out->reuse = F->reuse;
+    out->two_game = F->tgame ? 1 : 0;
     return SRW_OK;
 }
 
@@ -275,6 +321,7 @@ int srw_pcg_solve(const srw_csr* A, const srw_factor* F, const double* b, double
                   int32_t max_iter, double* x, int32_t* iters, double* rel_residual, void* stream)
 {
     if (!F || !csr_ok(A) || A->n != F->n || A->nnz != F->nnz_a) return SRW_E_ARG;
+    if (F->tgame) return SRW_E_ARG;  // a two-game factor is not symmetric: srw_bicgstab_solve
     if (A->n > 0 && (!b || !x)) return SRW_E_ARG;
     if (!(tol >= 0.0) || max_iter < 0) return SRW_E_ARG;
     if (iters) *iters = 0;

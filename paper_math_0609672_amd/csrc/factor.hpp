@@ -44,6 +44,10 @@ struct srw_factor {
     // longest dependency chain of the triangular solves, -1 until srw_factor_depth
     int32_t depth = -1;
 
+    // asymmetric A (Section 7.1): the factor of the game of A^T with the same ordering
+    // (owned); the preconditioner is then (Y_T^T D Y)^{-1}
+    srw_factor* tgame = nullptr;
+
     // batched build: nmat matrices stacked block-diagonally (0 = one matrix)
     int32_t nmat = 0;
     std::vector<int64_t> mat_off_host;  // [nmat+1] first stacked row of every matrix
@@ -135,9 +139,21 @@ struct LengthRule {
 // Internal status of a walks-only build (never returned by the C ABI).
 constexpr int SRW_WALKS_ONLY = 100;
 
+// asym: the matrix's values need not be symmetric (its pattern must be); used for
+// each game of an asymmetric matrix
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                       const srw_options* opt, srw_factor** out, hipStream_t s,
-                      const BatchKeys* batch = nullptr, const LengthRule* rule = nullptr);
+                      const BatchKeys* batch = nullptr, const LengthRule* rule = nullptr,
+                      bool asym = false);
+// Asymmetric A (Section 7.1): the game of A, then the game of A^T with its ordering.
+int build_ldu_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
+                   const srw_options* opt, srw_factor** out, hipStream_t s);
+// Preconditioned BiCGSTAB (F may be null: no preconditioner).
+int bicgstab_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
+                  double* x, int32_t* iters, double* rel_residual, hipStream_t s);
+// z = M^{-1} r for a factor (symmetric or two-game); work: 2 n doubles; err: one int.
+hipError_t apply_factor(const srw_factor* F, const double* r, void* work, double* z, int* err,
+                        hipStream_t s);
 int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt, double delta,
                   double z, int32_t min_walks, int32_t max_walks, int32_t* walks, hipStream_t s);
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,

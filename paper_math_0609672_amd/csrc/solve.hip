@@ -408,11 +408,72 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
     return e;
 }
 
+// Two-game factor (Section 7.1): the backward solve runs over the plan of the game of
+// A^T (its Y^T by slot) and writes its result by node into z; the result is gathered
+// into the slot order of the game of A, whose forward solve (with D) finishes in z.
+template <typename T>
+__global__ void k_gather_slots(int64_t n, const int32_t* __restrict__ slot_node,
+                               const double* __restrict__ x, T* __restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        y[i] = (T)x[slot_node[i]];
+}
+
+template <typename T>
+hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol, double* z,
+                          int* err, hipStream_t s)
+{
+    const srw_factor* G = F->tgame;
+    int64_t n = F->n;
+    k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, work);
+    k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, sol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        const int64_t* ptr = G->bptr;
+        const int32_t* col = G->bcol;
+        const T* val = (const T*)G->bval;
+        const T* dslot = nullptr;
+        const int32_t* slot_node = G->slot_node;
+        const double* rhs = r;
+        const T* w = nullptr;
+        T* out_sol = work;
+        double* out = z;
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        e = coop_launch(k_trsv<T, false>, n, args, s);
+        if (e != hipSuccess) return e;
+    }
+    k_gather_slots<T><<<fill_grid(n), BLOCK, 0, s>>>(n, F->slot_node, z, work);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        const int64_t* ptr = F->fptr;
+        const int32_t* col = F->fcol;
+        const T* val = (const T*)F->fval;
+        const T* dslot = (const T*)F->dslot;
+        const int32_t* slot_node = F->slot_node;
+        const double* rhs = nullptr;
+        const T* w = work;
+        T* out_sol = sol;
+        double* out = z;
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        e = coop_launch(k_trsv<T, true>, n, args, s);
+    }
+    return e;
+}
+
 // work: 2 n doubles of scratch; err: one int (0 on entry).
 hipError_t apply_any(const srw_factor* F, const double* r, void* work, double* z, int* err,
                      hipStream_t s)
 {
     if (F->n == 0) return hipSuccess;
+    if (F->tgame) {
+        if (F->precision == SRW_FP32) {
+            float* w = (float*)work;
+            return apply_ldu_plan<float>(F, r, w, w + F->n, z, err, s);
+        }
+        double* w = (double*)work;
+        return apply_ldu_plan<double>(F, r, w, w + F->n, z, err, s);
+    }
     if (F->precision == SRW_FP32) {
         float* w = (float*)work;
         return apply_plan<float>(F, r, w, w + F->n, z, err, s);
@@ -428,6 +489,12 @@ int red_grid(int64_t n)
 }
 
 }  // namespace
+
+hipError_t apply_factor(const srw_factor* F, const double* r, void* work, double* z, int* err,
+                        hipStream_t s)
+{
+    return apply_any(F, r, work, z, err, s);
+}
 
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s)
 {

@@ -52,7 +52,7 @@ class _Stats(ctypes.Structure):
                 ("walk_deg_sum", ctypes.c_int64), ("levels_fwd", ctypes.c_int32),
                 ("levels_bwd", ctypes.c_int32), ("precision", ctypes.c_int32), ("keep", ctypes.c_int32),
                 ("phase_ms", ctypes.c_double * NUM_PHASES), ("tallied_walks", ctypes.c_int64),
-                ("reuse", ctypes.c_int32)]
+                ("reuse", ctypes.c_int32), ("two_game", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -86,6 +86,11 @@ _lib.srw_build_factor_batched.argtypes = [_I32, _P, _I32, _D, _P, ctypes.POINTER
                                           ctypes.POINTER(_P), _P]
 _lib.srw_batch_info.argtypes = [_P, ctypes.POINTER(_I32), _P]
 _lib.srw_pcg_solve_batched.argtypes = [_P, _I32, _P, _D, _I32, _P, _P, _P, _I32, _P]
+_lib.srw_build_factor_ldu.argtypes = [ctypes.POINTER(_Csr), _I32, _D, _U64, ctypes.POINTER(_Options),
+                                      ctypes.POINTER(_P), _P]
+_lib.srw_factor_transpose_game.argtypes = [_P, ctypes.POINTER(_P)]
+_lib.srw_bicgstab_solve.argtypes = [ctypes.POINTER(_Csr), _P, _P, _D, _I32, _P, ctypes.POINTER(_I32),
+                                    ctypes.POINTER(_D), _P]
 _lib.srw_last_error.argtypes = []
 _lib.srw_last_error.restype = ctypes.c_char_p
 _lib.srw_status_string.argtypes = [ctypes.c_int]
@@ -142,17 +147,25 @@ class Matrix:
 class Factor:
     """Handle of a library-owned srw_factor."""
 
-    def __init__(self, handle: int, device):
+    def __init__(self, handle: int, device, owner=None):
         self._h = ctypes.c_void_p(handle)
         self.device = device
+        self._owner = owner  # a factor inside another handle is freed with it
 
     def __del__(self):
         self.free()
 
     def free(self):
         if getattr(self, "_h", None) and self._h.value:
-            _lib.srw_factor_free(self._h)
+            if self._owner is None:
+                _lib.srw_factor_free(self._h)
             self._h = ctypes.c_void_p(0)
+
+    def transpose_game(self) -> "Factor":
+        """srw_factor_transpose_game: the factor of the game of A^T of a two-game factor."""
+        g = _P(0)
+        _check(_lib.srw_factor_transpose_game(self._h, ctypes.byref(g)), "srw_factor_transpose_game")
+        return Factor(g.value, self.device, owner=self)
 
     @property
     def handle(self):
@@ -250,6 +263,50 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
                  reuse: bool = False, stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A (with reuse, the
     walks extracted by Algorithm "reuse" of Section 5.3 join the tallies)."""
+    opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
+                   solve_order, reuse)
+    h = ctypes.c_void_p(0)
+    csr = A.c()
+    st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),
+                               ctypes.byref(opt), ctypes.byref(h), _stream(stream))
+    _check(st, "srw_build_factor")
+    return Factor(h.value, A.rowptr.device)
+
+
+def build_factor_ldu(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None,
+                     walks=None, precision: str = "fp64", max_steps: int = 0, keep: int = 0,
+                     refill_period: int = 0, profile: bool = False, schedule: int = 1,
+                     solve_order: int = 1, reuse: bool = False, stream=None) -> Factor:
+    """srw_build_factor_ldu: the two-game preconditioner of an asymmetric A (Section 7.1)."""
+    opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
+                   solve_order, reuse)
+    h = ctypes.c_void_p(0)
+    csr = A.c()
+    st = _lib.srw_build_factor_ldu(ctypes.byref(csr), int(walks_per_row), float(drop_tol),
+                                   int(seed) & (2**64 - 1), ctypes.byref(opt), ctypes.byref(h),
+                                   _stream(stream))
+    _check(st, "srw_build_factor_ldu")
+    return Factor(h.value, A.rowptr.device)
+
+
+def bicgstab_solve(A: Matrix, F, b: torch.Tensor, tol: float, max_iter: int = 10000, x=None,
+                   stream=None):
+    """srw_bicgstab_solve (F None: no preconditioner).  Returns (status, x, iters,
+    rel_residual); errors raise SrwError."""
+    if x is None:
+        x = torch.empty_like(b)
+    it = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    csr = A.c()
+    st = _lib.srw_bicgstab_solve(ctypes.byref(csr), F.handle if F is not None else None, _ptr(b),
+                                 float(tol), int(max_iter), _ptr(x), ctypes.byref(it),
+                                 ctypes.byref(rel), _stream(stream))
+    _check(st, "srw_bicgstab_solve")
+    return st, x, it.value, rel.value
+
+
+def _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
+             solve_order, reuse) -> _Options:
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
     if rank is not None:
@@ -265,12 +322,7 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
     opt.schedule = int(schedule)
     opt.solve_order = int(solve_order)
     opt.reuse = 1 if reuse else 0
-    h = ctypes.c_void_p(0)
-    csr = A.c()
-    st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),
-                               ctypes.byref(opt), ctypes.byref(h), _stream(stream))
-    _check(st, "srw_build_factor")
-    return Factor(h.value, A.rowptr.device)
+    return opt
 
 
 def pcg_solve(A: Matrix, F: Factor, b: torch.Tensor, tol: float, max_iter: int = 10000, x=None,

@@ -43,6 +43,10 @@ WORKLOADS = {
 for _m in (50, 60, 70, 80, 90, 100):
     WORKLOADS[f"laplace3d_{_m}"] = ("laplace3d_dirichlet", dict(m=_m), 24, 0.0, 1e-6)
 ONES_RHS = {k for k in WORKLOADS if k.startswith("laplace3d_")}
+# asymmetric 3D grids (Section 7.1): two walk games, BiCGSTAB instead of PCG
+for _m in (64, 128):
+    WORKLOADS[f"grid3d_asym_{_m}"] = ("config_grid3d_asym", dict(m=_m), 256, 1e-4, 1e-8)
+ASYM = {k for k in WORKLOADS if k.startswith("grid3d_asym_")}
 
 
 def parse():
@@ -76,37 +80,44 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(A, walks, seed, target_s):
-    """Oracle build on a random sample of rows, scaled to all rows."""
+def cpu_baseline(A, walks, seed, target_s, two_games=False):
+    """Oracle build on a random sample of rows, scaled to all rows (for an asymmetric A,
+    the same for the game of A^T, half the time each)."""
     import numpy as np
 
     import oracle as O
 
+    games = [A, O.transpose(A)] if two_games else [A]
     t0 = time.perf_counter()
     rk = O.rank(A.n, seed)
-    tb = O.table(A, rk)
+    tbs = [O.table(G, rk) for G in games]
     t_setup = time.perf_counter() - t0
-    walking = np.flatnonzero(tb.tau > 0)
-    rng = np.random.default_rng(12345)
-    order = rng.permutation(walking)
-    done_rows, steps = 0, 0
-    t_walk = 0.0
-    chunk = 256
-    while t_walk < target_s and done_rows < order.size:
-        rows = order[done_rows:done_rows + chunk]
-        t1 = time.perf_counter()
-        wk = O.walk_rows(A, rk, tb, seed, rows, walks)
-        t_walk += time.perf_counter() - t1
-        steps += int(wk.length.sum())
-        done_rows += rows.size
-    est_walk = t_walk * walking.size / max(done_rows, 1)
+    est_walk, t_walk, steps, parts = 0.0, 0.0, 0, []
+    for G, tb in zip(games, tbs):
+        walking = np.flatnonzero(tb.tau > 0)
+        rng = np.random.default_rng(12345)
+        order = rng.permutation(walking)
+        done_rows, tg = 0, 0.0
+        chunk = 256
+        while tg < target_s / len(games) and done_rows < order.size:
+            rows = order[done_rows:done_rows + chunk]
+            t1 = time.perf_counter()
+            wk = O.walk_rows(G, rk, tb, seed, rows, walks)
+            tg += time.perf_counter() - t1
+            steps += int(wk.length.sum())
+            done_rows += rows.size
+        est_walk += tg * walking.size / max(done_rows, 1)
+        t_walk += tg
+        parts.append(f"{done_rows} of {walking.size} walking rows")
     return {
         "value": round(t_setup + est_walk, 3),
-        "unit": "s (oracle build, walks scaled from the sample; PCG not included)",
+        "unit": "s (oracle build, walks scaled from the sample; "
+                + ("BiCGSTAB" if two_games else "PCG") + " not included)",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{done_rows} of {walking.size} walking rows drawn uniformly, {walks} walks each; "
-                  f"ordering and table on all rows ({t_setup:.2f} s)",
+        "sample": " and ".join(parts) + (" (games of A and A^T)" if two_games else "")
+                  + f" drawn uniformly, {walks} walks each; ordering and table on all rows "
+                  f"({t_setup:.2f} s)",
         "walk_steps_per_s": round(steps / max(t_walk, 1e-9), 1),
         "sample_walk_s": round(t_walk, 3),
     }
@@ -167,21 +178,26 @@ def main():
     x = torch.empty_like(b)
     torch.cuda.synchronize()
 
+    asym = args.workload in ASYM
+    build = srw.build_factor_ldu if asym else srw.build_factor
+    solve = srw.bicgstab_solve if asym else srw.pcg_solve
+
     def step():
         t0 = time.perf_counter()
         budgets = None
         if args.adaptive > 0:
             budgets = srw.adaptive_budgets(M, args.seed, args.adaptive, alpha=0.99)
-        F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
-                             refill_period=args.refill, schedule=args.schedule,
-                             solve_order=args.solve_order, profile=True, walks=budgets,
-                             reuse=args.reuse)
+        F = build(M, walks, drop, args.seed, precision=args.precision,
+                  refill_period=args.refill, schedule=args.schedule,
+                  solve_order=args.solve_order, profile=True, walks=budgets,
+                  reuse=args.reuse)
         t1 = time.perf_counter()
-        st, _, it, rel = srw.pcg_solve(M, F, b, tol, 10000, x=x)
+        st, _, it, rel = solve(M, F, b, tol, 10000, x=x)
         t2 = time.perf_counter()
         s = F.stats()
+        s2 = F.transpose_game().stats() if asym else None
         F.free()
-        return dict(build_s=t1 - t0, pcg_s=t2 - t1, iters=it, rel=rel, status=st, stats=s)
+        return dict(build_s=t1 - t0, pcg_s=t2 - t1, iters=it, rel=rel, status=st, stats=s, tstats=s2)
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -201,9 +217,9 @@ def main():
 
     K = args.steps
     s0 = runs[-1]["stats"]
-    F = srw.build_factor(M, walks, drop, args.seed, precision=args.precision,
-                         refill_period=args.refill, schedule=args.schedule,
-                         solve_order=args.solve_order, reuse=args.reuse)
+    F = build(M, walks, drop, args.seed, precision=args.precision,
+              refill_period=args.refill, schedule=args.schedule,
+              solve_order=args.solve_order, reuse=args.reuse)
     depth = F.depth()  # reported only; outside the timed steps
     F.free()
     walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in runs) / K
@@ -211,7 +227,19 @@ def main():
     walk_bytes = 12.0 * steps_per_build + 8.0 * s0["walk_deg_sum"]
     if args.reuse:  # plus one 16-byte record per counted walk
         walk_bytes += 16.0 * s0["tallied_walks"]
+    t0s = runs[-1]["tstats"]
+    if asym:  # one walk launch per game: the average over both
+        walk_ms_t = sum(r["tstats"]["phase_ms"]["walk"] for r in runs) / K
+        bytes_t = 12.0 * t0s["walk_steps"] + 8.0 * t0s["walk_deg_sum"]
+        if args.reuse:
+            bytes_t += 16.0 * t0s["tallied_walks"]
+        achieved_pair = (walk_bytes + bytes_t) / ((walk_ms + walk_ms_t) * 1e-3) / 1e9
     achieved = walk_bytes / (walk_ms * 1e-3) / 1e9
+    if asym:
+        achieved = achieved_pair
+        steps_per_build += t0s["walk_steps"]
+        walk_bytes = (walk_bytes + bytes_t) / 2
+        walk_ms = (walk_ms + walk_ms_t) / 2
     build_s = sum(r["build_s"] for r in runs) / K
     pcg_s = sum(r["pcg_s"] for r in runs) / K
     iters = runs[-1]["iters"]
@@ -237,16 +265,18 @@ def main():
                         + (f"Section 5.1 walks (delta {args.adaptive}, alpha 0.99)" if args.adaptive > 0
                            else f"{walks} walks/row")
                         + (", walk reuse (Section 5.3)" if args.reuse else "")
+                        + (", two games (A, A^T; Section 7.1), BiCGSTAB" if asym else "")
                         + f", drop {drop}, tol {tol}, seed {args.seed}",
             "global_batch": 1,
             "parallelism": "single GPU",
         },
-        "walk_steps_per_s": round(steps_per_build / (walk_ms * 1e-3), 1),
+        "walk_steps_per_s": round(steps_per_build / (walk_ms * 1e-3 * (2 if asym else 1)), 1),
         "walk_steps": steps_per_build,
         "walks": s0["walks"],
         "tallied_walks": s0["tallied_walks"],
         "build_s": round(build_s, 4),
         "pcg_s": round(pcg_s, 4),
+        "solver": "bicgstab" if asym else "pcg",
         "pcg_iters": iters,
         "rel_residual": runs[-1]["rel"],
         "converged": all(r["status"] == srw.OK for r in runs),
@@ -271,16 +301,16 @@ def main():
     if args.compare_precision:
         other = "fp32" if args.precision == "fp64" else "fp64"
         x_main = x.clone()
-        F2 = srw.build_factor(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
-                              schedule=args.schedule, solve_order=args.solve_order)
+        F2 = build(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
+                   schedule=args.schedule, solve_order=args.solve_order)
         F2.free()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F2 = srw.build_factor(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
-                              schedule=args.schedule, solve_order=args.solve_order)
+        F2 = build(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
+                   schedule=args.schedule, solve_order=args.solve_order)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        st2, x2, it2, rel2 = srw.pcg_solve(M, F2, b, tol, 10000)
+        st2, x2, it2, rel2 = solve(M, F2, b, tol, 10000)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         F2.free()
@@ -302,12 +332,12 @@ def main():
         log(f"copy calibration: 3 x {args.copy_calibration} MiB read + written by one kernel")
         del src, dst
     # counters were taken on the workload's own walk budget
-    default_walks = not (args.reuse or args.walks or args.adaptive > 0)
+    default_walks = not (args.reuse or args.walks or args.adaptive > 0 or asym)
     out["roofline"]["traffic"] = (measured_traffic(args.workload, args.precision)
                                   if default_walks else None)
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(A, walks, args.seed, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A, walks, args.seed, args.cpu_seconds, two_games=asym)
     print(json.dumps(out), flush=True)
 
 

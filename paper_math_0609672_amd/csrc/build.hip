@@ -693,6 +693,14 @@ namespace {
 thread_local char last_error[256] = "";
 }
 
+int64_t* host_scratch()
+{
+    thread_local int64_t* p = nullptr;
+    if (!p && hipHostMalloc((void**)&p, 32 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+        p = nullptr;
+    return p;
+}
+
 void set_last_error(const char* msg)
 {
     std::snprintf(last_error, sizeof(last_error), "%s", msg ? msg : "");
@@ -741,7 +749,8 @@ int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt_in, do
     budget = target + n;
     found = budget + n;
     open = (int*)(found + n);
-    e = hipHostMalloc((void**)&host_open, sizeof(int), hipHostMallocDefault);
+    host_open = (int*)(host_scratch() ? host_scratch() + 16 : nullptr);
+    if (!host_open) e = hipErrorOutOfMemory;
     const int g = grid_for(n, BLOCK);
     int status = SRW_OK;
     if (e == hipSuccess) {
@@ -768,7 +777,6 @@ int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt_in, do
     }
     (void)hipFreeAsync(target, s);
     (void)hipStreamSynchronize(s);
-    if (host_open) (void)hipHostFree(host_open);
     if (e != hipSuccess) return hip_fail(e, "adaptive budgets");
     return status;
 }
@@ -799,6 +807,13 @@ void free_factor(srw_factor* F)
     if (!F) return;
     free_factor(F->tgame);
     for (void* p : F->allocations) (void)hipFree(p);
+    if (!F->pool_allocations.empty()) {
+        // back to the pool once the device is idle (the caller guarantees no work on F
+        // is pending; the synchronization is what hipFree would have done)
+        (void)hipDeviceSynchronize();
+        for (void* p : F->pool_allocations) (void)hipFreeAsync(p, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    }
     if (F->host_scalars) (void)hipHostFree(F->host_scalars);
     delete F;
 }
@@ -864,6 +879,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
     retain_pool_memory();
     tmp.pooled = true;
     tmp.stream = s;
+    keep.pooled = true;  // the factor's blocks too: repeated builds reuse pooled memory
+    keep.stream = s;
+    // shared chunks sized to the matrix: a few n-length arrays each
+    keep.chunk = std::max<size_t>((size_t)1 << 20, ((size_t)std::max<int64_t>(n, 1) * 32 + 255) & ~(size_t)255);
+    tmp.chunk = 4 * keep.chunk;
+    // arrays only exports need: owned by F with keep >= 1, build temporaries otherwise
+    Arena& xk = opt.keep >= 1 ? keep : tmp;
     int64_t* pinned = nullptr;
     int status = SRW_OK;
     const bool fp32 = opt.factor_precision == SRW_FP32;
@@ -890,11 +912,12 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         for (auto& e : ev)
             if (hipEventCreate(&e) != hipSuccess) e = nullptr;
     {
-        CHECK_HIP(hipHostMalloc((void**)&pinned, 8 * sizeof(int64_t), hipHostMallocDefault));
+        pinned = host_scratch();
+        if (!pinned) FAIL(SRW_E_NOMEM);
         const int g = grid_for(n, BLOCK);
         int* err = ALLOC(tmp, int, 1);
         int* changed = ALLOC(tmp, int, 1);
-        uint8_t* grounded = ALLOC(keep, uint8_t, n);
+        uint8_t* grounded = ALLOC(xk, uint8_t, n);
         int32_t* label = ALLOC(tmp, int32_t, n);
         uint8_t* comp = ALLOC(tmp, uint8_t, n);
         F->rank = ALLOC(keep, int32_t, n);
@@ -978,9 +1001,9 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         // walk records, then start records of the same shape
         uint4* recs = ALLOC(tmp, uint4, 2 * n_lines * 4);
         uint2* ent = opt.keep >= 1 ? ALLOC(keep, uint2, nnz_off) : nullptr;  // export only
-        uint32_t* mthr = ALLOC(keep, uint32_t, nnz_off);
-        double* tau = ALLOC(keep, double, n);
-        int32_t* budget = ALLOC(keep, int32_t, n);
+        uint32_t* mthr = ALLOC(xk, uint32_t, nnz_off);
+        double* tau = ALLOC(xk, double, n);
+        int32_t* budget = ALLOC(xk, int32_t, n);
         int32_t* maxb = ALLOC(tmp, int32_t, 1);
         if (!recs || (opt.keep >= 1 && !ent) || !mthr || !tau || !budget || !maxb)
             FAIL(SRW_E_NOMEM);
@@ -996,7 +1019,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         CHECK_HIP(hipGetLastError());
 
         // record offsets (node order) and the segmented chunk list
-        int64_t* rec_off = ALLOC(keep, int64_t, n);
+        int64_t* rec_off = ALLOC(xk, int64_t, n);
         int32_t* flag = ALLOC(tmp, int32_t, n);
         int32_t* flag2 = ALLOC(tmp, int32_t, n);
         int64_t* pos = ALLOC(tmp, int64_t, n);
@@ -1165,11 +1188,11 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         }
 
         // ---- 5. tallies
-        uint64_t* tJ = ALLOC(keep, uint64_t, n);
-        uint32_t* tG = ALLOC(keep, uint32_t, n);
-        uint64_t* tsteps = ALLOC(keep, uint64_t, n);
-        uint64_t* tvsq = ALLOC(keep, uint64_t, n);
-        int32_t* hlen = ALLOC(keep, int32_t, n);
+        uint64_t* tJ = ALLOC(xk, uint64_t, n);
+        uint32_t* tG = ALLOC(xk, uint32_t, n);
+        uint64_t* tsteps = ALLOC(xk, uint64_t, n);
+        uint64_t* tvsq = ALLOC(xk, uint64_t, n);
+        int32_t* hlen = ALLOC(xk, int32_t, n);
         // the H lists overwrite the records of their own row in place unless the
         // records or the lists outlive the build
         uint32_t* h_end = rec_end;
@@ -1181,7 +1204,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (reuse) {
             // sort the record slots by (start node, end node), unused slots last; the
             // first slot of every row, and so the number of records, by binary search
-            h_off = ALLOC(keep, int64_t, n + 1);
+            h_off = ALLOC(xk, int64_t, n + 1);
             uint64_t* key2 = ALLOC(tmp, uint64_t, n_slots);
             uint32_t* idx = ALLOC(tmp, uint32_t, n_slots);
             uint32_t* idx2 = ALLOC(tmp, uint32_t, n_slots);
@@ -1404,7 +1427,6 @@ done:
         (void)hipStreamSynchronize(s);
     }
     tmp.release();
-    if (pinned) (void)hipHostFree(pinned);
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     if (status != SRW_OK) {
@@ -1413,23 +1435,14 @@ done:
         return status == SRW_WALKS_ONLY ? SRW_OK : status;
     }
     if (opt.keep < 1) {
-        // drop what only export needs
-        void* drop[] = {F->ent, F->mthr, F->tau, F->grounded, F->budget, F->rec_off, F->h_off,
-                        F->tJ, F->tG, F->tsteps, F->tvsq, F->hlen};
-        for (void* p : drop) {
-            auto it = std::find(keep.blocks.begin(), keep.blocks.end(), p);
-            if (it != keep.blocks.end()) {
-                (void)hipFree(p);
-                keep.blocks.erase(it);
-            }
-        }
+        // what only export needs lived in the build temporaries
         F->ent = nullptr; F->mthr = nullptr; F->tau = nullptr; F->grounded = nullptr;
         F->budget = nullptr; F->rec_off = nullptr; F->h_off = nullptr; F->tJ = nullptr;
         F->tG = nullptr;
         F->tsteps = nullptr; F->tvsq = nullptr; F->hlen = nullptr;
         F->h_end = nullptr; F->h_cnt = nullptr;
     }
-    F->allocations = std::move(keep.blocks);
+    F->pool_allocations = std::move(keep.blocks);
     *out = F;
     return SRW_OK;
 }

@@ -20,6 +20,10 @@ namespace srw {
 // Records "what: <HIP error name>" as the calling thread's last error; returns
 // SRW_E_NOMEM for allocation failures, SRW_E_HIP otherwise.
 int hip_fail(hipError_t e, const char* what);
+// Small pinned host block of this thread (32 int64), allocated on first use and kept
+// until the process ends; nullptr if the allocation failed.  Slots: [0, 8) the build,
+// [8, 12) the solvers, [16] the adaptive budget rounds.
+int64_t* host_scratch();
 void set_last_error(const char* msg);
 const char* get_last_error();
 

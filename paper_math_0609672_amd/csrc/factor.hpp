@@ -83,7 +83,8 @@ struct srw_factor {
     double* scalars = nullptr;
     double* host_scalars = nullptr;  // pinned
 
-    std::vector<void*> allocations;  // every device/pinned block owned by this factor
+    std::vector<void*> allocations;       // device blocks owned by this factor (hipMalloc)
+    std::vector<void*> pool_allocations;  // ... from the stream-ordered pool (hipMallocAsync)
 };
 
 namespace srw {
@@ -91,28 +92,48 @@ namespace srw {
 // Device allocation tracked by an owner list (freed together).  With a stream the
 // blocks come from the stream-ordered pool (hipMallocAsync / hipFreeAsync), so the
 // temporaries of repeated builds reuse pooled memory instead of being mapped anew.
+// With a chunk size, requests up to half a chunk are carved out of shared chunks
+// (256-byte aligned), larger ones get a block of their own: each runtime allocation
+// and free costs tens to hundreds of microseconds, so a build makes few of them.
 struct Arena {
     std::vector<void*> blocks;
     hipError_t last = hipSuccess;
     hipStream_t stream = nullptr;
     bool pooled = false;
+    size_t chunk = 0;    // 0: every request is a block of its own
+    char* cur = nullptr;  // free tail of the current chunk
+    size_t left = 0;
     template <typename T>
     T* alloc(size_t count)
     {
-        void* p = nullptr;
         const size_t bytes = (((count ? count * sizeof(T) : sizeof(T)) + 255) & ~(size_t)255);
-        hipError_t e = pooled ? hipMallocAsync(&p, bytes, stream) : hipMalloc(&p, bytes);
+        if (bytes <= left) {
+            void* r = cur;
+            cur += bytes;
+            left -= bytes;
+            return (T*)r;
+        }
+        const bool own = bytes > chunk / 2;
+        const size_t size = own ? bytes : chunk;
+        void* p = nullptr;
+        hipError_t e = pooled ? hipMallocAsync(&p, size, stream) : hipMalloc(&p, size);
         if (e != hipSuccess) {
             last = e;
             return nullptr;
         }
         blocks.push_back(p);
+        if (!own) {
+            cur = (char*)p + bytes;
+            left = size - bytes;
+        }
         return (T*)p;
     }
     void release()
     {
         for (void* p : blocks) (void)(pooled ? hipFreeAsync(p, stream) : hipFree(p));
         blocks.clear();
+        cur = nullptr;
+        left = 0;
     }
 };
 

@@ -311,7 +311,8 @@ int bicgstab_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, 
     double* sums = part + 2 * RED;
     int* err = (int*)(sums + 2);
     double* host = nullptr;
-    hipError_t e = hipHostMalloc((void**)&host, 4 * sizeof(double), hipHostMallocDefault);
+    host = host_scratch() ? (double*)(host_scratch() + 8) : nullptr;
+    hipError_t e = host ? hipSuccess : hipErrorOutOfMemory;
     if (e != hipSuccess) {
         (void)hipFreeAsync(ws, s);
         return hip_fail(e, "hipHostMalloc");
@@ -435,7 +436,6 @@ out:
 #undef STEP
     (void)hipFreeAsync(ws, s);
     (void)hipStreamSynchronize(s);
-    (void)hipHostFree(host);
     if (iters_out) *iters_out = it;
     if (rel_out) *rel_out = rel;
     if (gave_up) {

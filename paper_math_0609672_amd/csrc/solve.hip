@@ -572,7 +572,8 @@ int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32
     double* partials = ws + 6 * vec;
     double* sc = partials + RED_GRID;
     int* err = (int*)(sc + S_COUNT);
-    hipError_t herr = hipHostMalloc((void**)&host, 4 * sizeof(double), hipHostMallocDefault);
+    host = host_scratch() ? (double*)(host_scratch() + 8) : nullptr;
+    hipError_t herr = host ? hipSuccess : hipErrorOutOfMemory;
     if (herr != hipSuccess) {
         (void)hipFreeAsync(ws, s);
         return hip_fail(herr, "hipHostMalloc");
@@ -669,7 +670,6 @@ out:
 #undef STEP
     (void)hipFreeAsync(ws, s);
     (void)hipStreamSynchronize(s);
-    (void)hipHostFree(host);
     if (gave_up) {
         set_last_error("pcg: a triangular solve gave up waiting, or the residual is not finite");
         return SRW_E_HIP;

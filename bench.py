@@ -156,7 +156,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the walk build and PCG of this library run on a "
-              "single MI355X; multi-GPU runs are not part of this build.", file=sys.stderr)
+              "single MI355X; it has no multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,0 +1,177 @@
+"""Parity at full size, in the launch configuration bench.py times.
+
+3D grid 128^3 (n = 2,097,152), 256 walks per row, drop 1e-4: the ordering of every
+node, and for sampled rows (the 16 lowest-ranked, whose walks are the longest, and 240
+drawn uniformly) every walk record, the tallies and the factor row, bit-exact with the
+oracle, which computes those rows one by one.  PCG to 1e-8 and the preconditioner are
+checked through properties that hold at any size: the true residual, recomputed on the
+host, and Y^T D Y z = r for z = M^{-1} r.  The asymmetric 128^3 grid gets the same
+sampled check for both of its games, and the random geometric graph (n = 2,000,000,
+512 walks per row, FP32 factor under FP64 PCG to 1e-10; generated in about a minute on
+the host) for its FP32 factor rows, which must be the oracle's FP64 rows rounded once.
+The batch of 256 pruned grids (8.86M rows, 64 walks per row, 8 right-hand sides each):
+sampled blocks of the batched factor equal the single builds of their matrices, which
+are bit-exact with the oracle on sampled rows, and every one of the 2,048 systems meets
+1e-8 on its true residual.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_math_0609672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def srw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_math_0609672_amd import srw as s
+    return s
+
+
+DEV = "cuda:0"
+WALKS, DROP, SEED = 256, 1e-4, 0
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def sampled_rows(rank, n, seed=1, low=(0, 16)):
+    """Rows ranked low[0] .. low[1] - 1 (long walks) and 240 rows drawn uniformly."""
+    by_rank = np.argsort(rank)
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([by_rank[low[0]:low[1]], rng.choice(n, 240, replace=False)]))
+
+
+def check_game(A, F, rk, rows, walks=WALKS, fp32=False):
+    """Records, tallies and factor rows of the sampled rows against the oracle."""
+    rec = F.records()
+    tl = F.tallies()
+    ex = {k: np_(v) for k, v in F.export().items()}
+    tb = O.table(A, rk)
+    wk = O.walk_rows(A, rk, tb, SEED, rows, walks)
+    off = np_(rec["rec_off"])
+    budget = np_(tl["walks"])
+    for r, k in enumerate(rows):
+        m = int(budget[k])
+        assert m == wk.budget[r]
+        if m == 0:
+            continue
+        s = slice(wk.rec_off[r], wk.rec_off[r + 1])
+        g = slice(int(off[k]), int(off[k]) + m)
+        assert np.array_equal(np_(rec["end"][g]), wk.end[s]), k
+        assert np.array_equal(np_(rec["visits"][g]).view(np.uint32), wk.visits[s]), k
+        assert np.array_equal(np_(rec["length"][g]).view(np.uint32), wk.length[s]), k
+    t = O.tally(wk)
+    idx = torch.as_tensor(rows, device=DEV)
+    assert np.array_equal(np_(tl["J"][idx]).view(np.uint64), t.J)
+    assert np.array_equal(np_(tl["G"][idx]).view(np.uint32), t.G)
+    assert np.array_equal(np_(tl["hlen"][idx]), t.hlen)
+    ref = O.assemble(A, rk, tb, t, rows, DROP)
+    for k in rows:
+        a0, a1 = ex["yptr"][k], ex["yptr"][k + 1]
+        b0, b1 = ref.yptr[k], ref.yptr[k + 1]
+        assert np.array_equal(ex["ycol"][a0:a1], ref.ycol[b0:b1]), k
+        want = ref.yval[b0:b1].astype(np.float32) if fp32 else ref.yval[b0:b1]
+        assert np.array_equal(ex["yval"][a0:a1], want), k
+        assert ex["d"][k] == (np.float32(ref.d[k]) if fp32 else ref.d[k]), k
+    return ex
+
+
+def test_grid3d_128_sampled_rows_and_pcg(srw):
+    A = W.config_grid3d(128, 0)
+    n = A.n
+    Mx = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(Mx, WALKS, DROP, SEED, keep=2)
+    rk = O.rank(n, SEED)
+    ex0 = np_(F.export()["rank"])
+    assert np.array_equal(ex0, rk)
+    rows = sampled_rows(rk, n)
+    ex = check_game(A, F, rk, rows)
+    # PCG to 1e-8: true residual on the host
+    b = W.rhs(n, seed=0)
+    st, x, it, rel = srw.pcg_solve(Mx, F, torch.as_tensor(b, device=DEV), 1e-8)
+    S = A.to_scipy()
+    xr = np_(x)
+    assert st == 0 and rel <= 1e-8
+    assert np.linalg.norm(b - S @ xr) <= 1e-8 * np.linalg.norm(b)
+    # the preconditioner: Y^T D Y z = r (Y unit, strictly lower in rank, node labels)
+    import scipy.sparse as sp
+    r = np.random.default_rng(2).standard_normal(n)
+    z = np_(srw.apply(F, torch.as_tensor(r, device=DEV)))
+    Y = sp.csr_matrix((ex["yval"], ex["ycol"], ex["yptr"]), shape=(n, n)) + sp.identity(n, format="csr")
+    back = Y.T @ (ex["d"] * (Y @ z))
+    assert np.linalg.norm(back - r) <= 1e-10 * np.linalg.norm(r)
+
+
+def test_grid3d_asym_128_sampled_rows_both_games(srw):
+    A = W.config_grid3d_asym(128, 0)
+    n = A.n
+    Mx = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor_ldu(Mx, WALKS, DROP, SEED, keep=2)
+    rk = O.rank(n, SEED)
+    rows = sampled_rows(rk, n, seed=3)
+    check_game(A, F, rk, rows)
+    check_game(O.transpose(A), F.transpose_game(), rk, rows)
+    b = W.rhs(n, seed=0)
+    st, x, it, rel = srw.bicgstab_solve(Mx, F, torch.as_tensor(b, device=DEV), 1e-8)
+    assert st == 0 and rel <= 1e-8
+    assert np.linalg.norm(b - A.to_scipy() @ np_(x)) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_rgg_2m_fp32_sampled_rows_and_pcg(srw):
+    A = W.config_rgg()
+    n = A.n
+    Mx = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(Mx, 512, DROP, SEED, keep=2, precision="fp32")
+    rk = O.rank(n, SEED)
+    # ranks 64 .. 71: the oracle follows the walks of the very lowest ranks (up to
+    # 7.7e5 steps each, 6.5e8 steps for 16 rows) too slowly for a test
+    rows = sampled_rows(rk, n, seed=4, low=(64, 72))
+    check_game(A, F, rk, rows, walks=512, fp32=True)
+    b = W.rhs(n, seed=0)
+    st, x, it, rel = srw.pcg_solve(Mx, F, torch.as_tensor(b, device=DEV), 1e-10)
+    assert st == 0 and rel <= 1e-10
+    assert np.linalg.norm(b - A.to_scipy() @ np_(x)) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_batch_256_sampled_blocks_and_pcg(srw):
+    mats = W.config_batch(256, seed=0)
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    seeds = list(range(256))
+    F = srw.build_factor_batched(Ms, 64, 1e-3, seeds)
+    nmat, off = srw.batch_info(F)
+    assert nmat == 256
+    N = off[-1]
+    ex = {k: np_(v) for k, v in F.export().items()}
+    sizes = np.array([A.n for A in mats])
+    for i in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 128}):
+        A = mats[i]
+        a, b = off[i], off[i + 1]
+        rk = O.rank(A.n, seeds[i])
+        assert np.array_equal(ex["rank"][a:b] - a, rk)
+        rows = np.random.default_rng(i).choice(A.n, min(A.n, 64), replace=False)
+        tb = O.table(A, rk)
+        wk = O.walk_rows(A, rk, tb, seeds[i], rows, 64)
+        ref = O.assemble(A, rk, tb, O.tally(wk), rows, 1e-3)
+        for k in rows:
+            g0, g1 = ex["yptr"][a + k], ex["yptr"][a + k + 1]
+            assert np.array_equal(ex["ycol"][g0:g1] - a, ref.ycol[ref.yptr[k]:ref.yptr[k + 1]]), (i, k)
+            assert np.array_equal(ex["yval"][g0:g1], ref.yval[ref.yptr[k]:ref.yptr[k + 1]]), (i, k)
+            assert ex["d"][a + k] == ref.d[k], (i, k)
+    Bh = np.random.default_rng(0).standard_normal((N, 8))
+    st, X, it, rel = srw.pcg_solve_batched(F, torch.as_tensor(Bh, device=DEV), 1e-8, 1000)
+    assert st == srw.OK
+    Xh = np_(X)
+    worst = 0.0
+    for i, A in enumerate(mats):
+        S = A.to_scipy()
+        a, b = off[i], off[i + 1]
+        R = Bh[a:b] - S @ Xh[a:b]
+        worst = max(worst, float(np.max(np.linalg.norm(R, axis=0) / np.linalg.norm(Bh[a:b], axis=0))))
+    assert worst <= 1e-8

@@ -71,6 +71,8 @@ def parse():
                          "(fp32 <-> fp64) and report it under ext_precision")
     ap.add_argument("--walks", type=int, default=0,
                     help="walks per row instead of the workload's (0 keeps the workload's)")
+    ap.add_argument("--walk-waves", type=int, default=0,
+                    help="waves per CU of the persistent walk kernel (0 = the library default)")
     ap.add_argument("--reuse", action="store_true",
                     help="walk reuse (Section 5.3): the walks extracted from every walk join "
                          "the tallies of their start rows")
@@ -190,7 +192,7 @@ def main():
         F = build(M, walks, drop, args.seed, precision=args.precision,
                   refill_period=args.refill, schedule=args.schedule,
                   solve_order=args.solve_order, profile=True, walks=budgets,
-                  reuse=args.reuse)
+                  reuse=args.reuse, walk_waves=args.walk_waves)
         t1 = time.perf_counter()
         st, _, it, rel = solve(M, F, b, tol, 10000, x=x)
         t2 = time.perf_counter()
@@ -219,7 +221,7 @@ def main():
     s0 = runs[-1]["stats"]
     F = build(M, walks, drop, args.seed, precision=args.precision,
               refill_period=args.refill, schedule=args.schedule,
-              solve_order=args.solve_order, reuse=args.reuse)
+              solve_order=args.solve_order, reuse=args.reuse, walk_waves=args.walk_waves)
     depth = F.depth()  # reported only; outside the timed steps
     F.free()
     walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in runs) / K

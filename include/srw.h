@@ -95,6 +95,12 @@ typedef struct {
                                   not for batched builds.  A walk keeps at most 64
                                   open segments (else SRW_E_WALK_LIMIT, see
                                   srw_last_error).  0 (default) = off               */
+    int32_t walk_waves;        /* waves per compute unit that the persistent walk
+                                  kernel runs: 4..64, rounded down to a multiple of
+                                  4 and capped at what the kernel's registers allow;
+                                  0 = 8.  Fewer walks in flight than the chip can hold
+                                  see shorter memory latency per step, which bounds
+                                  the longest walks; results do not depend on it     */
 } srw_options;
 
 void srw_default_options(srw_options* opt);

@@ -200,6 +200,11 @@ __global__ void k_rank_given(int64_t n, const int32_t* __restrict__ given, int32
 // one XCD share a compact part of the graph and of that XCD's L2.
 constexpr int NSLAB = 8;
 constexpr uint32_t REUSE_STACK = 64;  // walk reuse: stack entries per lane
+// Default waves per CU of the walk kernel.  A walk step is one dependent record load,
+// so the longest walks run at the memory latency the other walks cause: on a 3D grid
+// (128^3, 256 walks per row) 8 waves per CU finish the walks in 175 ms, 24 (all that
+// fit) in 205 ms, 4 in 283 ms.
+constexpr int WALK_WAVES_PER_CU = 8;
 constexpr int NSEG = NSLAB + 1;
 
 __global__ void k_flag_long(int64_t n, int64_t long_rank, const int32_t* __restrict__ by_rank,
@@ -264,12 +269,12 @@ __global__ __launch_bounds__(64) void k_length_rule(int64_t n, const int32_t* __
                                                     double delta, double z, int32_t min_walks,
                                                     int32_t* __restrict__ found)
 {
-    const int64_t k = blockIdx.x;
     const int lane = threadIdx.x;
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const int32_t m = budget[k];
     if (m == 0) {
         if (lane == 0) found[k] = -1;
-        return;
+        continue;
     }
     const int64_t base = rec_off[k];
     uint64_t s1 = 0, s2 = 0;  // sums over the walks before this chunk
@@ -300,10 +305,13 @@ __global__ __launch_bounds__(64) void k_length_rule(int64_t n, const int32_t* __
         s2 += __shfl(p2, 63, 64);
     }
     if (lane == 0) found[k] = hit;
+    }
 }
 
 // --------------------------------------------------------------------- tallies
-// One wave per row.  LDS: P sort keys (P = power of two >= budget) + P run heads.
+// One wave per row, rows in a grid-stride loop.  LDS: P sort keys (P = power of two >=
+// budget) + P run heads.  Launched with one workgroup per row: on a 3D grid (2.1M
+// rows, 256 walks each) that takes 6.8 ms, a chip-sized grid looping over rows 8.5 ms.
 __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restrict__ budget,
                                               const int64_t* __restrict__ rec_off,
                                               const uint32_t* rec_end,
@@ -318,10 +326,9 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
     extern __shared__ uint32_t lds[];
     uint32_t* key = lds;
     uint32_t* head = lds + P;
-    const int64_t k = blockIdx.x;
-    if (k >= n) return;
-    const int m = budget[k];
     const int lane = threadIdx.x;
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const int m = budget[k];
     if (m == 0) {  // exact row: no walks
         if (lane == 0) {
             J[k] = 0;
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
             vsq[k] = 0;
             hlen[k] = 0;
         }
-        return;
+        continue;
     }
     const int64_t base = rec_off[k];
     uint64_t jv = 0, sl = 0, vq = 0;
@@ -391,6 +398,8 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
         vsq[k] = vq;
         hlen[k] = run;
     }
+    __syncthreads();  // the next row reuses the LDS
+    }
 }
 
 // ------------------------------------------------------- tallies, walk reuse
@@ -425,7 +434,7 @@ __global__ void k_row_count(int64_t n, const int64_t* __restrict__ beg, int32_t*
     if (k < n) cnt[k] = (int32_t)(beg[k + 1] - beg[k]);
 }
 
-// One wave per row over its sorted records: the sums of k_tally and the H list
+// One wave per row (grid-stride over rows) over its sorted records: the sums of k_tally and the H list
 // (distinct end nodes, ascending, with counts) written from beg[k] on.  A run of equal
 // end nodes starts at a head; the count of a run is the distance from its head to
 // the next head (or to the first ground record).
@@ -435,10 +444,9 @@ __global__ __launch_bounds__(64) void k_tally_sorted(
     uint32_t* __restrict__ G, uint64_t* __restrict__ steps, uint64_t* __restrict__ vsq,
     int32_t* __restrict__ hlen, uint32_t* __restrict__ h_end, uint32_t* __restrict__ h_cnt)
 {
-    const int64_t k = blockIdx.x;
-    if (k >= n) return;
     const int lane = threadIdx.x;
     const uint64_t lt = lanemask_lt();
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const int64_t b = beg[k], e = beg[k + 1];
     uint64_t jv = 0, sl = 0, vq = 0;
     uint32_t g = 0;
@@ -491,6 +499,7 @@ __global__ __launch_bounds__(64) void k_tally_sorted(
         steps[k] = sl;
         vsq[k] = vq;
         hlen[k] = run;
+    }
     }
 }
 
@@ -672,6 +681,18 @@ __global__ void k_sum_u64(int64_t n, const uint64_t* __restrict__ x, unsigned lo
         s += x[i];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (unsigned long long)s);
+}
+
+// Grid of the one-wave-per-row kernels that loop over rows: 32 single-wave workgroups
+// per CU, at least one and at most one per row.
+unsigned row_grid(int64_t n)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)cus * 32));
 }
 
 int map_err(int e)
@@ -1112,7 +1133,6 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             int dev = 0, cus = 0;
             CHECK_HIP(hipGetDevice(&dev));
             CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            // persistent grid: as many blocks as fit on the chip at once
             void (*kern)(WalkArgs) = nullptr;
             if (reuse) {
                 kern = k_walk_reuse;
@@ -1124,9 +1144,11 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
                     default: kern = k_walk<1>; break;
                 }
             }
+            // persistent grid of walk_waves waves per CU (at most what fits)
             int per_cu = 0;
             CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
-            int64_t blocks = (int64_t)cus * std::max(1, per_cu);
+            const int want = (opt.walk_waves > 0 ? opt.walk_waves : WALK_WAVES_PER_CU) / (BLOCK / 64);
+            int64_t blocks = (int64_t)cus * std::max(1, std::min(per_cu, want));
             blocks = std::min<int64_t>(blocks, (n_chunks + BLOCK / 64 - 1) / (BLOCK / 64));
             if (blocks < 1) blocks = 1;
             if (!reuse) {
@@ -1179,7 +1201,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (herr) FAIL(map_err(herr));
         F->deg_sum = pinned[5];
         if (rule) {  // walks only: the stopping rule's verdict per row, no factor
-            k_length_rule<<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
+            k_length_rule<<<row_grid(n), 64, 0, s>>>(
                 n, budget, rec_off, rec_len, rule->delta, rule->z, rule->min_walks, rule->found);
             CHECK_HIP(hipGetLastError());
             CHECK_HIP(hipStreamSynchronize(s));
@@ -1241,7 +1263,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             // one wave per row over its sorted records; the walks per row become the
             // counted walks
             k_row_count<<<g, BLOCK, 0, s>>>(n, h_off, budget);
-            k_tally_sorted<<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
+            k_tally_sorted<<<row_grid(n), 64, 0, s>>>(
                 n, h_off, ko, vo, out_vl, tJ, tG, tsteps, tvsq, hlen, h_end, h_cnt);
             CHECK_HIP(hipGetLastError());
         } else if (max_budget > 0) {

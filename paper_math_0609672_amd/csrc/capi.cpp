@@ -38,6 +38,7 @@ int options_ok(const srw_options* opt, int64_t n)
     if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && n > 0) return SRW_E_ARG;
     if (opt->reuse != 0 && opt->reuse != 1) return SRW_E_ARG;
     if (opt->reuse && (opt->keep == 2 || (rp != 0 && rp != 8))) return SRW_E_ARG;
+    if (opt->walk_waves != 0 && (opt->walk_waves < 4 || opt->walk_waves > 64)) return SRW_E_ARG;
     return SRW_OK;
 }
 
@@ -59,6 +60,7 @@ void srw_default_options(srw_options* opt)
     opt->schedule = 1;
     opt->solve_order = 1;
     opt->reuse = 0;
+    opt->walk_waves = 0;
 }
 
 

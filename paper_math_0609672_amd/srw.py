@@ -39,7 +39,8 @@ class _Options(ctypes.Structure):
                 ("factor_precision", ctypes.c_int32), ("max_steps", ctypes.c_uint64),
                 ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("solve_order", ctypes.c_int32), ("reuse", ctypes.c_int32)]
+                ("solve_order", ctypes.c_int32), ("reuse", ctypes.c_int32),
+                ("walk_waves", ctypes.c_int32)]
 
 
 NUM_PHASES = 8
@@ -260,11 +261,11 @@ def _check(st: int, what: str):
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
                  profile: bool = False, schedule: int = 1, solve_order: int = 1,
-                 reuse: bool = False, stream=None) -> Factor:
+                 reuse: bool = False, walk_waves: int = 0, stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A (with reuse, the
     walks extracted by Algorithm "reuse" of Section 5.3 join the tallies)."""
     opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-                   solve_order, reuse)
+                   solve_order, reuse, walk_waves)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),
@@ -276,10 +277,11 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
 def build_factor_ldu(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None,
                      walks=None, precision: str = "fp64", max_steps: int = 0, keep: int = 0,
                      refill_period: int = 0, profile: bool = False, schedule: int = 1,
-                     solve_order: int = 1, reuse: bool = False, stream=None) -> Factor:
+                     solve_order: int = 1, reuse: bool = False, walk_waves: int = 0,
+                     stream=None) -> Factor:
     """srw_build_factor_ldu: the two-game preconditioner of an asymmetric A (Section 7.1)."""
     opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-                   solve_order, reuse)
+                   solve_order, reuse, walk_waves)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor_ldu(ctypes.byref(csr), int(walks_per_row), float(drop_tol),
@@ -306,7 +308,7 @@ def bicgstab_solve(A: Matrix, F, b: torch.Tensor, tol: float, max_iter: int = 10
 
 
 def _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-             solve_order, reuse) -> _Options:
+             solve_order, reuse, walk_waves=0) -> _Options:
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
     if rank is not None:
@@ -322,6 +324,7 @@ def _options(rank, walks, precision, max_steps, keep, refill_period, profile, sc
     opt.schedule = int(schedule)
     opt.solve_order = int(solve_order)
     opt.reuse = 1 if reuse else 0
+    opt.walk_waves = int(walk_waves)
     return opt
 
 

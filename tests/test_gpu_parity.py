@@ -74,9 +74,9 @@ def test_table_bit_exact(srw, name):
     assert np.array_equal(np_(tb["grounded"]), ref.grounded)
 
 
-def compare_walks(srw, A, walks, seed, budget=None, refill=0, schedule=0):
+def compare_walks(srw, A, walks, seed, budget=None, refill=0, schedule=0, walk_waves=0):
     Mx = srw.Matrix.from_host(A, DEV)
-    kw = dict(keep=2, refill_period=refill, schedule=schedule)
+    kw = dict(keep=2, refill_period=refill, schedule=schedule, walk_waves=walk_waves)
     if budget is not None:
         kw["walks"] = torch.as_tensor(budget, dtype=torch.int32, device=DEV)
     F = srw.build_factor(Mx, walks, 0.0, seed, **kw)
@@ -119,6 +119,14 @@ def test_walks_and_tallies_bit_exact(srw, name):
 def test_walks_independent_of_scheduling(srw, refill, schedule):
     A, walks = CASES["grid3d_12"]
     compare_walks(srw, A, walks, 21, refill=refill, schedule=schedule)
+
+
+@pytest.mark.parametrize("walk_waves", [4, 12, 24, 64])
+def test_walks_independent_of_walk_waves(srw, walk_waves):
+    # the persistent walk grid's size (64: capped at the kernel's occupancy) moves walks
+    # between lanes and waves only
+    A, walks = CASES["random_3000"]
+    compare_walks(srw, A, walks, 8, walk_waves=walk_waves)
 
 
 def test_per_row_budgets_ragged(srw):

@@ -139,16 +139,16 @@ def walk_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, walk_waves):
     """HBM bytes per walk launch from the committed counter summary, if it was taken
-    on this workload with the walk kernel's current source; else None."""
+    on this workload with the walk kernel's current source and grid; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if (t.get("source_sha256") != walk_source_sha() or t.get("workload") != workload
-            or t.get("precision") != precision):
+            or t.get("precision") != precision or t.get("walk_waves_per_cu") != walk_waves):
         return None
     return t.get("traffic_bytes")
 
@@ -276,6 +276,7 @@ def main():
         "walk_steps": steps_per_build,
         "walks": s0["walks"],
         "tallied_walks": s0["tallied_walks"],
+        "walk_waves_per_cu": s0["walk_waves"],
         "build_s": round(build_s, 4),
         "pcg_s": round(pcg_s, 4),
         "solver": "bicgstab" if asym else "pcg",
@@ -335,7 +336,7 @@ def main():
         del src, dst
     # counters were taken on the workload's own walk budget
     default_walks = not (args.reuse or args.walks or args.adaptive > 0 or asym)
-    out["roofline"]["traffic"] = (measured_traffic(args.workload, args.precision)
+    out["roofline"]["traffic"] = (measured_traffic(args.workload, args.precision, s0["walk_waves"])
                                   if default_walks else None)
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle sample)")

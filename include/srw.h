@@ -167,6 +167,7 @@ typedef struct {
                               simulated walks plus the extracted ones              */
     int32_t reuse;         /* srw_options.reuse of the build                        */
     int32_t two_game;      /* 1 for a factor of srw_build_factor_ldu                */
+    int32_t walk_waves;    /* waves per CU the walk kernel ran (0: no walks)        */
 } srw_stats;
 
 /* Counters and (if profiled) phase times of a factor; host output. */

@@ -1149,6 +1149,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
             const int want = (opt.walk_waves > 0 ? opt.walk_waves : WALK_WAVES_PER_CU) / (BLOCK / 64);
             int64_t blocks = (int64_t)cus * std::max(1, std::min(per_cu, want));
+            F->walk_waves = std::max(1, std::min(per_cu, want)) * (BLOCK / 64);
             blocks = std::min<int64_t>(blocks, (n_chunks + BLOCK / 64 - 1) / (BLOCK / 64));
             if (blocks < 1) blocks = 1;
             if (!reuse) {

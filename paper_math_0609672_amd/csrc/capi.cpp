@@ -226,6 +226,7 @@ int srw_factor_stats(const srw_factor* F, srw_stats* out)
     out->tallied_walks = F->tallied_total;
     out->reuse = F->reuse;
     out->two_game = F->tgame ? 1 : 0;
+    out->walk_waves = F->walk_waves;
     return SRW_OK;
 }
 

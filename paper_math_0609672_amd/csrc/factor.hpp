@@ -20,6 +20,7 @@ struct srw_factor {
     int64_t tallied_total = 0;     // walks in the tallies (with walk reuse, the simulated
                                    // walks plus those extracted from them)
     int32_t reuse = 0;
+    int32_t walk_waves = 0;  // waves per CU of the walk launch
     int64_t deg_sum = 0;
     double phase_ms[SRW_NUM_PHASES] = {-1, -1, -1, -1, -1, -1, -1, -1};
 

@@ -53,7 +53,8 @@ class _Stats(ctypes.Structure):
                 ("walk_deg_sum", ctypes.c_int64), ("levels_fwd", ctypes.c_int32),
                 ("levels_bwd", ctypes.c_int32), ("precision", ctypes.c_int32), ("keep", ctypes.c_int32),
                 ("phase_ms", ctypes.c_double * NUM_PHASES), ("tallied_walks", ctypes.c_int64),
-                ("reuse", ctypes.c_int32), ("two_game", ctypes.c_int32)]
+                ("reuse", ctypes.c_int32), ("two_game", ctypes.c_int32),
+                ("walk_waves", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

@@ -126,7 +126,11 @@ def test_walks_independent_of_walk_waves(srw, walk_waves):
     # the persistent walk grid's size (64: capped at the kernel's occupancy) moves walks
     # between lanes and waves only
     A, walks = CASES["random_3000"]
-    compare_walks(srw, A, walks, 8, walk_waves=walk_waves)
+    F, _ = compare_walks(srw, A, walks, 8, walk_waves=walk_waves)
+    ran = F.stats()["walk_waves"]
+    assert ran % 4 == 0 and 4 <= ran <= walk_waves
+    if walk_waves <= 12:
+        assert ran == walk_waves
 
 
 def test_per_row_budgets_ragged(srw):

@@ -162,7 +162,8 @@ __global__ __launch_bounds__(BLOCK) void k_copy(int64_t n, const double* __restr
 // starts filled with a signalling-NaN pattern that arithmetic never produces; a
 // row's value is published with one device-scope store and is its own ready flag.
 // A waiting wave polls one address only -- that of its missing dependency which the
-// order solves last -- and reloads its other missing values once that one is there.
+// order solves last -- and once that one is there reloads its other missing values,
+// if any.
 // The lane partial sums are added by a wave-wide butterfly, so the result does not
 // depend on timing.
 template <typename T>
@@ -244,7 +245,11 @@ __device__ __forceinline__ void wait_published(typename Bits<T>::U& bits, const 
             __builtin_amdgcn_s_sleep(SRW_POLL_SLEEP);
             continue;
         }
-        if (mine) bits = load_published((const U*)sol + c);
+        // the lead's lane takes the polled value; only the other missing lanes reload
+        // (often there are none, and the row goes on without another round trip)
+        if (mine && c == lead) bits = lb;
+        const bool other = mine && c != lead;
+        if (ballot(other) != 0 && other) bits = load_published((const U*)sol + c);
         miss = ballot(valid && bits == Bits<T>::sentinel);
     }
 }

@@ -363,7 +363,8 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = lane; i < (P >> 1); i += 64) {
-                const int lo = 2 * stride * (i / stride) + (i % stride);
+                // stride is a power of two: pair i's lower index without a division
+                const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
                 const uint32_t x = key[lo], y = key[hi];

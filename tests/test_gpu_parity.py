@@ -189,6 +189,31 @@ def test_solve_order_does_not_change_results(srw, name):
     assert F1.depth() == F0.depth()
 
 
+def test_level_order_matches_rank_order_mid_size(srw):
+    """13,824 rows (several tiles of every kernel): each row's sum has a fixed order,
+    so the level-ordered plan gives the rank-ordered plan's preconditioner and PCG
+    iterates bit for bit, and the preconditioner matches the oracle's factor."""
+    A = W.grid((24, 24, 24), g=("loguniform", 1e-2, 1e2), ground_frac=0.01,
+               excess=("uniform", 0.01, 1.0), seed=4)
+    M = srw.Matrix.from_host(A, DEV)
+    F0 = srw.build_factor(M, 64, 1e-3, 9, solve_order=0)
+    F1 = srw.build_factor(M, 64, 1e-3, 9, solve_order=1)
+    for seed in (8, 9):
+        r = torch.as_tensor(W.rhs(A.n, seed=seed), device=DEV)
+        assert torch.equal(srw.apply(F0, r), srw.apply(F1, r))
+    b = torch.as_tensor(W.rhs(A.n, seed=10), device=DEV)
+    st0, x0, it0, _ = srw.pcg_solve(M, F0, b, 1e-10)
+    st1, x1, it1, _ = srw.pcg_solve(M, F1, b, 1e-10)
+    assert st0 == st1 == srw.OK and it0 == it1
+    assert torch.equal(x0, x1)
+    assert F1.depth() == F0.depth()
+    ref = O.build_factor(A, 64, 1e-3, 9)
+    r = W.rhs(A.n, seed=8)
+    z = np_(srw.apply(F1, torch.as_tensor(r, device=DEV)))
+    zr = O.apply(ref, r)
+    assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("tol", [1e-8, 1e-10])
 def test_pcg_matches_oracle(srw, name, tol):

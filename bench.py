@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=1)
-    ap.add_argument("--solve-order", type=int, default=1)
+    ap.add_argument("--solve-order", type=int, default=2,
+                    help="0 rank order, 1 level order, 2 the library's automatic choice")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--adaptive", type=float, default=0.0, metavar="DELTA",

@@ -84,8 +84,11 @@ typedef struct {
                                   first); 1 (default) = rows ranked below n/256 by
                                   rank, then the rest in node-id slabs, one per XCD */
     int32_t solve_order;       /* order in which the triangular solves take rows:
-                                  0 = rank; 1 (default) = dependency level, then rank
-                                  (the build computes the levels once)              */
+                                  0 = rank; 1 = dependency level, then rank (the
+                                  build computes the levels once); 2 (default) =
+                                  level for batched builds, whose many-system solves
+                                  need it, else rank (as fast there, and the build
+                                  skips the levels)                                  */
     int32_t reuse;             /* 1 = walk reuse (Section 5.3, Algorithm "reuse"):
                                   every walk also counts, for their start nodes, the
                                   walks its two stacks extract (disjoint segments of

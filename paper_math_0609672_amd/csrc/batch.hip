@@ -463,6 +463,7 @@ int build_batched_impl(int32_t nmat, const srw_csr* A, int32_t walks_per_row, do
     srw_options opt = *opt_in;
     opt.ordering = SRW_ORDER_GIVEN;
     opt.rank = rank;
+    if (opt.solve_order == 2) opt.solve_order = 1;  // the batched solves need the levels
     srw_csr cat{N, NNZ, rowptr, col, val};
     BatchKeys keys{node_mat, mat_off, mat_seed};
     srw_factor* F = nullptr;

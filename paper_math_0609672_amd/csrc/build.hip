@@ -1397,7 +1397,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipMemsetAsync(F->bptr, 0, sizeof(int64_t), s));
         }
         // level order: slots by (dependency level, rank)
-        if (opt.solve_order == 1 && n > 0) {
+        if (opt.solve_order == 1 && n > 0) {  // 2 (automatic) is the rank order here
             int32_t* lev = ALLOC(tmp, int32_t, n);
             uint32_t* lkey = ALLOC(tmp, uint32_t, n);
             uint32_t* lkey2 = ALLOC(tmp, uint32_t, n);

@@ -34,7 +34,7 @@ int options_ok(const srw_options* opt, int64_t n)
     const int rp = opt->refill_period;
     if (rp != 0 && rp != 1 && rp != 2 && rp != 4 && rp != 8) return SRW_E_ARG;
     if (opt->schedule != 0 && opt->schedule != 1) return SRW_E_ARG;
-    if (opt->solve_order != 0 && opt->solve_order != 1) return SRW_E_ARG;
+    if (opt->solve_order < 0 || opt->solve_order > 2) return SRW_E_ARG;
     if (opt->ordering == SRW_ORDER_GIVEN && !opt->rank && n > 0) return SRW_E_ARG;
     if (opt->reuse != 0 && opt->reuse != 1) return SRW_E_ARG;
     if (opt->reuse && (opt->keep == 2 || (rp != 0 && rp != 8))) return SRW_E_ARG;
@@ -58,7 +58,7 @@ void srw_default_options(srw_options* opt)
     opt->refill_period = 0;
     opt->profile = 0;
     opt->schedule = 1;
-    opt->solve_order = 1;
+    opt->solve_order = 2;
     opt->reuse = 0;
     opt->walk_waves = 0;
 }

@@ -261,7 +261,7 @@ def _check(st: int, what: str):
 
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
-                 profile: bool = False, schedule: int = 1, solve_order: int = 1,
+                 profile: bool = False, schedule: int = 1, solve_order: int = 2,
                  reuse: bool = False, walk_waves: int = 0, stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A (with reuse, the
     walks extracted by Algorithm "reuse" of Section 5.3 join the tallies)."""
@@ -278,7 +278,7 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
 def build_factor_ldu(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None,
                      walks=None, precision: str = "fp64", max_steps: int = 0, keep: int = 0,
                      refill_period: int = 0, profile: bool = False, schedule: int = 1,
-                     solve_order: int = 1, reuse: bool = False, walk_waves: int = 0,
+                     solve_order: int = 2, reuse: bool = False, walk_waves: int = 0,
                      stream=None) -> Factor:
     """srw_build_factor_ldu: the two-game preconditioner of an asymmetric A (Section 7.1)."""
     opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
@@ -435,7 +435,7 @@ def mlp_budgets(pred: torch.Tensor, eps: float, lo: int, hi: int, stream=None) -
 # ---------------------------------------------------------------- batched solves
 def build_factor_batched(mats, walks_per_row: int, drop_tol: float, seeds, *, walks=None,
                          precision: str = "fp64", keep: int = 0, profile: bool = False,
-                         solve_order: int = 1, stream=None) -> Factor:
+                         solve_order: int = 2, stream=None) -> Factor:
     """srw_build_factor_batched: one factor for a list of Matrix objects stacked
     block-diagonally (matrix i ordered and walked with seeds[i])."""
     import numpy as np

@@ -125,3 +125,27 @@ def test_walk_waves_option_range_without_gpu():
         st = lib.srw_build_factor(ctypes.byref(A), 8, ctypes.c_double(0.0), ctypes.c_uint64(0),
                                   ctypes.byref(opt), ctypes.byref(out), None)
         assert st == -1, w
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsrw.so not built")
+def test_solve_order_option_range_without_gpu():
+    """srw_options.solve_order: 0 rank, 1 level, 2 automatic (the default)."""
+    from paper_math_0609672_amd import srw
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+
+    class Csr(ctypes.Structure):
+        _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", P), ("col", P),
+                    ("val", P)]
+
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the option checks fail first
+    A = Csr(4, 4, fake, fake, fake)
+    out = ctypes.c_void_p(0)
+    opt = srw._Options()
+    lib.srw_default_options(ctypes.byref(opt))
+    assert opt.solve_order == 2
+    for v in (-1, 3, 7):
+        opt.solve_order = v
+        st = lib.srw_build_factor(ctypes.byref(A), 8, ctypes.c_double(0.0), ctypes.c_uint64(0),
+                                  ctypes.byref(opt), ctypes.byref(out), None)
+        assert st == -1, v

@@ -184,9 +184,11 @@ def test_solve_order_does_not_change_results(srw, name):
     M = srw.Matrix.from_host(A, DEV)
     F0 = srw.build_factor(M, walks, 1e-3, 6, solve_order=0)
     F1 = srw.build_factor(M, walks, 1e-3, 6, solve_order=1)
+    F2 = srw.build_factor(M, walks, 1e-3, 6, solve_order=2)
     r = torch.as_tensor(W.rhs(A.n, seed=8), device=DEV)
-    assert torch.equal(srw.apply(F0, r), srw.apply(F1, r))
-    assert F1.depth() == F0.depth()
+    z0 = srw.apply(F0, r)
+    assert torch.equal(z0, srw.apply(F1, r)) and torch.equal(z0, srw.apply(F2, r))
+    assert F1.depth() == F0.depth() == F2.depth()
 
 
 def test_level_order_matches_rank_order_mid_size(srw):

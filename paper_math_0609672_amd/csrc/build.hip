@@ -413,13 +413,14 @@ __global__ void k_iota_u32(int64_t n, uint32_t* x)
     if (i < n) x[i] = (uint32_t)i;
 }
 
-// beg[k] = first record of row k (k = 0..n; beg[n] = m), by binary search
+// beg[k] = first of the m sorted keys whose bits from `shift` up are >= k (k = 0..n;
+// beg[n] = m when every key is below n << shift), by binary search
 __global__ void k_row_begin(int64_t n, const uint64_t* __restrict__ key, int64_t m,
-                            int64_t* __restrict__ beg)
+                            int64_t* __restrict__ beg, int shift = 32)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k > n) return;
-    const uint64_t want = (uint64_t)k << 32;
+    const uint64_t want = (uint64_t)k << shift;
     int64_t lo = 0, hi = m;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
@@ -577,24 +578,21 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
 // Sort key of entry (k, i) of Y for the rows of Y^T: column i first, then the rank
 // of k descending -- the order in which the backward substitution finishes the
 // w_k it needs, so a long Y^T row meets its last-ready values at its end.
+// Sixteen lanes per row (rows of Y hold about twenty entries), entries strided by 16.
 __global__ void k_entry_keys(int64_t n, const int64_t* __restrict__ yptr,
                              const int32_t* __restrict__ ycol, const int32_t* __restrict__ rank,
                              int rank_bits, uint32_t* rowid, uint32_t* idx, uint64_t* key)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = t >> 4;
     if (k >= n) return;
     const uint64_t rdesc = (uint64_t)(n - 1 - rank[k]);
-    for (int64_t q = yptr[k]; q < yptr[k + 1]; ++q) {
+    const int64_t e = yptr[k + 1];
+    for (int64_t q = yptr[k] + (t & 15); q < e; q += 16) {
         rowid[q] = (uint32_t)k;
         idx[q] = (uint32_t)q;
         key[q] = ((uint64_t)(uint32_t)ycol[q] << rank_bits) | rdesc;
     }
-}
-
-__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ ycol, int32_t* cnt)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nnz) atomicAdd(&cnt[ycol[q]], 1);
 }
 
 template <typename T>
@@ -1335,19 +1333,17 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             uint32_t* idx2 = ALLOC(tmp, uint32_t, nnz_y);
             uint64_t* key = ALLOC(tmp, uint64_t, nnz_y);
             uint64_t* key2 = ALLOC(tmp, uint64_t, nnz_y);
-            int32_t* ccount = ALLOC(tmp, int32_t, n);
             void* rt = ALLOC(tmp, char, radix_tmp_bytes(nnz_y));
-            if (!rowid || !idx || !idx2 || !key || !key2 || !ccount || !rt) FAIL(SRW_E_NOMEM);
+            if (!rowid || !idx || !idx2 || !key || !key2 || !rt) FAIL(SRW_E_NOMEM);
             int rbits = 1;
             while (rbits < 31 && ((int64_t)1 << rbits) < n) ++rbits;
-            k_entry_keys<<<g, BLOCK, 0, s>>>(n, F->yptr, F->ycol, F->rank, rbits, rowid, idx, key);
+            k_entry_keys<<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(n, F->yptr, F->ycol, F->rank,
+                                                                   rbits, rowid, idx, key);
             uint64_t* ko;
             uint32_t* vo;
             CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, 2 * rbits, rt, &ko, &vo, s));
-            CHECK_HIP(hipMemsetAsync(ccount, 0, n * sizeof(int32_t), s));
-            k_col_count<<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(nnz_y, F->ycol, ccount);
-            CHECK_HIP(exclusive_scan_i32_to_i64(ccount, ytptr, n, st, s));
-            k_set_last<<<1, 1, 0, s>>>(ytptr, n, nnz_y);
+            // rows of Y^T: where each column's run of sorted keys begins
+            k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, nnz_y, ytptr, rbits);
             if (fp32)
                 k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
                     nnz_y, vo, rowid, (const float*)F->yval, ytcol, (float*)ytval);

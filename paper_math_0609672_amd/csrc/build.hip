@@ -403,6 +403,121 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
     }
 }
 
+// The same tallies for budgets up to 2048 walks, without sorting every end node: the
+// ends go into an LDS hash table of 2P slots (linear probing, counts by atomic add),
+// the distinct ones (about C/N of them) are compacted in slot order and only those are
+// sorted, as (node << 32 | count).  The H list is then the same as k_tally's.
+// LDS: 2P keys + 2P counts (u32) + P pairs (u64).
+__global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __restrict__ budget,
+                                                   const int64_t* __restrict__ rec_off,
+                                                   const uint32_t* rec_end,
+                                                   const uint32_t* rec_vis,
+                                                   const uint32_t* __restrict__ rec_len, int P,
+                                                   uint64_t* __restrict__ J,
+                                                   uint32_t* __restrict__ G,
+                                                   uint64_t* __restrict__ steps,
+                                                   uint64_t* __restrict__ vsq,
+                                                   int32_t* __restrict__ hlen, uint32_t* h_end,
+                                                   uint32_t* h_cnt)
+{
+    extern __shared__ uint64_t lds64[];
+    const int HS = 2 * P;                      // table slots, a power of two
+    uint64_t* cp = lds64;                      // [P] compacted (node << 32 | count)
+    uint32_t* tk = (uint32_t*)(lds64 + P);     // [HS] keys, END_GROUND = empty
+    uint32_t* tc = tk + HS;                    // [HS] counts
+    const int64_t k = blockIdx.x;
+    if (k >= n) return;
+    const int m = budget[k];
+    const int lane = threadIdx.x;
+    if (m == 0) {  // exact row: no walks
+        if (lane == 0) {
+            J[k] = 0;
+            G[k] = 0;
+            steps[k] = 0;
+            vsq[k] = 0;
+            hlen[k] = 0;
+        }
+        return;
+    }
+    int hbits = 0;
+    while ((1 << hbits) < HS) ++hbits;
+    for (int i = lane; i < HS; i += 64) {
+        tk[i] = END_GROUND;
+        tc[i] = 0;
+    }
+    __syncthreads();
+    const int64_t base = rec_off[k];
+    uint64_t jv = 0, sl = 0, vq = 0;
+    uint32_t g = 0;
+    for (int i = lane; i < m; i += 64) {
+        const uint32_t e = rec_end[base + i];
+        const uint64_t v = rec_vis[base + i];
+        jv += v;
+        vq += v * v;
+        sl += rec_len[base + i];
+        if (e == END_GROUND) {
+            ++g;
+            continue;
+        }
+        uint32_t h = (e * 0x9E3779B1u) >> (32 - hbits);
+        for (;;) {  // at most m of the 2P >= 2m slots are taken: an empty one is reached
+            const uint32_t prev = atomicCAS(&tk[h], END_GROUND, e);
+            if (prev == END_GROUND || prev == e) {
+                atomicAdd(&tc[h], 1u);
+                break;
+            }
+            h = (h + 1) & (uint32_t)(HS - 1);
+        }
+    }
+    jv = wave_sum(jv);
+    vq = wave_sum(vq);
+    sl = wave_sum(sl);
+    g = wave_sum(g);
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    int D = 0;
+    for (int i0 = 0; i0 < HS; i0 += 64) {
+        const int i = i0 + lane;
+        const uint32_t key = tk[i];
+        const bool ok = key != END_GROUND;
+        const uint64_t mask = ballot(ok);
+        if (ok) cp[D + __popcll(mask & lt)] = ((uint64_t)key << 32) | tc[i];
+        D += __popcll(mask);
+    }
+    int D2 = 1;
+    while (D2 < D) D2 <<= 1;
+    for (int i = D + lane; i < D2; i += 64) cp[i] = ~0ull;
+    __syncthreads();
+    // bitonic sort of the D2 pairs, ascending
+    for (int size = 2; size <= D2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = lane; i < (D2 >> 1); i += 64) {
+                const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t x = cp[lo], y = cp[hi];
+                if ((x > y) == asc) {
+                    cp[lo] = y;
+                    cp[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = lane; j < D; j += 64) {
+        const uint64_t x = cp[j];
+        h_end[base + j] = (uint32_t)(x >> 32);
+        h_cnt[base + j] = (uint32_t)x;
+    }
+    if (lane == 0) {
+        J[k] = jv;
+        G[k] = g;
+        steps[k] = sl;
+        vsq[k] = vq;
+        hlen[k] = D;
+    }
+}
+
 // ------------------------------------------------------- tallies, walk reuse
 // With walk reuse every counted walk is a record {start node << 32 | end node, stays,
 // steps}; the records are sorted by key, so a row's records are contiguous with
@@ -1269,10 +1384,18 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         } else if (max_budget > 0) {
             int P = 64;
             while (P < max_budget) P <<= 1;
-            const size_t lds = (size_t)(2 * P) * sizeof(uint32_t);
-            if (lds > 64 * 1024) FAIL(SRW_E_ARG);  // budgets above 8192 walks per row
-            k_tally<<<(unsigned)n, 64, lds, s>>>(n, budget, rec_off, rec_end, rec_vis, rec_len, P,
-                                                tJ, tG, tsteps, tvsq, hlen, h_end, h_cnt);
+            if (P <= 2048) {
+                const size_t lds = (size_t)P * sizeof(uint64_t) + (size_t)(4 * P) * sizeof(uint32_t);
+                k_tally_hash<<<(unsigned)n, 64, lds, s>>>(n, budget, rec_off, rec_end, rec_vis,
+                                                         rec_len, P, tJ, tG, tsteps, tvsq, hlen,
+                                                         h_end, h_cnt);
+            } else {
+                const size_t lds = (size_t)(2 * P) * sizeof(uint32_t);
+                if (lds > 64 * 1024) FAIL(SRW_E_ARG);  // budgets above 8192 walks per row
+                k_tally<<<(unsigned)n, 64, lds, s>>>(n, budget, rec_off, rec_end, rec_vis,
+                                                    rec_len, P, tJ, tG, tsteps, tvsq, hlen, h_end,
+                                                    h_cnt);
+            }
             CHECK_HIP(hipGetLastError());
         } else {
             CHECK_HIP(hipMemsetAsync(tJ, 0, n * sizeof(uint64_t), s));

@@ -78,6 +78,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_tile_apply(const In* in, int6
 
 int64_t ntiles(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 
+// block_exclusive for the radix sort's block (same size as the scan's)
+__device__ int64_t block_exclusive_radix(int64_t v, int64_t* out_excl, int64_t* lds_waves)
+{
+    return block_exclusive(v, out_excl, lds_waves);
+}
+
 template <typename In>
 hipError_t scan_impl(const In* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s)
 {
@@ -122,73 +128,114 @@ hipError_t exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n,
 // ------------------------------------------------------------------- radix sort
 namespace {
 
-constexpr int RADIX_BLOCK = 256;  // 4 waves, each an independent tile
-constexpr int RADIX_ITEMS = 32;
-constexpr int64_t RADIX_TILE = 64 * RADIX_ITEMS;
+constexpr int RADIX_BLOCK = 256;  // one tile of RADIX_ITEMS items per thread
+constexpr int RADIX_ITEMS = 16;
+constexpr int64_t RADIX_TILE = (int64_t)RADIX_BLOCK * RADIX_ITEMS;
 
+// Digit counts of each tile; item j*256 + t of the tile is thread t's j-th item.
 template <typename K>
 __global__ __launch_bounds__(RADIX_BLOCK) void radix_hist(const K* keys, int64_t n, int shift,
                                                           int64_t ntile, int32_t* hist)
 {
-    __shared__ int32_t cnt[RADIX_BLOCK / 64][256];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
-    for (int d = lane; d < 256; d += 64) cnt[wave][d] = 0;
+    __shared__ int32_t cnt[256];
+    cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t tile = (int64_t)blockIdx.x * (RADIX_BLOCK / 64) + wave;
-    if (tile < ntile) {
-        const int64_t base = tile * RADIX_TILE;
-        for (int j = 0; j < RADIX_ITEMS; ++j) {
-            const int64_t i = base + (int64_t)j * 64 + lane;
-            if (i < n) atomicAdd(&cnt[wave][(uint32_t)(keys[i] >> shift) & 255u], 1);
-        }
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * RADIX_TILE;
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * RADIX_BLOCK + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(uint32_t)(keys[i] >> shift) & 255u], 1);
     }
     __syncthreads();
-    if (tile < ntile)
-        for (int d = lane; d < 256; d += 64) hist[(int64_t)d * ntile + tile] = cnt[wave][d];
+    hist[(int64_t)threadIdx.x * ntile + tile] = cnt[threadIdx.x];
 }
 
+// One tile per block: every item's rank among the tile's items of its digit (index
+// order: j, then thread), then the tile sorted by digit in LDS, then written out in
+// LDS order, so each digit's items of the tile leave as one contiguous run.  Stable.
 template <typename K>
 __global__ __launch_bounds__(RADIX_BLOCK) void radix_scatter(const K* keys, const uint32_t* vals,
                                                              K* keys_out, uint32_t* vals_out,
                                                              int64_t n, int shift, int64_t ntile,
                                                              const int64_t* offs)
 {
-    __shared__ int64_t off[RADIX_BLOCK / 64][256];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
-    const int64_t tile = (int64_t)blockIdx.x * (RADIX_BLOCK / 64) + wave;
-    if (tile >= ntile) return;  // whole wave leaves; no block barrier below
-    for (int d = lane; d < 256; d += 64) off[wave][d] = offs[(int64_t)d * ntile + tile];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __shared__ K skey[RADIX_TILE];
+    __shared__ uint32_t sval[RADIX_TILE];
+    __shared__ int64_t goff[256];              // the tile's first output index per digit
+    __shared__ int32_t run[256];               // items of the digit placed so far
+    __shared__ int32_t wcnt[RADIX_BLOCK / 64][256];
+    __shared__ int64_t lds_waves[RADIX_BLOCK / 64];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t tile = blockIdx.x;
     const int64_t base = tile * RADIX_TILE;
-    const uint64_t lt = lanemask_lt();
+    goff[t] = offs[(int64_t)t * ntile + tile];
+    run[t] = 0;
+#pragma unroll
+    for (int w = 0; w < RADIX_BLOCK / 64; ++w) wcnt[w][t] = 0;
+    K key[RADIX_ITEMS];
+    uint32_t val[RADIX_ITEMS];
+    int32_t pos[RADIX_ITEMS];
+#pragma unroll
     for (int j = 0; j < RADIX_ITEMS; ++j) {
-        const int64_t i = base + (int64_t)j * 64 + lane;
-        const bool valid = i < n;
-        K key = valid ? keys[i] : K(0);
-        uint32_t val = valid ? vals[i] : 0u;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const int64_t i = base + (int64_t)j * RADIX_BLOCK + t;
+        key[j] = i < n ? keys[i] : K(0);
+        val[j] = i < n ? vals[i] : 0u;
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        const bool valid = base + (int64_t)j * RADIX_BLOCK + t < n;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
         uint64_t peers = ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint64_t bb = ballot(((d >> b) & 1u) != 0);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        const int64_t rank = __popcll(peers & lt);
-        int64_t dst = 0;
-        if (valid) dst = off[wave][d] + rank;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // the highest lane of each peer group advances its digit's offset
-        if (valid && (peers >> lane) == 1ull) off[wave][d] = dst + 1;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (valid) {
-            keys_out[dst] = key;
-            vals_out[dst] = val;
+        // the highest lane of each group of equal digits records the group's size
+        if (valid && (peers >> lane) == 1ull) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        int32_t before = run[d];
+        for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+        pos[j] = valid ? before + (int32_t)__popcll(peers & lt) : -1;
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < RADIX_BLOCK / 64; ++w) {
+            add += wcnt[w][t];
+            wcnt[w][t] = 0;
         }
+        run[t] += add;
+        __syncthreads();
+    }
+    // tile-local start of each digit
+    int64_t start;
+    const int64_t count = block_exclusive_radix(run[t], &start, lds_waves);
+    (void)count;
+    __syncthreads();
+    run[t] = (int32_t)start;  // reused: the digit's first LDS position
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        if (pos[j] >= 0) {
+            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+            const int p = run[d] + pos[j];
+            skey[p] = key[j];
+            sval[p] = val[j];
+        }
+    }
+    __syncthreads();
+    const int64_t m = n - base < RADIX_TILE ? n - base : RADIX_TILE;
+    for (int p = t; p < m; p += RADIX_BLOCK) {
+        const K k = skey[p];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const int64_t dst = goff[d] + (p - run[d]);
+        keys_out[dst] = k;
+        vals_out[dst] = sval[p];
     }
 }
 
@@ -204,7 +251,7 @@ hipError_t radix_impl(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     int32_t* hist = (int32_t*)tmp;
     int64_t* offs = (int64_t*)((char*)tmp + ((nh * sizeof(int32_t) + 255) & ~(size_t)255));
     void* scan_tmp = (char*)offs + ((nh * sizeof(int64_t) + 255) & ~(size_t)255);
-    const unsigned grid = (unsigned)((nt + RADIX_BLOCK / 64 - 1) / (RADIX_BLOCK / 64));
+    const unsigned grid = (unsigned)nt;  // one tile per block
     K *ka = keys, *kb = keys_alt;
     uint32_t *va = vals, *vb = vals_alt;
     for (int shift = 0; shift < bits; shift += 8) {

@@ -270,7 +270,7 @@ __device__ __forceinline__ void emit_walks(const WalkArgs& a, bool em, uint32_t 
 // ranked above the top is pushed, one equal to it is a stay.  The walk ends exactly
 // when the stack empties; the walk itself is the bottom entry's record.
 #ifndef SRW_WALK_WAVES
-#define SRW_WALK_WAVES 6  // waves per SIMD the register budget is cut for
+#define SRW_WALK_WAVES 4  // waves per SIMD the register budget is cut for (the grid runs 2)
 #endif
 template <int R, bool REUSE>
 __device__ __forceinline__ void walk_body(const WalkArgs& a)
@@ -296,6 +296,13 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         REUSE ? a.stack + ((size_t)blockIdx.x * BLOCK + threadIdx.x) * a.stack_depth : nullptr;
     uint64_t steps_acc = 0;
     uint64_t blk_next = 0, blk_end = 0;  // the wave's block of record slots
+    // LOCK: a finished walk's result waits one iteration and is stored just after the
+    // next record load is issued.  Stored at once, the wave had to wait for the stores
+    // to complete before that load could reuse their registers: a store round trip
+    // in front of nearly every step.
+    bool pend = false;
+    uint64_t pend_rec = 0;
+    uint32_t pend_end = 0, pend_vis = 0, pend_len = 0;
 
     for (uint32_t iter = 0;; ++iter) {
         if ((iter % R) == 0 && !done) {
@@ -360,8 +367,13 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
             if (done) break;
             continue;
         }
-        if (active) {  // structured: the lanes rejoin before the next refill's ballots
-        if ((t & 7) == 0) {
+        // LOCK (refill period 8, no reuse): every lane runs the step; an idle lane takes
+        // no entry and loads line 0 (any record line will do), and keeps no result.
+        // Active lanes started their walks at multiples of 8 iterations, so t and the
+        // iteration count agree mod 8 and the random block refresh is wave-uniform.
+        constexpr bool LOCK = !REUSE && R == 8;
+        if (LOCK || active) {  // structured: the lanes rejoin before the next refill's ballots
+        if ((LOCK ? (iter & 7u) : (uint32_t)(t & 7)) == 0) {
             const u64x4 b = philox4x64_10(t >> 3, w, key, STREAM_WALK, seedw, 0);
             q0 = (uint32_t)b.x0; q1 = (uint32_t)(b.x0 >> 32);
             q2 = (uint32_t)b.x1; q3 = (uint32_t)(b.x1 >> 32);
@@ -371,7 +383,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         const uint32_t u = q0;
         q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
 
-        const uint32_t deg = r0.y & DESC_DEG_MASK;
+        const uint32_t deg = (!LOCK || active) ? (r0.y & DESC_DEG_MASK) : 0u;
         degsum += deg;
         // The next node is the first entry m with u < threshold_m; the words of the
         // record's first line are held in registers.
@@ -421,12 +433,19 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         // keeps the load below unconditional
         const bool to_ground = !found && (r0.y & DESC_GROUNDED) != 0;
         if (!found) next_line = e[3];
+        if (LOCK && !active) next_line = 0;
         const uint4* lp = a.recs + (size_t)next_line * 4;
         r0 = lp[0];
         r1 = lp[1];
         r2 = lp[2];
         r3 = lp[3];
         cline = next_line;
+        if (LOCK && pend) {  // the previous iteration's finished walk, behind this load
+            a.rec_end[pend_rec] = pend_end;
+            a.rec_vis[pend_rec] = pend_vis;
+            a.rec_len[pend_rec] = pend_len;
+            pend = false;
+        }
         // home: a node ranked below the row (the first step only reaches higher ranks)
         bool fin = to_ground || r0.x < rank_k;
         uint32_t endv = to_ground ? END_GROUND : r0.z;
@@ -469,7 +488,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
             }
         }
         ++t;
-        if (!fin && t >= a.max_steps) {
+        if (LOCK && !active) fin = false;  // an idle lane keeps nothing
+        if (!fin && active && t >= a.max_steps) {
             fin = true;
             endv = END_LIMIT;
             atomicOr(a.err, ERR_LIMIT);
@@ -477,6 +497,12 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         if (fin) {
             if constexpr (REUSE) {
                 steps_acc += t;
+            } else if constexpr (LOCK) {
+                pend = true;
+                pend_rec = rec;
+                pend_end = endv;
+                pend_vis = visits;
+                pend_len = (uint32_t)t;
             } else {
                 a.rec_end[rec] = endv;
                 a.rec_vis[rec] = visits;
@@ -493,6 +519,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
     if constexpr (REUSE) {
         for (uint64_t q = blk_next + lane; q < blk_end; q += 64)
             if (q < a.out_cap) a.out_key[q] = ~0ull;
+    }
+    if (pend) {  // LOCK: the last finished walk of the lane
+        a.rec_end[pend_rec] = pend_end;
+        a.rec_vis[pend_rec] = pend_vis;
+        a.rec_len[pend_rec] = pend_len;
     }
     degsum = wave_sum(degsum);
     if (lane == 0 && degsum) atomicAdd(a.deg_sum, (unsigned long long)degsum);

@@ -202,8 +202,8 @@ constexpr int NSLAB = 8;
 constexpr uint32_t REUSE_STACK = 64;  // walk reuse: stack entries per lane
 // Default waves per CU of the walk kernel.  A walk step is one dependent record load,
 // so the longest walks run at the memory latency the other walks cause: on a 3D grid
-// (128^3, 256 walks per row) 8 waves per CU finish the walks in 175 ms, 24 (all that
-// fit) in 205 ms, 4 in 283 ms.
+// (128^3, 256 walks per row) 8 waves per CU finish the walks in 165 ms, 12 in 179 ms
+// (an earlier build: 8 in 175 ms, 24 in 205 ms, 4 in 283 ms).
 constexpr int WALK_WAVES_PER_CU = 8;
 constexpr int NSEG = NSLAB + 1;
 

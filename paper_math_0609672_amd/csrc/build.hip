@@ -221,17 +221,17 @@ __global__ void k_flag_slab(int64_t n, int64_t long_rank, const int32_t* __restr
     if (v < n) flag[v] = (budget[v] > 0 && rank[v] >= long_rank) ? 1 : 0;
 }
 
-// order[pos] = row, chunks[pos] = its number of chunks
+// order[pos] = row, chunks[pos] = its number of chunks of cs walks
 __global__ void k_compact(int64_t count, const int32_t* __restrict__ rows_or_null,
                           const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
                           int64_t base, const int32_t* __restrict__ budget, int32_t* order,
-                          int32_t* chunks)
+                          int32_t* chunks, int32_t cs)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count || !flag[i]) return;
     const int32_t v = rows_or_null ? rows_or_null[i] : (int32_t)i;
     order[base + pos[i]] = v;
-    chunks[base + pos[i]] = (budget[v] + SRW_WAVE - 1) / SRW_WAVE;
+    chunks[base + pos[i]] = (budget[v] + cs - 1) / cs;
 }
 
 __global__ void k_read_last(const int64_t* scan, const int32_t* last_in, int64_t n, int64_t* out)
@@ -1190,8 +1190,9 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         int32_t max_budget = 0;
         std::memcpy(&max_budget, &pinned[3], sizeof(int32_t));
         k_compact<<<grid_for(long_rank, BLOCK), BLOCK, 0, s>>>(long_rank, F->by_rank, flag, pos, 0,
-                                                               budget, order, chunks);
-        k_compact<<<g, BLOCK, 0, s>>>(n, nullptr, flag2, pos2, nlong, budget, order, chunks);
+                                                               budget, order, chunks, SRW_WAVE);
+        k_compact<<<g, BLOCK, 0, s>>>(n, nullptr, flag2, pos2, nlong, budget, order, chunks,
+                                      (int32_t)CHUNK_WALKS);
         CHECK_HIP(exclusive_scan_i32_to_i64(chunks, chunk_off, norder, st, s));
         k_read_last<<<1, 1, 0, s>>>(chunk_off, chunks, norder, tot + 3);
         CHECK_HIP(hipMemcpyAsync(&pinned[4], tot + 3, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1202,7 +1203,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (!cdesc) FAIL(SRW_E_NOMEM);
         k_set_last<<<1, 1, 0, s>>>(chunk_off, norder, n_chunks);
         k_chunks<<<grid_for(norder, BLOCK), BLOCK, 0, s>>>(
-            norder, order, chunk_off, budget, rline, n_lines, F->rank, rec_off, seed,
+            norder, nlong, order, chunk_off, budget, rline, n_lines, F->rank, rec_off, seed,
             batch ? batch->node_mat : nullptr, batch ? batch->mat_off : nullptr,
             batch ? batch->mat_seed : nullptr, cdesc);
         k_seg_bounds<<<1, 1, 0, s>>>(n, nlong, nslab_rows, pos2, chunk_off, bounds);

@@ -7,6 +7,14 @@
 #include "../../include/srw.h"
 
 #define SRW_WAVE 64
+#ifndef SRW_CHUNK_WALKS
+#define SRW_CHUNK_WALKS 256
+#endif
+// Walks of one row a wave takes from the walk queue at a time (the last chunk of a row
+// may hold fewer): SRW_WAVE for the rows walked first (the lowest ranks, whose walks
+// are the longest, so that they spread over many waves), CHUNK_WALKS for the others
+// (fewer queue claims per wave).
+constexpr uint32_t CHUNK_WALKS = SRW_CHUNK_WALKS;
 
 // Status propagation for HIP runtime calls inside the C-ABI.
 #define SRW_HIP(call)                                 \

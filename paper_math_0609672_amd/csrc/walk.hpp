@@ -138,8 +138,9 @@ struct ChunkDesc {
 };
 static_assert(sizeof(ChunkDesc) == 32, "chunk descriptors are 32 bytes");
 
-// chunk descriptors of the rows in schedule order
-__global__ void k_chunks(int64_t norder, const int32_t* __restrict__ order,
+// chunk descriptors of the rows in schedule order: consecutive walks of a row, SRW_WAVE
+// per chunk for the first nlong rows, CHUNK_WALKS for the others
+__global__ void k_chunks(int64_t norder, int64_t nlong, const int32_t* __restrict__ order,
                          const int64_t* __restrict__ chunk_off, const int32_t* __restrict__ budget,
                          const int64_t* __restrict__ rline, int64_t n_lines,
                          const int32_t* __restrict__ rank, const int64_t* __restrict__ rec_off,
@@ -163,8 +164,9 @@ __global__ void k_chunks(int64_t norder, const int32_t* __restrict__ order,
     d.rank = (uint32_t)rank[v];
     d.rec = (uint64_t)rec_off[v];
     for (int64_t c = chunk_off[j]; c < chunk_off[j + 1]; ++c) {
-        const uint32_t w0 = (uint32_t)(c - chunk_off[j]) * SRW_WAVE;
-        const uint32_t cnt = min((uint32_t)SRW_WAVE, (uint32_t)b - w0);
+        const uint32_t cs = j < nlong ? (uint32_t)SRW_WAVE : CHUNK_WALKS;
+        const uint32_t w0 = (uint32_t)(c - chunk_off[j]) * cs;
+        const uint32_t cnt = min(cs, (uint32_t)b - w0);
         d.walks = w0 | (cnt << 16);
         cdesc[c] = d;
     }

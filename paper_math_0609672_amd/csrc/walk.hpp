@@ -395,10 +395,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         bool found = false;
         if (deg <= 6) {
             // entries 0..5 in words 4..15, scanned from the top with selects (the
-            // lowest hit is taken last): no branches
+            // lowest hit is taken last): no branches.  Unused entries are zero words,
+            // and no u is below a zero threshold.
 #pragma unroll
             for (int m = 5; m >= 0; --m) {
-                const bool hit = (uint32_t)m < deg && u < e[4 + 2 * m];
+                const bool hit = u < e[4 + 2 * m];
                 next_line = hit ? e[5 + 2 * m] : next_line;
                 found = found || hit;
             }
@@ -408,8 +409,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
             const uint32_t L = (deg + 7) / 8;
             uint32_t lh = 0;
 #pragma unroll
-            for (int i = 11; i >= 0; --i) {
-                const bool h = (uint32_t)(i + 1) <= L && u < e[4 + i];
+            for (int i = 11; i >= 0; --i) {  // summaries past the last line are zero
+                const bool h = u < e[4 + i];
                 lh = h ? (uint32_t)(i + 1) : lh;
             }
             for (uint32_t l = lh ? lh : (L > 12 ? 13u : 0u); l != 0 && l <= L && !found; ++l) {
@@ -417,12 +418,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
                 const uint4 x0 = lp[0], x1 = lp[1], x2 = lp[2], x3 = lp[3];
                 const uint32_t f[16] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w,
                                         x2.x, x2.y, x2.z, x2.w, x3.x, x3.y, x3.z, x3.w};
-                const uint32_t m0 = 8 * (l - 1);
                 uint32_t nl = 0;
                 bool hit_any = false;
 #pragma unroll
-                for (int i = 7; i >= 0; --i) {
-                    const bool hit = m0 + i < deg && u < f[2 * i];
+                for (int i = 7; i >= 0; --i) {  // entries past the last are zero words
+                    const bool hit = u < f[2 * i];
                     nl = hit ? f[2 * i + 1] : nl;
                     hit_any = hit_any || hit;
                 }

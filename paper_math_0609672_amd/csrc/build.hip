@@ -103,10 +103,16 @@ __global__ void k_check_values(int64_t n, const int64_t* __restrict__ rowptr,
     if (bad) atomicOr(err, ERR_NOT_R);
 }
 
+// Plain loads: a label read here may be older than one another thread has just set
+// (labels only decrease and label[x] <= x holds at every moment, so the walk up still
+// ends at a root).  A stale root can only hook a node that is no longer a root, which
+// at worst splits a tree along an edge the next pass hooks again; the loop ends after
+// a pass in which no thread hooked, and in that pass nothing changed, so every thread
+// read the settled labels.
 __device__ __forceinline__ int32_t cc_root(const int32_t* label, int32_t x)
 {
     for (;;) {
-        const int32_t y = __hip_atomic_load(&label[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t y = label[x];
         if (y == x) return x;
         x = y;
     }
@@ -126,12 +132,15 @@ __global__ void k_cc_hook(int64_t n, const int64_t* __restrict__ rowptr,
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     int any = 0;
+    int32_t ru = -1;
     for (int64_t p = rowptr[u]; p < rowptr[u + 1]; ++p) {
         const int32_t v = col[p];
         if (v <= u) continue;  // each undirected edge once
-        const int32_t ru = cc_root(label, (int32_t)u), rv = cc_root(label, v);
+        if (ru < 0) ru = cc_root(label, (int32_t)u);
+        const int32_t rv = cc_root(label, v);
         if (ru != rv) {
             atomicMin(&label[ru > rv ? ru : rv], ru < rv ? ru : rv);
+            ru = ru < rv ? ru : rv;  // u's tree now hangs below the smaller root
             any = 1;
         }
     }

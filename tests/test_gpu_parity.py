@@ -375,9 +375,7 @@ def test_adaptive_budgets_bit_exact(srw, name, delta, max_walks):
     F.free()
 
 
-def test_walks_bit_exact_with_hub_nodes(srw):
-    # nodes of degree > 96: the record's line summaries cover twelve lines and the
-    # step scans on from the thirteenth; degrees 7..96 use the summaries
+def hub_matrix():
     rng = np.random.default_rng(11)
     n = 900
     base = W.random_graph(n, 2500, seed=11, ground_frac=0.02)
@@ -395,7 +393,29 @@ def test_walks_bit_exact_with_hub_nodes(srw):
     g = rng.uniform(0.1, 10.0, e.shape[0])
     excess = np.zeros(n)
     excess[rng.choice(n, 20, replace=False)] = rng.uniform(0.1, 1.0, 20)
-    A = W.assemble(n, e[:, 0], e[:, 1], g, excess)
+    return W.assemble(n, e[:, 0], e[:, 1], g, excess)
+
+
+def test_walks_bit_exact_with_hub_nodes(srw):
+    # nodes of degree > 96: the record's line summaries cover twelve lines and the
+    # step scans on from the thirteenth; degrees 7..96 use the summaries
+    A = hub_matrix()
     deg = np.diff(A.rowptr) - 1
     assert deg.max() > 96
     compare_walks(srw, A, 48, 13)
+
+
+@pytest.mark.parametrize("drop", [0.0, 1e-3])
+def test_factor_bit_exact_with_wide_rows(srw, drop):
+    # rows with more than 64 entries and rows with more than 64 distinct walk ends
+    A = hub_matrix()
+    walks = 160
+    _, F = gpu_build(srw, A, walks, drop, 6, keep=2)
+    assert (np.diff(A.rowptr) > 64).any()
+    assert np_(F.tallies()["hlen"]).max() > 64
+    ref = O.build_factor(A, walks, drop, 6)
+    got = {k: np_(v) for k, v in F.export().items()}
+    assert np.array_equal(got["yptr"], ref.yptr)
+    assert np.array_equal(got["ycol"], ref.ycol)
+    assert np.array_equal(got["yval"], ref.yval)
+    assert np.array_equal(got["d"], ref.d)

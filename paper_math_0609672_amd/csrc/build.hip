@@ -437,6 +437,9 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
     const int64_t k = blockIdx.x;
     if (k >= n) return;
     const int m = budget[k];
+    const int64_t base = rec_off[k];
+    // both scalar loads leave before the branch on m (one round trip, not two)
+    asm volatile("" ::"s"(base));
     const int lane = threadIdx.x;
     if (m == 0) {  // exact row: no walks
         if (lane == 0) {
@@ -450,32 +453,55 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
     }
     int hbits = 0;
     while ((1 << hbits) < HS) ++hbits;
+    // the row's first 256 walks are loaded before the table is cleared, in one round
+    // trip rather than one per 64 walks
+    constexpr int U = 4;
+    uint32_t re[U], rv[U], rl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t q = base + min(u * 64 + lane, m - 1);  // in the row; unused past m
+        re[u] = rec_end[q];
+        rv[u] = rec_vis[q];
+        rl[u] = rec_len[q];
+    }
     for (int i = lane; i < HS; i += 64) {
         tk[i] = END_GROUND;
         tc[i] = 0;
     }
     __syncthreads();
-    const int64_t base = rec_off[k];
     uint64_t jv = 0, sl = 0, vq = 0;
     uint32_t g = 0;
-    for (int i = lane; i < m; i += 64) {
-        const uint32_t e = rec_end[base + i];
-        const uint64_t v = rec_vis[base + i];
-        jv += v;
-        vq += v * v;
-        sl += rec_len[base + i];
-        if (e == END_GROUND) {
-            ++g;
-            continue;
-        }
-        uint32_t h = (e * 0x9E3779B1u) >> (32 - hbits);
-        for (;;) {  // at most m of the 2P >= 2m slots are taken: an empty one is reached
-            const uint32_t prev = atomicCAS(&tk[h], END_GROUND, e);
-            if (prev == END_GROUND || prev == e) {
-                atomicAdd(&tc[h], 1u);
-                break;
+    for (int i0 = 0; i0 < m; i0 += U * 64) {
+        if (i0 > 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = base + min(i0 + u * 64 + lane, m - 1);
+                re[u] = rec_end[q];
+                rv[u] = rec_vis[q];
+                rl[u] = rec_len[q];
             }
-            h = (h + 1) & (uint32_t)(HS - 1);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * 64 + lane >= m) continue;
+            const uint32_t e = re[u];
+            const uint64_t v = rv[u];
+            jv += v;
+            vq += v * v;
+            sl += rl[u];
+            if (e == END_GROUND) {
+                ++g;
+                continue;
+            }
+            uint32_t h = (e * 0x9E3779B1u) >> (32 - hbits);
+            for (;;) {  // at most m of the 2P >= 2m slots are taken: an empty one is reached
+                const uint32_t prev = atomicCAS(&tk[h], END_GROUND, e);
+                if (prev == END_GROUND || prev == e) {
+                    atomicAdd(&tc[h], 1u);
+                    break;
+                }
+                h = (h + 1) & (uint32_t)(HS - 1);
+            }
         }
     }
     jv = wave_sum(jv);
@@ -492,6 +518,28 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
         const uint64_t mask = ballot(ok);
         if (ok) cp[D + __popcll(mask & lt)] = ((uint64_t)key << 32) | tc[i];
         D += __popcll(mask);
+    }
+    if (D <= 64) {
+        // at most one distinct end per lane: its place in ascending order is the number
+        // of smaller ends (the ends are distinct), counted over the lanes
+        __syncthreads();
+        const uint64_t x = lane < D ? cp[lane] : ~0ull;
+        const uint32_t key = (uint32_t)(x >> 32);
+        int below = 0;
+        for (int j = 0; j < D; ++j)  // j is wave-uniform: lane reads, no LDS
+            below += (uint32_t)__builtin_amdgcn_readlane((int)key, j) < key;
+        if (lane < D) {
+            h_end[base + below] = key;
+            h_cnt[base + below] = (uint32_t)x;
+        }
+        if (lane == 0) {
+            J[k] = jv;
+            G[k] = g;
+            steps[k] = sl;
+            vsq[k] = vq;
+            hlen[k] = D;
+        }
+        return;
     }
     int D2 = 1;
     while (D2 < D) D2 <<= 1;

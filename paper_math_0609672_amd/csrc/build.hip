@@ -429,7 +429,7 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
                                                    int32_t* __restrict__ hlen, uint32_t* h_end,
                                                    uint32_t* h_cnt)
 {
-    extern __shared__ uint64_t lds64[];
+    extern __shared__ __align__(16) uint64_t lds64[];
     const int HS = 2 * P;                      // table slots, a power of two
     uint64_t* cp = lds64;                      // [P] compacted (node << 32 | count)
     uint32_t* tk = (uint32_t*)(lds64 + P);     // [HS] keys, END_GROUND = empty
@@ -464,10 +464,13 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
         rv[u] = rec_vis[q];
         rl[u] = rec_len[q];
     }
-    for (int i = lane; i < HS; i += 64) {
-        tk[i] = END_GROUND;
-        tc[i] = 0;
+    __shared__ uint32_t used[64];  // the first 64 slots taken, in the order taken
+    __shared__ int nused;
+    for (int i = lane; i < HS / 4; i += 64) {  // HS >= 128: whole 16-byte groups
+        ((uint4*)tk)[i] = make_uint4(END_GROUND, END_GROUND, END_GROUND, END_GROUND);
+        ((uint4*)tc)[i] = make_uint4(0u, 0u, 0u, 0u);
     }
+    if (lane == 0) nused = 0;
     __syncthreads();
     uint64_t jv = 0, sl = 0, vq = 0;
     uint32_t g = 0;
@@ -496,6 +499,10 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
             uint32_t h = (e * 0x9E3779B1u) >> (32 - hbits);
             for (;;) {  // at most m of the 2P >= 2m slots are taken: an empty one is reached
                 const uint32_t prev = atomicCAS(&tk[h], END_GROUND, e);
+                if (prev == END_GROUND) {
+                    const int at = atomicAdd(&nused, 1);
+                    if (at < 64) used[at] = h;
+                }
                 if (prev == END_GROUND || prev == e) {
                     atomicAdd(&tc[h], 1u);
                     break;
@@ -509,6 +516,29 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
     sl = wave_sum(sl);
     g = wave_sum(g);
     __syncthreads();
+    const int DU = nused;  // distinct ends
+    if (DU <= 64) {
+        // at most one distinct end per lane: its place in ascending order is the number
+        // of smaller ends (the ends are distinct), counted over the lanes
+        const uint32_t h = lane < DU ? used[lane] : 0u;
+        const uint32_t key = lane < DU ? tk[h] : END_GROUND;
+        const uint32_t cnt = lane < DU ? tc[h] : 0u;
+        int below = 0;
+        for (int j = 0; j < DU; ++j)  // j is wave-uniform: lane reads, no LDS
+            below += (uint32_t)__builtin_amdgcn_readlane((int)key, j) < key;
+        if (lane < DU) {
+            h_end[base + below] = key;
+            h_cnt[base + below] = cnt;
+        }
+        if (lane == 0) {
+            J[k] = jv;
+            G[k] = g;
+            steps[k] = sl;
+            vsq[k] = vq;
+            hlen[k] = DU;
+        }
+        return;
+    }
     const uint64_t lt = lanemask_lt();
     int D = 0;
     for (int i0 = 0; i0 < HS; i0 += 64) {
@@ -518,28 +548,6 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
         const uint64_t mask = ballot(ok);
         if (ok) cp[D + __popcll(mask & lt)] = ((uint64_t)key << 32) | tc[i];
         D += __popcll(mask);
-    }
-    if (D <= 64) {
-        // at most one distinct end per lane: its place in ascending order is the number
-        // of smaller ends (the ends are distinct), counted over the lanes
-        __syncthreads();
-        const uint64_t x = lane < D ? cp[lane] : ~0ull;
-        const uint32_t key = (uint32_t)(x >> 32);
-        int below = 0;
-        for (int j = 0; j < D; ++j)  // j is wave-uniform: lane reads, no LDS
-            below += (uint32_t)__builtin_amdgcn_readlane((int)key, j) < key;
-        if (lane < D) {
-            h_end[base + below] = key;
-            h_cnt[base + below] = (uint32_t)x;
-        }
-        if (lane == 0) {
-            J[k] = jv;
-            G[k] = g;
-            steps[k] = sl;
-            vsq[k] = vq;
-            hlen[k] = D;
-        }
-        return;
     }
     int D2 = 1;
     while (D2 < D) D2 <<= 1;
@@ -813,15 +821,15 @@ __global__ void k_permute_rows(int64_t n, const int32_t* __restrict__ slot_node,
                                const T* __restrict__ sval, const int64_t* __restrict__ dptr,
                                int32_t* __restrict__ dcol, T* __restrict__ dval)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); s < n; s += nw) {
-        const int32_t k = slot_node[s];
-        const int64_t a = sptr[k], len = sptr[k + 1] - a, o = dptr[s];
-        for (int64_t j = lane; j < len; j += 64) {
-            dcol[o + j] = node_slot[scol[a + j]];
-            dval[o + j] = sval[a + j];
-        }
+    // sixteen lanes per slot (rows hold about twenty entries), one slot per group
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = t >> 4;
+    if (s >= n) return;
+    const int32_t k = slot_node[s];
+    const int64_t a = sptr[k], len = sptr[k + 1] - a, o = dptr[s];
+    for (int64_t j = t & 15; j < len; j += 16) {
+        dcol[o + j] = node_slot[scol[a + j]];
+        dval[o + j] = sval[a + j];
     }
 }
 
@@ -1554,7 +1562,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             hipError_t e = exclusive_scan_i32_to_i64(lens, dptr, n, st, s);
             if (e != hipSuccess) return e;
             k_set_last<<<1, 1, 0, s>>>(dptr, n, nnz_y);
-            const unsigned pg = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
+            const unsigned pg = (unsigned)grid_for(16 * n, BLOCK);
             if (fp32)
                 k_permute_rows<float><<<pg, BLOCK, 0, s>>>(n, F->slot_node, F->node_slot, sptr,
                                                            scol, (const float*)sval, dptr, dcol,

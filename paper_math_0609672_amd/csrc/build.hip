@@ -761,7 +761,7 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
 // Sixteen lanes per row (rows of Y hold about twenty entries), entries strided by 16.
 __global__ void k_entry_keys(int64_t n, const int64_t* __restrict__ yptr,
                              const int32_t* __restrict__ ycol, const int32_t* __restrict__ rank,
-                             int rank_bits, uint32_t* rowid, uint32_t* idx, uint64_t* key)
+                             int rank_bits, uint32_t* idx, uint64_t* key)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = t >> 4;
@@ -769,22 +769,24 @@ __global__ void k_entry_keys(int64_t n, const int64_t* __restrict__ yptr,
     const uint64_t rdesc = (uint64_t)(n - 1 - rank[k]);
     const int64_t e = yptr[k + 1];
     for (int64_t q = yptr[k] + (t & 15); q < e; q += 16) {
-        rowid[q] = (uint32_t)k;
         idx[q] = (uint32_t)q;
         key[q] = ((uint64_t)(uint32_t)ycol[q] << rank_bits) | rdesc;
     }
 }
 
+// The source row of a sorted entry comes back from its key's rank field through the
+// rank-ordered node list (a small, cached table) rather than a gather by entry.
 template <typename T>
-__global__ void k_transpose_fill(int64_t nnz, const uint32_t* __restrict__ sorted_idx,
-                                 const uint32_t* __restrict__ rowid, const T* __restrict__ yval,
+__global__ void k_transpose_fill(int64_t nnz, int64_t n, const uint64_t* __restrict__ sorted_key,
+                                 const uint32_t* __restrict__ sorted_idx, int rank_bits,
+                                 const int32_t* __restrict__ by_rank, const T* __restrict__ yval,
                                  int32_t* __restrict__ ytcol, T* __restrict__ ytval)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nnz) return;
-    const uint32_t q = sorted_idx[j];
-    ytcol[j] = (int32_t)rowid[q];
-    ytval[j] = yval[q];
+    const int64_t rdesc = (int64_t)(sorted_key[j] & ((1ull << rank_bits) - 1ull));
+    ytcol[j] = by_rank[n - 1 - rdesc];
+    ytval[j] = yval[sorted_idx[j]];
 }
 
 __global__ void k_set_last(int64_t* ptr, int64_t n, int64_t v) { ptr[n] = v; }
@@ -1517,17 +1519,16 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         void* ytval = ALLOC(tmp, char, nnz_y * vbytes);
         if (!ytptr || !ytcol || !ytval) FAIL(SRW_E_NOMEM);
         {
-            uint32_t* rowid = ALLOC(tmp, uint32_t, nnz_y);
             uint32_t* idx = ALLOC(tmp, uint32_t, nnz_y);
             uint32_t* idx2 = ALLOC(tmp, uint32_t, nnz_y);
             uint64_t* key = ALLOC(tmp, uint64_t, nnz_y);
             uint64_t* key2 = ALLOC(tmp, uint64_t, nnz_y);
             void* rt = ALLOC(tmp, char, radix_tmp_bytes(nnz_y));
-            if (!rowid || !idx || !idx2 || !key || !key2 || !rt) FAIL(SRW_E_NOMEM);
+            if (!idx || !idx2 || !key || !key2 || !rt) FAIL(SRW_E_NOMEM);
             int rbits = 1;
             while (rbits < 31 && ((int64_t)1 << rbits) < n) ++rbits;
             k_entry_keys<<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(n, F->yptr, F->ycol, F->rank,
-                                                                   rbits, rowid, idx, key);
+                                                                   rbits, idx, key);
             uint64_t* ko;
             uint32_t* vo;
             CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, 2 * rbits, rt, &ko, &vo, s));
@@ -1535,10 +1536,12 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, nnz_y, ytptr, rbits);
             if (fp32)
                 k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, vo, rowid, (const float*)F->yval, ytcol, (float*)ytval);
+                    nnz_y, n, ko, vo, rbits, F->by_rank, (const float*)F->yval, ytcol,
+                    (float*)ytval);
             else
                 k_transpose_fill<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, vo, rowid, (const double*)F->yval, ytcol, (double*)ytval);
+                    nnz_y, n, ko, vo, rbits, F->by_rank, (const double*)F->yval, ytcol,
+                    (double*)ytval);
             CHECK_HIP(hipGetLastError());
         }
 

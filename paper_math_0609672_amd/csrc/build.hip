@@ -596,7 +596,7 @@ __global__ void k_iota_u32(int64_t n, uint32_t* x)
 // beg[k] = first of the m sorted keys whose bits from `shift` up are >= k (k = 0..n;
 // beg[n] = m when every key is below n << shift), by binary search
 __global__ void k_row_begin(int64_t n, const uint64_t* __restrict__ key, int64_t m,
-                            int64_t* __restrict__ beg, int shift = 32)
+                            int64_t* __restrict__ beg, int shift = 32, uint64_t mask = ~0ull)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k > n) return;
@@ -604,7 +604,7 @@ __global__ void k_row_begin(int64_t n, const uint64_t* __restrict__ key, int64_t
     int64_t lo = 0, hi = m;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
-        if (key[mid] < want) lo = mid + 1;
+        if ((key[mid] & mask) < want) lo = mid + 1;
         else hi = mid;
     }
     beg[k] = lo;
@@ -755,37 +755,49 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
 }
 
 // ------------------------------------------------------------------- transpose
-// Sort key of entry (k, i) of Y for the rows of Y^T: column i first, then the rank
-// of k descending -- the order in which the backward substitution finishes the
-// w_k it needs, so a long Y^T row meets its last-ready values at its end.
+// Entries of Y for the rows of Y^T, listed row by row in descending rank of the source
+// row k, with key (position of k in that list) << 32 | column i.  A stable sort on the
+// column alone then orders each row of Y^T by the rank of k descending -- the order in
+// which the backward substitution finishes the w_k it needs, so a long Y^T row meets
+// its last-ready values at its end.
+// lens[r] = length of the row of rank n-1-r.
+__global__ void k_desc_lens(int64_t n, const int32_t* __restrict__ by_rank,
+                            const int64_t* __restrict__ yptr, int32_t* __restrict__ lens)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t k = by_rank[n - 1 - r];
+    lens[r] = (int32_t)(yptr[k + 1] - yptr[k]);
+}
+
 // Sixteen lanes per row (rows of Y hold about twenty entries), entries strided by 16.
-__global__ void k_entry_keys(int64_t n, const int64_t* __restrict__ yptr,
-                             const int32_t* __restrict__ ycol, const int32_t* __restrict__ rank,
-                             int rank_bits, uint32_t* idx, uint64_t* key)
+__global__ void k_entry_keys(int64_t n, const int32_t* __restrict__ by_rank,
+                             const int64_t* __restrict__ yptr, const int32_t* __restrict__ ycol,
+                             const int64_t* __restrict__ doff, uint32_t* idx, uint64_t* key)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t k = t >> 4;
-    if (k >= n) return;
-    const uint64_t rdesc = (uint64_t)(n - 1 - rank[k]);
-    const int64_t e = yptr[k + 1];
-    for (int64_t q = yptr[k] + (t & 15); q < e; q += 16) {
-        idx[q] = (uint32_t)q;
-        key[q] = ((uint64_t)(uint32_t)ycol[q] << rank_bits) | rdesc;
+    const int64_t r = t >> 4;
+    if (r >= n) return;
+    const int32_t k = by_rank[n - 1 - r];
+    const int64_t b = yptr[k], e = yptr[k + 1], o = doff[r] - b;
+    for (int64_t q = b + (t & 15); q < e; q += 16) {
+        idx[o + q] = (uint32_t)q;
+        key[o + q] = ((uint64_t)r << 32) | (uint32_t)ycol[q];
     }
 }
 
-// The source row of a sorted entry comes back from its key's rank field through the
-// rank-ordered node list (a small, cached table) rather than a gather by entry.
+// The source row of a sorted entry comes back from its key's position field through
+// the rank-ordered node list (a small, cached table) rather than a gather by entry.
 template <typename T>
 __global__ void k_transpose_fill(int64_t nnz, int64_t n, const uint64_t* __restrict__ sorted_key,
-                                 const uint32_t* __restrict__ sorted_idx, int rank_bits,
+                                 const uint32_t* __restrict__ sorted_idx,
                                  const int32_t* __restrict__ by_rank, const T* __restrict__ yval,
                                  int32_t* __restrict__ ytcol, T* __restrict__ ytval)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nnz) return;
-    const int64_t rdesc = (int64_t)(sorted_key[j] & ((1ull << rank_bits) - 1ull));
-    ytcol[j] = by_rank[n - 1 - rdesc];
+    const int64_t r = (int64_t)(sorted_key[j] >> 32);
+    ytcol[j] = by_rank[n - 1 - r];
     ytval[j] = yval[sorted_idx[j]];
 }
 
@@ -1527,20 +1539,27 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             if (!idx || !idx2 || !key || !key2 || !rt) FAIL(SRW_E_NOMEM);
             int rbits = 1;
             while (rbits < 31 && ((int64_t)1 << rbits) < n) ++rbits;
-            k_entry_keys<<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(n, F->yptr, F->ycol, F->rank,
-                                                                   rbits, idx, key);
+            int32_t* dlen = ALLOC(tmp, int32_t, n);
+            int64_t* doff = ALLOC(tmp, int64_t, n + 1);
+            if (!dlen || !doff) FAIL(SRW_E_NOMEM);
+            k_desc_lens<<<g, BLOCK, 0, s>>>(n, F->by_rank, F->yptr, dlen);
+            CHECK_HIP(exclusive_scan_i32_to_i64(dlen, doff, n, st, s));
+            k_entry_keys<<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(n, F->by_rank, F->yptr, F->ycol,
+                                                                   doff, idx, key);
             uint64_t* ko;
             uint32_t* vo;
-            CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, 2 * rbits, rt, &ko, &vo, s));
+            // stable on the column bits only: the listing order supplies the rank order
+            CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, rbits, rt, &ko, &vo, s));
             // rows of Y^T: where each column's run of sorted keys begins
-            k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, nnz_y, ytptr, rbits);
+            k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, nnz_y, ytptr, 0,
+                                                                 (1ull << 32) - 1ull);
             if (fp32)
                 k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, n, ko, vo, rbits, F->by_rank, (const float*)F->yval, ytcol,
+                    nnz_y, n, ko, vo, F->by_rank, (const float*)F->yval, ytcol,
                     (float*)ytval);
             else
                 k_transpose_fill<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, n, ko, vo, rbits, F->by_rank, (const double*)F->yval, ytcol,
+                    nnz_y, n, ko, vo, F->by_rank, (const double*)F->yval, ytcol,
                     (double*)ytval);
             CHECK_HIP(hipGetLastError());
         }

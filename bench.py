@@ -14,8 +14,8 @@ per row, drop tolerance 1e-4, FP64 factor, one right-hand side N(0, 1), PCG to
 Prints one JSON line (rank 0).  `roofline` is for the walk kernel, the dominant
 kernel: algorithmic bytes = 12 B per step + 8 B per entry of the row the step
 leaves (counted exactly by the kernel) over the kernel's HIP-event duration on the
-build stream.  `cpu_baseline` times the CPU oracle on a random sample of rows of
-the same matrix and scales to all rows.
+build stream.  `cpu_baseline` times the CPU oracle on the whole workload (build and
+solve), its rows' walks and tallies split over the host threads.
 """
 import argparse
 import json
@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--solve-order", type=int, default=2,
                     help="0 rank order, 1 level order, 2 the library's automatic choice")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU baseline (the oracle on the whole workload)")
     ap.add_argument("--adaptive", type=float, default=0.0, metavar="DELTA",
                     help="walks per row by the Section 5.1 stopping rule with relative margin "
                          "DELTA at 99%% confidence (at least 20 walks), decided inside each "
@@ -83,46 +83,57 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(A, walks, seed, target_s, two_games=False):
-    """Oracle build on a random sample of rows, scaled to all rows (for an asymmetric A,
-    the same for the game of A^T, half the time each)."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def host_threads() -> int:
+    """Oracle threads: the host's CPU share for one GPU (16) at most."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(A, walks, drop, seed, tol, b, two_games=False, reuse=False):
+    """The whole workload on the CPU oracle, as it stands: ordering and table on one
+    thread, every row's walks and tallies split over the host threads, the factor and
+    the solve (PCG, or BiCGSTAB for two games) on one thread.  Timed end to end."""
     import oracle as O
 
-    games = [A, O.transpose(A)] if two_games else [A]
+    threads = host_threads()
     t0 = time.perf_counter()
-    rk = O.rank(A.n, seed)
-    tbs = [O.table(G, rk) for G in games]
-    t_setup = time.perf_counter() - t0
-    est_walk, t_walk, steps, parts = 0.0, 0.0, 0, []
-    for G, tb in zip(games, tbs):
-        walking = np.flatnonzero(tb.tau > 0)
-        rng = np.random.default_rng(12345)
-        order = rng.permutation(walking)
-        done_rows, tg = 0, 0.0
-        chunk = 256
-        while tg < target_s / len(games) and done_rows < order.size:
-            rows = order[done_rows:done_rows + chunk]
-            t1 = time.perf_counter()
-            wk = O.walk_rows(G, rk, tb, seed, rows, walks)
-            tg += time.perf_counter() - t1
-            steps += int(wk.length.sum())
-            done_rows += rows.size
-        est_walk += tg * walking.size / max(done_rows, 1)
-        t_walk += tg
-        parts.append(f"{done_rows} of {walking.size} walking rows")
+    if two_games:
+        F = O.build_factor_ldu(A, walks, drop, seed, reuse=reuse, threads=threads)
+        steps = int(F.a.walks.length.sum()) + int(F.t.walks.length.sum())
+    else:
+        F = O.build_factor(A, walks, drop, seed, reuse=reuse, threads=threads)
+        steps = int(F.tallies.steps.sum())
+    t1 = time.perf_counter()
+    if two_games:
+        st, x, it, rel = O.bicgstab(A, F, b, tol)
+    else:
+        st, x, it, rel = O.pcg(A, F, b, tol)
+    t2 = time.perf_counter()
     return {
-        "value": round(t_setup + est_walk, 3),
-        "unit": "s (oracle build, walks scaled from the sample; "
-                + ("BiCGSTAB" if two_games else "PCG") + " not included)",
-        "cores": 1,
+        "value": round(t2 - t0, 3),
+        "unit": "s (oracle build + " + ("BiCGSTAB" if two_games else "PCG") + " to the same tolerance)",
+        "cores": threads,
         "kind": "oracle",
-        "sample": " and ".join(parts) + (" (games of A and A^T)" if two_games else "")
-                  + f" drawn uniformly, {walks} walks each; ordering and table on all rows "
-                  f"({t_setup:.2f} s)",
-        "walk_steps_per_s": round(steps / max(t_walk, 1e-9), 1),
-        "sample_walk_s": round(t_walk, 3),
+        "sample": f"the whole workload: all {A.n} rows, {walks} walks each "
+                  + ("(games of A and A^T) " if two_games else "")
+                  + f"on {threads} host threads (walks and tallies), factor and solve on one",
+        "cpu_model": cpu_model(),
+        "build_s": round(t1 - t0, 3),
+        "solve_s": round(t2 - t1, 3),
+        "iters": it,
+        "rel_residual": rel,
+        "converged": st == 0,
+        "walk_steps_per_s": round(steps / max(t1 - t0, 1e-9), 1),
     }
 
 
@@ -339,9 +350,11 @@ def main():
     default_walks = not (args.reuse or args.walks or args.adaptive > 0 or asym)
     out["roofline"]["traffic"] = (measured_traffic(args.workload, args.precision, s0["walk_waves"])
                                   if default_walks else None)
-    if args.cpu_seconds > 0:
-        log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(A, walks, args.seed, args.cpu_seconds, two_games=asym)
+    if not args.no_cpu and args.adaptive <= 0:
+        log(f"cpu baseline (oracle, whole workload, {host_threads()} threads)")
+        out["cpu_baseline"] = cpu_baseline(A, walks, drop, args.seed, tol, b_host, two_games=asym,
+                                           reuse=args.reuse)
+        log(f"cpu baseline: {out['cpu_baseline']['value']} s")
     print(json.dumps(out), flush=True)
 
 

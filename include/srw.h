@@ -41,6 +41,8 @@ extern "C" {
 
 #define SRW_ORDER_RANDOM 0    /* seeded random ordering (Section 5.4)               */
 #define SRW_ORDER_GIVEN 1     /* caller-supplied ranks                              */
+#define SRW_ORDER_NATURAL 2   /* rank = node id: the natural ordering 1..N the
+                                 paper's derivations assume (Sections 2-3)          */
 
 #define SRW_FP64 0            /* factor values and triangular solves in FP64        */
 #define SRW_FP32 1            /* factor stored and solved in FP32 under FP64 PCG    */
@@ -64,11 +66,13 @@ typedef struct {
 
 /* Build options; srw_default_options() fills the defaults shown. */
 typedef struct {
-    int32_t ordering;          /* SRW_ORDER_RANDOM                                  */
+    int32_t ordering;          /* SRW_ORDER_RANDOM (or _GIVEN, _NATURAL)            */
     const int32_t* rank;       /* device int32[n], a permutation of 0..n-1, read
                                   when ordering == SRW_ORDER_GIVEN; rank 0 first     */
     const int32_t* walks;      /* device int32[n] per-row walk budgets, or NULL for
-                                  the uniform walks_per_row; values < 1 count as 1  */
+                                  the uniform walks_per_row; values < 1 count as 1;
+                                  a budget above 8192 on a row that walks fails the
+                                  build with SRW_E_ARG before any walk runs          */
     int32_t factor_precision;  /* SRW_FP64                                          */
     uint64_t max_steps;        /* per-walk step cap, 0 = 2^22; exceeding it fails
                                   the build with SRW_E_WALK_LIMIT                    */
@@ -140,6 +144,22 @@ int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, u
                      const srw_options* opt, srw_factor** out, void* stream);
 
 void srw_factor_free(srw_factor* F);
+
+/* The comparison preconditioner of the paper's ICCG columns (Section 6, Tables 1-2):
+ * zero fill-in incomplete Cholesky of the R-matrix A in the same form as the
+ * random-walk factor, A ~ Y^T D Y with Y unit lower triangular in rank order.  Nodes
+ * are eliminated in decreasing rank and every update outside A's pattern is dropped,
+ * so row k of Y holds exactly the lower-ranked neighbours of k:
+ *   D_k = A_kk - sum_{j in Up(k)} D_j Y_jk^2,
+ *   Y_ki = (A_ki - sum_{j in Up(k), j ~ i} D_j Y_jk Y_ji) / D_k,
+ * Up(k) the higher-ranked neighbours of k (sums in row k's CSR order).  The ordering
+ * comes from opt as for srw_build_factor (SRW_ORDER_NATURAL for the conventional
+ * ICCG; the default is the random ordering of `seed`); walks, reuse and FP32 are
+ * refused (SRW_E_ARG).  A is validated as by srw_build_factor.  The result is an
+ * srw_factor: srw_pcg_solve, srw_apply, srw_factor_export and srw_factor_free take
+ * it as they take a random-walk factor (its walk counters are zero). */
+int srw_build_ic0(const srw_csr* A, uint64_t seed, const srw_options* opt, srw_factor** out,
+                  void* stream);
 
 /* Sizes and counters of a factor (host outputs; any pointer may be NULL):
  * n, nnz_y (strictly triangular entries kept), walks (simulated walks), walk_steps

@@ -70,6 +70,7 @@ def lib():
         L.srwo_factor.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, dbl, P, P, P, P]
         L.srwo_apply.argtypes = [i64, P, P, P, P, P, P, P, P]
         L.srwo_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, dbl, i32, P, P, P]
+        L.srwo_ic0.argtypes = [i64, P, P, P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -141,7 +142,49 @@ class Walks:
     length: np.ndarray    # uint32     steps
 
 
-def walk_rows(A, rk, tb: Table, seed: int, rows, budget) -> Walks:
+def _at(a: np.ndarray, i: int):
+    """Pointer to element i of a contiguous array."""
+    return ctypes.c_void_p(a.ctypes.data + i * a.itemsize)
+
+
+def _over_rows(nrows: int, threads: int, fn, chunk: int = 1024) -> None:
+    """Calls fn(a, b) for consecutive slices [a, b) of a row list.  With threads > 1 the
+    slices are taken in order by that many host threads; ctypes releases the GIL for
+    the duration of each C call, and every slice writes disjoint outputs, so the result
+    is the one a single call over all rows gives."""
+    if threads <= 1 or nrows <= chunk:
+        fn(0, nrows)
+        return
+    import threading
+
+    starts = iter(range(0, nrows, chunk))
+    lock = threading.Lock()
+    errors = []
+
+    def work():
+        while True:
+            with lock:
+                a = next(starts, None)
+            if a is None or errors:
+                return
+            try:
+                fn(a, min(a + chunk, nrows))
+            except BaseException as e:  # noqa: BLE001 - re-raised in the caller
+                errors.append(e)
+                return
+
+    pool = [threading.Thread(target=work) for _ in range(threads)]
+    for t in pool:
+        t.start()
+    for t in pool:
+        t.join()
+    if errors:
+        raise errors[0]
+
+
+def walk_rows(A, rk, tb: Table, seed: int, rows, budget, threads: int = 1) -> Walks:
+    """The walks of the listed rows (records in list order).  threads > 1 splits the
+    list over host threads (same records)."""
     rows = _c(rows, np.int64)
     budget = np.broadcast_to(np.asarray(budget, np.int32), rows.shape).copy()
     budget[tb.tau[rows] <= 0.0] = 0
@@ -151,11 +194,17 @@ def walk_rows(A, rk, tb: Table, seed: int, rows, budget) -> Walks:
     end = np.zeros(tot, np.int32)
     vis = np.zeros(tot, np.uint32)
     ln = np.zeros(tot, np.uint32)
-    st = lib().srwo_walk_rows(A.n, _p(_c(A.rowptr, np.int64)), _p(tb.nbr), _p(tb.thr),
-                              _p(tb.mthr), _p(tb.tau), _p(tb.grounded), _p(_c(rk, np.int32)),
-                              seed, rows.size, _p(rows), _p(budget), _p(rec_off), _p(end),
-                              _p(vis), _p(ln))
-    assert st == OK
+    rowptr = _c(A.rowptr, np.int64)
+    rkc = _c(rk, np.int32)
+
+    def run(a, b):
+        st = lib().srwo_walk_rows(A.n, _p(rowptr), _p(tb.nbr), _p(tb.thr), _p(tb.mthr),
+                                  _p(tb.tau), _p(tb.grounded), _p(rkc), seed, b - a,
+                                  _at(rows, a), _at(budget, a), _at(rec_off, a), _p(end),
+                                  _p(vis), _p(ln))
+        assert st == OK
+
+    _over_rows(rows.size, threads, run)
     n = int(rec_off[-1])
     return Walks(rows, budget, rec_off, end[:n], vis[:n], ln[:n])
 
@@ -230,7 +279,8 @@ class Tallies:
     h_cnt: np.ndarray     # uint32    H'_{k,i}
 
 
-def tally(wk: Walks) -> Tallies:
+def tally(wk: Walks, threads: int = 1) -> Tallies:
+    """Per-row tallies of the walks (threads > 1 splits the rows over host threads)."""
     r = wk.rows.size
     count = wk.budget.astype(np.int32)
     rr = max(r, 1)
@@ -241,9 +291,16 @@ def tally(wk: Walks) -> Tallies:
     end = wk.end if wk.end.size else np.zeros(1, np.int32)
     vis = wk.visits if wk.visits.size else np.zeros(1, np.uint32)
     ln = wk.length if wk.length.size else np.zeros(1, np.uint32)
-    lib().srwo_tally_rows(r, _p(count), _p(wk.rec_off), _p(end), _p(vis), _p(ln), _p(t.walks),
-                          _p(t.J), _p(t.G), _p(t.steps), _p(t.visits_sq), _p(t.hlen),
-                          _p(t.h_end), _p(t.h_cnt))
+    rec_off = _c(wk.rec_off, np.int64)
+
+    def run(a, b):
+        st = lib().srwo_tally_rows(b - a, _at(count, a), _at(rec_off, a), _p(end), _p(vis),
+                                   _p(ln), _at(t.walks, a), _at(t.J, a), _at(t.G, a),
+                                   _at(t.steps, a), _at(t.visits_sq, a), _at(t.hlen, a),
+                                   _p(t.h_end), _p(t.h_cnt))
+        assert st == OK
+
+    _over_rows(r, threads, run)
     return Tallies(t.walks[:r], t.J[:r], t.G[:r], t.steps[:r], t.visits_sq[:r], t.hlen[:r],
                    t.h_off[:r], t.h_end, t.h_cnt)
 
@@ -300,22 +357,48 @@ def assemble(A, rk, tb: Table, tl: Tallies, rows: np.ndarray, drop_tol: float) -
 
 
 def build_factor(A, walks_per_row, drop_tol: float, seed: int, rk=None,
-                 reuse: bool = False) -> Factor:
+                 reuse: bool = False, threads: int = 1) -> Factor:
     """The whole preconditioning phase of Algorithm 1 on the CPU.  `walks_per_row` is
     an int (uniform) or an int array over nodes (per-row budgets, each >= 1).  With
     reuse, every walk also contributes the walks Algorithm "reuse" extracts from it
-    (Section 5.3) to the tallies of their start nodes."""
+    (Section 5.3) to the tallies of their start nodes.  threads > 1 runs the rows'
+    walks and tallies on that many host threads (rows are independent); the factor is
+    the same."""
     rk = rank(A.n, seed) if rk is None else np.asarray(rk, np.int32)
     tb = table(A, rk)
     rows = np.arange(A.n, dtype=np.int64)
     if reuse:
         wk = records_to_walks(A.n, walk_rows_reuse(A, rk, tb, seed, rows, walks_per_row))
     else:
-        wk = walk_rows(A, rk, tb, seed, rows, walks_per_row)
-    tl = tally(wk)
+        wk = walk_rows(A, rk, tb, seed, rows, walks_per_row, threads=threads)
+    tl = tally(wk, threads=threads)
     F = assemble(A, rk, tb, tl, rows, drop_tol)
     F.walks, F.tallies = wk, tl
     return F
+
+
+def ic0(A, rk=None) -> Factor:
+    """Zero fill-in incomplete Cholesky (the ICCG preconditioner of the paper's
+    comparisons, Section 6, Tables 1-2) in the factor's form A ~ Y^T D Y, eliminating
+    in decreasing rank (natural ordering when rk is None: rank = node id).  The
+    result plugs into apply / pcg like a random-walk factor."""
+    n = A.n
+    rk = np.arange(n, dtype=np.int32) if rk is None else _c(rk, np.int32)
+    by_rank = np.empty(max(n, 1), np.int32)
+    by_rank[rk] = np.arange(n, dtype=np.int32)
+    yptr = np.zeros(n + 1, np.int64)
+    args = [n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)), _p(_c(A.val, np.float64)),
+            _p(rk), _p(by_rank)]
+    st = lib().srwo_ic0(*args, _p(yptr), None, None, None)
+    assert st == OK
+    nnz = int(yptr[-1])
+    ycol = np.zeros(max(nnz, 1), np.int32)
+    yval = np.zeros(max(nnz, 1))
+    d = np.zeros(max(n, 1))
+    st = lib().srwo_ic0(*args, _p(yptr), _p(ycol), _p(yval), _p(d))
+    if st != OK:
+        raise ValueError("IC(0) breakdown: a pivot is not positive")
+    return Factor(n, rk, yptr, ycol[:nnz], yval[:nnz], d[:n])
 
 
 def apply(F: Factor, r: np.ndarray) -> np.ndarray:
@@ -433,12 +516,13 @@ class LduFactor:
 
 
 def build_factor_ldu(A, walks_per_row, drop_tol: float, seed: int, rk=None,
-                     reuse: bool = False) -> LduFactor:
+                     reuse: bool = False, threads: int = 1) -> LduFactor:
     """Both games of Section 7.1 with the ordering of `seed` (or `rk`) and the same walk
     draws (so for a symmetric A the two factors coincide)."""
     rk = rank(A.n, seed) if rk is None else np.asarray(rk, np.int32)
-    Fa = build_factor(A, walks_per_row, drop_tol, seed, rk=rk, reuse=reuse)
-    Ft = build_factor(transpose(A), walks_per_row, drop_tol, seed, rk=rk, reuse=reuse)
+    Fa = build_factor(A, walks_per_row, drop_tol, seed, rk=rk, reuse=reuse, threads=threads)
+    Ft = build_factor(transpose(A), walks_per_row, drop_tol, seed, rk=rk, reuse=reuse,
+                      threads=threads)
     return LduFactor(Fa, Ft)
 
 

@@ -1016,3 +1016,76 @@ int srwo_bicgstab(int64_t n, const int64_t* rowptr, const int32_t* col, const do
     free(r);
     return status;
 }
+
+/* ------------------------------------------------------------------------- */
+/* IC(0): the incomplete Cholesky comparison preconditioner of Section 6     */
+/* (the ICCG columns of Tables 1-2), in the factor's form A ~ Y^T D Y.       */
+/* ------------------------------------------------------------------------- */
+
+/* Y_{j,c} of a factor row stored in ascending column id, or 0 if absent. */
+static double row_entry(const int64_t* yptr, const int32_t* ycol, const double* yval,
+                        int64_t j, int32_t c)
+{
+    for (int64_t q = yptr[j]; q < yptr[j + 1]; q++)
+        if (ycol[q] == c) return yval[q];
+    return 0.0;
+}
+
+/* Zero fill-in incomplete Cholesky of an R-matrix in the factor's form: nodes are
+ * eliminated one at a time in decreasing rank, and the update of every remaining
+ * entry outside the pattern of A is discarded.  Row k of Y keeps exactly the
+ * lower-ranked neighbours of k:
+ *     D_k  = A_kk - sum_{j in Up(k)} (D_j Y_jk) Y_jk
+ *     Y_ki = (A_ki - sum_{j in Up(k), j adjacent to i} (D_j Y_jk) Y_ji) / D_k
+ * with Up(k) the higher-ranked neighbours of k, taken in the CSR order of row k.
+ * First call with ycol == NULL fills yptr (entries in ascending column id); the
+ * second fills ycol, yval and d.  by_rank[p] is the node of rank p.  Returns
+ * SRWO_E_NOT_RMATRIX if a pivot is not positive. */
+int srwo_ic0(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+             const int32_t* rank, const int32_t* by_rank, int64_t* yptr, int32_t* ycol,
+             double* yval, double* d)
+{
+    if (!ycol) {
+        yptr[0] = 0;
+        for (int64_t k = 0; k < n; k++) {
+            int64_t m = 0;
+            for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++)
+                if (col[p] != k && rank[col[p]] < rank[k]) m++;
+            yptr[k + 1] = yptr[k] + m;
+        }
+        return SRWO_OK;
+    }
+    for (int64_t pos = n - 1; pos >= 0; pos--) {
+        int64_t k = by_rank[pos];
+        double a = 0.0;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++)
+            if (col[p] == k) a = val[p];
+        double dk = a;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++) {
+            int32_t j = col[p];
+            if (j == k || rank[j] < rank[k]) continue;
+            double yjk = row_entry(yptr, ycol, yval, j, (int32_t)k);
+            dk = dk - (d[j] * yjk) * yjk;
+        }
+        if (!(dk > 0.0)) return SRWO_E_NOT_RMATRIX;
+        d[k] = dk;
+        int64_t q = yptr[k];
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++) {
+            int32_t i = col[p];
+            if (i == k || rank[i] > rank[k]) continue;
+            double s = val[p];
+            for (int64_t p2 = rowptr[k]; p2 < rowptr[k + 1]; p2++) {
+                int32_t j = col[p2];
+                if (j == k || rank[j] < rank[k]) continue;
+                double yji = row_entry(yptr, ycol, yval, j, i);
+                if (yji == 0.0) continue;
+                double yjk = row_entry(yptr, ycol, yval, j, (int32_t)k);
+                s = s - (d[j] * yjk) * yji;
+            }
+            ycol[q] = i;
+            yval[q] = s / dk;
+            q++;
+        }
+    }
+    return SRWO_OK;
+}

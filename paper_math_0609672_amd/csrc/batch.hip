@@ -12,6 +12,8 @@
 // in order.  A system's scalars (rho, alpha, ...) live on the device; a system stops
 // moving once its recurrence residual meets the tolerance.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cmath>
 #include <cstring>
@@ -259,8 +261,17 @@ __global__ void k_zero_n(int* a, int n)
 // row's values are published by lane 0 with one device-scope store each, every value
 // its own ready flag (signalling-NaN sentinel).  A waiting wave polls one address --
 // the last value of its dependency that the order solves last -- then reloads its
-// missing values.  Wave i takes slots i, i + W, ...; the grid is sized so that every
-// wave is resident (occupancy x CUs).
+// missing values.
+//
+// Work is claimed, not assigned: a wave takes the next `chunk` consecutive slots of the
+// order from one counter (one atomic per claim) and solves them in order.  Claims are
+// handed out in slot order, so every slot below the lowest unclaimed one belongs to a
+// wave that is running.  The lowest unfinished slot therefore always has a running
+// owner that has finished the earlier slots of its claim, and its dependencies (all
+// lower slots) are finished: the solve progresses whether or not every wave of the
+// grid is resident at once.  (A fixed cycle -- wave i takes slots i, i + W, ... --
+// does not: a slot whose wave has not been dispatched yet can hold up the waves that
+// occupy the chip.)
 template <typename T>
 struct MBits;
 template <>
@@ -275,8 +286,6 @@ struct MBits<float> {
     static constexpr U sentinel = 0x7FA5A5A5u;
     static __device__ U nan_bits() { return 0x7FC00000u; }
 };
-
-constexpr uint32_t SPIN_LIMIT = 1u << 20;
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_mfill(int64_t n, T* x)
@@ -299,8 +308,18 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
+// Solve-claim counters, zeroed before every launch (a kernel, not a memset: the solves
+// are captured in a graph).
+__global__ void k_zero_u64(unsigned long long* a, int n)
+{
+    if ((int)threadIdx.x < n) a[threadIdx.x] = 0ull;
+}
+
+// wait_ticks: wall-clock ticks (constant-rate counter) after which a wait gives up --
+// a guard against a defect, far above any legitimate wait (a claimed slot waits at
+// most for the slots claimed before it).
 template <typename T, bool FWD>
-__global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs,
+__global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs, int32_t chunk,
                                                       const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ col,
                                                       const T* __restrict__ val,
@@ -308,93 +327,103 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs,
                                                       const int32_t* __restrict__ slot_node,
                                                       const double* __restrict__ rhs,
                                                       const T* __restrict__ w, T* sol,
-                                                      double* __restrict__ out, int* err)
+                                                      double* __restrict__ out, int* err,
+                                                      unsigned long long* claim, int64_t wait_ticks)
 {
     using U = typename MBits<T>::U;
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
-    const int64_t wid =
-        (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t i = wid; i < n; i += nw) {
-        const int64_t s = FWD ? i : n - 1 - i;
-        const int64_t q0 = ptr[s], q1 = ptr[s + 1];
-        T acc[MAXR];
+    for (;;) {
+        // every lane executes the atomic (lane 0 adds the chunk) and the claim is read
+        // from lane 0 as a scalar, so the loop exit below is a uniform branch
+        const uint64_t base =
+            lane0_u64(atomicAdd(claim, lane == 0 ? (unsigned long long)chunk : 0ull));
+        if (base >= (uint64_t)n) break;
+        const int64_t stop = std::min<int64_t>((int64_t)base + chunk, n);
+        for (int64_t i = (int64_t)base; i < stop; ++i) {
+            const int64_t s = FWD ? i : n - 1 - i;
+            const int64_t q0 = ptr[s], q1 = ptr[s + 1];
+            T acc[MAXR];
 #pragma unroll
-        for (int j = 0; j < MAXR; ++j) acc[j] = T(0);
-        for (int64_t qb = q0; qb < q1; qb += 64) {
-            const int64_t q = qb + lane;
-            const bool ok = q < q1;
-            const int32_t c = ok ? col[q] : 0;
-            const T a = ok ? val[q] : T(0);
-            const U* src = (const U*)sol + (int64_t)c * nrhs;
-            U bits[MAXR];
-            bool miss_mine = false;
-#pragma unroll
-            for (int j = 0; j < MAXR; ++j) {
-                bits[j] = (ok && j < nrhs) ? mload(src + j) : U(0);
-                miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
-            }
-            uint64_t miss = ballot(miss_mine);
-            uint32_t spins = 0;
-            while (miss != 0) {
-                // give up at the limit, or at once when another wave already gave up
-                // (a failed solve then drains instead of waiting at every row)
-                const bool failed = (spins & 255u) == 255u &&
-                                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-                if (++spins > SPIN_LIMIT || failed) {
-                    // the slot this wave waited for (every lane takes part in the max)
-                    const bool mine_d = (miss >> lane) & 1ull;
-                    const int key_d = wave_max_i(mine_d ? (FWD ? c : -c) : INT_MIN);
-                    const int32_t lead_d = FWD ? key_d : -key_d;
-                    if (lane == 0) {
-                        atomicOr(err, 1);
-                        // the first wave to reach the limit records where it waited:
-                        // err[2..6] = direction, slot, awaited slot, awaited value still
-                        // absent, waves in the grid
-                        if (!failed && atomicCAS(err + 1, 0, 1) == 0) {
-                            err[2] = FWD ? 1 : 0;
-                            err[3] = (int)s;
-                            err[4] = lead_d;
-                            err[5] = mload((const U*)sol + (int64_t)lead_d * nrhs + (nrhs - 1)) ==
-                                     MBits<T>::sentinel;
-                            err[6] = (int)nw;
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < MAXR; ++j)
-                        if (bits[j] == MBits<T>::sentinel) bits[j] = MBits<T>::nan_bits();
-                    break;
-                }
-                const bool mine = (miss >> lane) & 1ull;
-                const int key = wave_max_i(mine ? (FWD ? c : -c) : INT_MIN);
-                const int32_t lead = FWD ? key : -key;
-                const U lb = mload((const U*)sol + (int64_t)lead * nrhs + (nrhs - 1));
-                if (lb == MBits<T>::sentinel) {
-                    __builtin_amdgcn_s_sleep(2);
-                    continue;
-                }
-                miss_mine = false;
+            for (int j = 0; j < MAXR; ++j) acc[j] = T(0);
+            for (int64_t qb = q0; qb < q1; qb += 64) {
+                const int64_t q = qb + lane;
+                const bool ok = q < q1;
+                const int32_t c = ok ? col[q] : 0;
+                const T a = ok ? val[q] : T(0);
+                const U* src = (const U*)sol + (int64_t)c * nrhs;
+                U bits[MAXR];
+                bool miss_mine = false;
 #pragma unroll
                 for (int j = 0; j < MAXR; ++j) {
-                    if (mine && j < nrhs && bits[j] == MBits<T>::sentinel) bits[j] = mload(src + j);
+                    bits[j] = (ok && j < nrhs) ? mload(src + j) : U(0);
                     miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
                 }
-                miss = ballot(miss_mine);
+                uint64_t miss = ballot(miss_mine);
+                uint32_t spins = 0;
+                const int64_t t0 = miss ? wall_clock64() : 0;
+                while (miss != 0) {
+                    // every 256 polls: give up past the time limit, or at once when
+                    // another wave already gave up (a failed solve then drains)
+                    bool give_up = false, failed = false;
+                    if ((++spins & 255u) == 0) {
+                        failed = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                        give_up = failed || wall_clock64() - t0 > wait_ticks;
+                    }
+                    if (give_up) {
+                        // the slot this wave waited for (every lane takes part in the max)
+                        const bool mine_d = (miss >> lane) & 1ull;
+                        const int key_d = wave_max_i(mine_d ? (FWD ? c : -c) : INT_MIN);
+                        const int32_t lead_d = FWD ? key_d : -key_d;
+                        if (lane == 0) {
+                            atomicOr(err, 1);
+                            // the first wave to reach the limit records where it waited:
+                            // err[2..6] = direction, slot, awaited slot, awaited value
+                            // still absent, chunk
+                            if (!failed && atomicCAS(err + 1, 0, 1) == 0) {
+                                err[2] = FWD ? 1 : 0;
+                                err[3] = (int)s;
+                                err[4] = lead_d;
+                                err[5] = mload((const U*)sol + (int64_t)lead_d * nrhs + (nrhs - 1)) ==
+                                         MBits<T>::sentinel;
+                                err[6] = chunk;
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < MAXR; ++j)
+                            if (bits[j] == MBits<T>::sentinel) bits[j] = MBits<T>::nan_bits();
+                        break;
+                    }
+                    const bool mine = (miss >> lane) & 1ull;
+                    const int key = wave_max_i(mine ? (FWD ? c : -c) : INT_MIN);
+                    const int32_t lead = FWD ? key : -key;
+                    const U lb = mload((const U*)sol + (int64_t)lead * nrhs + (nrhs - 1));
+                    if (lb == MBits<T>::sentinel) {
+                        __builtin_amdgcn_s_sleep(2);
+                        continue;
+                    }
+                    miss_mine = false;
+#pragma unroll
+                    for (int j = 0; j < MAXR; ++j) {
+                        if (mine && j < nrhs && bits[j] == MBits<T>::sentinel) bits[j] = mload(src + j);
+                        miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
+                    }
+                    miss = ballot(miss_mine);
+                }
+#pragma unroll
+                for (int j = 0; j < MAXR; ++j) acc[j] += a * __builtin_bit_cast(T, bits[j]);
             }
+            const int32_t node = slot_node[s];
 #pragma unroll
-            for (int j = 0; j < MAXR; ++j) acc[j] += a * __builtin_bit_cast(T, bits[j]);
-        }
-        const int32_t node = slot_node[s];
-#pragma unroll
-        for (int j = 0; j < MAXR; ++j) {
-            if (j >= nrhs) continue;
-            const T sum = wave_sum(acc[j]);
-            if (lane == 0) {
-                const T base = FWD ? w[s * nrhs + j] / dslot[s] : (T)rhs[(int64_t)node * nrhs + j];
-                const T x = base - sum;
-                __hip_atomic_store((U*)sol + s * nrhs + j, __builtin_bit_cast(U, x),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (out) out[(int64_t)node * nrhs + j] = (double)x;
+            for (int j = 0; j < MAXR; ++j) {
+                if (j >= nrhs) continue;
+                const T sum = wave_sum(acc[j]);
+                if (lane == 0) {
+                    const T base_v = FWD ? w[s * nrhs + j] / dslot[s] : (T)rhs[(int64_t)node * nrhs + j];
+                    const T x = base_v - sum;
+                    __hip_atomic_store((U*)sol + s * nrhs + j, __builtin_bit_cast(U, x),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (out) out[(int64_t)node * nrhs + j] = (double)x;
+                }
             }
         }
     }
@@ -491,16 +520,23 @@ struct BatchWork {
     Sys* sys = nullptr;
     int* active = nullptr;
     int* err = nullptr;
+    unsigned long long* claim = nullptr;  // two solve-claim counters
+    int64_t wait_ticks = 0;
     Tiles tiles{};
     int64_t* mat_tile = nullptr;
 };
 
-// Ordinary (stream-ordered) launch of a grid that fits on the chip at once:
-// occupancy x CUs blocks, capped per CU by the autotuner.  Nothing else runs on the
-// device between this launch's neighbours on the stream, so every block is resident;
-// should one not be, the waits time out, drain, and the solve reports the failure.
+// Solve schedule: blocks per CU of the launch grid and slots per claim.
+struct Sched {
+    int per_cu = 0;  // 0: not tuned
+    int chunk = 0;
+};
+
+// Stream-ordered launch of a persistent grid of up to per_cu_cap blocks per CU (the
+// occupancy the kernel allows, capped), no more than the work can use.  Progress does
+// not depend on these blocks being resident together (see k_trsv_multi).
 template <typename K>
-hipError_t resident_launch(K kernel, int64_t rows, int per_cu_cap, void** args, hipStream_t s)
+hipError_t solve_launch(K kernel, int64_t rows, int chunk, int per_cu_cap, void** args, hipStream_t s)
 {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -509,20 +545,24 @@ hipError_t resident_launch(K kernel, int64_t rows, int per_cu_cap, void** args, 
     if (e != hipSuccess) return e;
     if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
     int64_t blocks = (int64_t)cus * std::max(1, per_cu);
-    blocks = std::min<int64_t>(blocks, (rows + BLOCK / 64 - 1) / (BLOCK / 64));
+    const int64_t claims = (rows + chunk - 1) / chunk;
+    blocks = std::min<int64_t>(blocks, (claims + BLOCK / 64 - 1) / (BLOCK / 64));
     if (blocks < 1) blocks = 1;
     return hipLaunchKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK), args, 0, s);
 }
 
 template <typename T>
-hipError_t batch_apply(const srw_factor* F, BatchWork& W, hipStream_t s)
+hipError_t batch_apply(const srw_factor* F, BatchWork& W, const Sched& sc, hipStream_t s)
 {
     int64_t n = F->n;
     int nrhs = W.nrhs;
+    int32_t chunk = sc.chunk;
+    int64_t ticks = W.wait_ticks;
     T* work = (T*)W.work;
     T* sol = work + n * nrhs;
     k_mfill<T><<<fill_grid(n * nrhs), BLOCK, 0, s>>>(n * nrhs, work);
     k_mfill<T><<<fill_grid(n * nrhs), BLOCK, 0, s>>>(n * nrhs, sol);
+    k_zero_u64<<<1, 64, 0, s>>>(W.claim, 2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     {
@@ -536,8 +576,10 @@ hipError_t batch_apply(const srw_factor* F, BatchWork& W, hipStream_t s)
         T* o = work;
         double* out = nullptr;
         int* err = W.err;
-        void* args[] = {&n, &nrhs, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err};
-        e = resident_launch(k_trsv_multi<T, false>, n, F->batch_per_cu, args, s);
+        unsigned long long* claim = W.claim;
+        void* args[] = {&n, &nrhs, &chunk, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err,
+                        &claim, &ticks};
+        e = solve_launch(k_trsv_multi<T, false>, n, chunk, sc.per_cu, args, s);
         if (e != hipSuccess) return e;
     }
     {
@@ -551,20 +593,22 @@ hipError_t batch_apply(const srw_factor* F, BatchWork& W, hipStream_t s)
         T* o = sol;
         double* out = W.z;
         int* err = W.err;
-        void* args[] = {&n, &nrhs, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err};
-        e = resident_launch(k_trsv_multi<T, true>, n, F->batch_per_cu, args, s);
+        unsigned long long* claim = W.claim + 1;
+        void* args[] = {&n, &nrhs, &chunk, &ptr, &col, &val, &dslot, &sn, &rhs, &w, &o, &out, &err,
+                        &claim, &ticks};
+        e = solve_launch(k_trsv_multi<T, true>, n, chunk, sc.per_cu, args, s);
     }
     return e;
 }
 
-hipError_t apply_b(const srw_factor* F, BatchWork& W, hipStream_t s)
+hipError_t apply_b(const srw_factor* F, BatchWork& W, const Sched& sc, hipStream_t s)
 {
-    return F->precision == SRW_FP32 ? batch_apply<float>(F, W, s) : batch_apply<double>(F, W, s);
+    return F->precision == SRW_FP32 ? batch_apply<float>(F, W, sc, s) : batch_apply<double>(F, W, sc, s);
 }
 
 // z = M^{-1} r, then rho / p for the active systems (restart = 1: p = z)
-hipError_t iteration(const srw_factor* F, BatchWork& W, double* X, double tol, int32_t max_iter,
-                     hipStream_t s)
+hipError_t iteration(const srw_factor* F, BatchWork& W, const Sched& sc, double* X, double tol,
+                     int32_t max_iter, hipStream_t s)
 {
     const srw_csr& A = F->Acat;
     const int nrhs = W.nrhs;
@@ -579,12 +623,42 @@ hipError_t iteration(const srw_factor* F, BatchWork& W, double* X, double tol, i
                                                       W.q, X, W.r, W.sys, W.partials);
     k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_RR, tol, max_iter, W.active);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = apply_b(F, W, s)) != hipSuccess) return e;
+    if ((e = apply_b(F, W, sc, s)) != hipSuccess) return e;
     k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.r,
                                                       W.z, nullptr, nullptr, W.sys, W.partials);
     k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_BETA, tol, max_iter, W.active);
     k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 0);
     return hipGetLastError();
+}
+
+// Process-wide cache of tuned solve schedules.
+struct TuneKey {
+    int64_t n, nnz;
+    int nrhs, precision;
+    bool operator<(const TuneKey& o) const
+    {
+        if (n != o.n) return n < o.n;
+        if (nnz != o.nnz) return nnz < o.nnz;
+        if (nrhs != o.nrhs) return nrhs < o.nrhs;
+        return precision < o.precision;
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, Sched> g_tuned;
+
+Sched tuned_schedule(const TuneKey& k)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(k);
+    return it == g_tuned.end() ? Sched{} : it->second;
+}
+
+void remember_schedule(const TuneKey& k, const Sched& sc, float ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[k] = sc;
+    (void)ms;
 }
 
 }  // namespace
@@ -617,7 +691,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     const size_t o_work = take(2 * nv * vb);
     const size_t o_part = take(std::max<int64_t>(W.ntile, 1) * nrhs * 8);
     const size_t o_sys = take(std::max<int64_t>(W.nsys, 1) * sizeof(Sys));
-    const size_t o_flag = take(64);
+    const size_t o_flag = take(128);
     const size_t o_tm = take(std::max<int64_t>(W.ntile, 1) * 4), o_tr = take((W.ntile + 1) * 8);
     const size_t o_mt = take((F->nmat + 1) * 8);
     char* ws = nullptr;
@@ -631,6 +705,8 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     W.sys = (Sys*)(ws + o_sys);
     W.active = (int*)(ws + o_flag);
     W.err = W.active + 1;
+    W.claim = (unsigned long long*)(ws + o_flag + 64);
+    W.wait_ticks = wait_ticks(5.0);
     int32_t* d_tmat = (int32_t*)(ws + o_tm);
     int64_t* d_trow = (int64_t*)(ws + o_tr);
     W.mat_tile = (int64_t*)(ws + o_mt);
@@ -640,7 +716,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     hipError_t e = hipHostMalloc((void**)&host_sys, std::max<int64_t>(W.nsys, 1) * sizeof(Sys), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&host_flag, 16 * sizeof(int), hipHostMallocDefault);
     if (host_flag) std::memset(host_flag, 0, 16 * sizeof(int));
-    int tuning_cap = 0;  // cap being timed when a solve failed (0: not while tuning)
+    Sched tuning{};  // schedule being timed when a solve failed (per_cu 0: not while tuning)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const int sg = (int)((W.nsys + 255) / 256);
@@ -673,44 +749,48 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         k_bfinal<<<sg, 256, 0, s>>>(W.nsys, nrhs, W.mat_tile, W.partials, W.sys, B_BB, tol, max_iter, W.active);
         e = hipGetLastError();
     }
-    // autotune the resident grid of the solves once per factor: 8, 4 or 2 blocks per CU
-    if (e == hipSuccess && F->batch_per_cu == 0) {
+    // the solve schedule: blocks per CU x slots per claim, timed once per problem shape
+    // (rows, factor entries, right-hand sides, precision) and kept for the process
+    const TuneKey key{F->n, F->nnz_y, nrhs, F->precision};
+    Sched sched = tuned_schedule(key);
+    if (e == hipSuccess && sched.per_cu == 0) {
         float best = 1e30f;
-        int best_cap = 8;
+        Sched best_s{8, 16};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
+        CK(apply_b(F, W, best_s, s));  // warm
         for (int cap : {8, 4, 2}) {
-            if (e != hipSuccess) break;
-            F->batch_per_cu = cap;
-            CK(apply_b(F, W, s));  // warm
-            CK(hipEventRecord(e0, s));
-            CK(apply_b(F, W, s));
-            CK(hipEventRecord(e1, s));
-            CK(hipEventSynchronize(e1));
-            CK(sync_flags());
-            if (e == hipSuccess && host_flag[1] != 0) {
-                tuning_cap = cap;
-                break;
+            for (int chunk : {4, 16, 64}) {
+                if (e != hipSuccess) break;
+                const Sched cand{cap, chunk};
+                CK(hipEventRecord(e0, s));
+                CK(apply_b(F, W, cand, s));
+                CK(hipEventRecord(e1, s));
+                CK(hipEventSynchronize(e1));
+                CK(sync_flags());
+                if (e == hipSuccess && host_flag[1] != 0) {
+                    tuning = cand;
+                    break;
+                }
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && ms < best) {
+                    best = ms;
+                    best_s = cand;
+                }
             }
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && ms < best) {
-                best = ms;
-                best_cap = cap;
-            }
+            if (tuning.per_cu) break;
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        F->batch_per_cu = best_cap;
-        F->batch_apply_ms = best;
+        sched = best_s;
+        if (e == hipSuccess && !tuning.per_cu) remember_schedule(key, sched, best);
     }
-    // a solve that failed while tuning stops the call (reported below; the next call
-    // tunes again)
+    // a solve that failed while tuning stops the call (reported below)
     const bool stop = host_flag[1] != 0;
-    if (stop) F->batch_per_cu = 0;
     // z = M^{-1} r, p = z, rho = r . z
-    if (!stop) CK(apply_b(F, W, s));
+    if (!stop) CK(apply_b(F, W, sched, s));
     if (e == hipSuccess && !stop) {
         k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 1);
         k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr, W.r,
@@ -727,7 +807,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         if (e == hipSuccess) {
-            hipError_t ce = iteration(F, W, X, tol, max_iter, cs);
+            hipError_t ce = iteration(F, W, sched, X, tol, max_iter, cs);
             hipError_t ee = hipStreamEndCapture(cs, &graph);
             e = ce != hipSuccess ? ce : ee;
         }
@@ -738,7 +818,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         while (e == hipSuccess && done_iters < max_iter) {
             for (int k = 0; k < CHUNK && e == hipSuccess; ++k) {
                 if (use_graph) e = hipGraphLaunch(exec, s);
-                else e = iteration(F, W, X, tol, max_iter, s);
+                else e = iteration(F, W, sched, X, tol, max_iter, s);
             }
             done_iters += CHUNK;
             if (e == hipSuccess) e = sync_flags();
@@ -754,7 +834,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         e = hipGetLastError();
         if (e == hipSuccess) e = sync_flags();
         if (e != hipSuccess || host_flag[0] == 0) break;
-        CK(apply_b(F, W, s));
+        CK(apply_b(F, W, sched, s));
         if (e == hipSuccess) {
             k_bupdate_p<<<grid_for(nv, 256), 256, 0, s>>>(W.N, nrhs, F->node_mat, W.z, W.p, W.sys, 1);
             k_tile<T_DOT><<<(unsigned)W.ntile, BLOCK, 0, s>>>(W.tiles, nrhs, nullptr, nullptr, nullptr,
@@ -769,13 +849,13 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         if (host_flag[1] != 0) {
             e = hipErrorLaunchFailure;  // a triangular solve gave up
             // host_flag[1 + i] = err[i]
+            const Sched& at = tuning.per_cu ? tuning : sched;
             std::snprintf(diag, sizeof(diag),
                           "batched %s solve gave up waiting: slot %d for slot %d (value %s), "
-                          "%d waves, cap %d%s",
+                          "%d blocks per CU, %d slots per claim%s",
                           host_flag[3] ? "forward" : "backward", host_flag[4], host_flag[5],
-                          host_flag[6] ? "absent" : "present", host_flag[7],
-                          tuning_cap ? tuning_cap : F->batch_per_cu,
-                          tuning_cap ? " (while tuning)" : "");
+                          host_flag[6] ? "absent" : "present", at.per_cu, host_flag[7],
+                          tuning.per_cu ? " (while tuning)" : "");
             where = diag;
         }
         bool all = true;

@@ -25,7 +25,7 @@ namespace {
 
 constexpr int BLOCK = 256;
 
-enum : int { ERR_ARG = 1, ERR_NOT_R = 2, ERR_SINGULAR = 4, ERR_LIMIT = 8, ERR_STACK = 16 };
+enum : int { ERR_ARG = 1, ERR_NOT_R = 2, ERR_SINGULAR = 4, ERR_LIMIT = 8, ERR_STACK = 16, ERR_WAIT = 32 };
 
 // ------------------------------------------------------------------- validation
 __global__ void k_check_structure(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
@@ -185,6 +185,15 @@ __global__ void k_rank_scatter(int64_t n, const uint32_t* __restrict__ sorted, i
     const uint32_t v = sorted[p];
     by_rank[p] = (int32_t)v;
     rank[v] = (int32_t)p;
+}
+
+// natural ordering: rank = node id
+__global__ void k_rank_natural(int64_t n, int32_t* rank, int32_t* by_rank)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    rank[v] = (int32_t)v;
+    by_rank[v] = (int32_t)v;
 }
 
 __global__ void k_rank_given(int64_t n, const int32_t* __restrict__ given, int32_t* rank,
@@ -888,6 +897,116 @@ unsigned row_grid(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)cus * 32));
 }
 
+// ------------------------------------------------------------------------ IC(0)
+// Zero fill-in incomplete Cholesky, the ICCG preconditioner the paper compares with
+// (Section 6, Tables 1-2), in the factor's form A ~ Y^T D Y: nodes are eliminated in
+// decreasing rank and every update outside A's pattern is discarded, so row k of Y
+// keeps exactly its lower-ranked neighbours (the pattern the build has laid out):
+//   D_k  = A_kk - sum_{j in Up(k)} (D_j Y_jk) Y_jk
+//   Y_ki = (A_ki - sum_{j in Up(k), j ~ i} (D_j Y_jk) Y_ji) / D_k
+// Up(k) = the higher-ranked neighbours of k, in the CSR order of row k.
+// One lane per row.  A wave claims the next 64 positions of the decreasing-rank order
+// (one atomic per claim) and its lanes wait for their rows' higher-ranked neighbours:
+// D of a row is published last (release), filled beforehand with a signalling-NaN
+// pattern, and is the row's ready flag.  Claims are handed out in order, so the
+// highest-ranked unfinished row always belongs to a running wave and has all its
+// dependencies done: the factorization progresses whatever the grid's residency.
+constexpr unsigned long long IC0_PENDING = 0x7FF4DEADBEEF5A5Aull;
+
+__global__ void k_fill_u64(int64_t n, unsigned long long* x, unsigned long long v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+__device__ __forceinline__ double ic0_entry(const int64_t* __restrict__ yptr,
+                                            const int32_t* __restrict__ ycol, const double* yval,
+                                            int64_t j, int32_t c)
+{
+    for (int64_t q = yptr[j]; q < yptr[j + 1]; ++q)
+        if (ycol[q] == c) return yval[q];
+    return 0.0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ic0(int64_t n, const int64_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ val,
+                                               const int32_t* __restrict__ rank,
+                                               const int32_t* __restrict__ by_rank,
+                                               const int64_t* __restrict__ yptr,
+                                               const int32_t* __restrict__ ycol, double* yval,
+                                               double* d, unsigned long long* claim, int* err,
+                                               int64_t ticks)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long* dbits = (unsigned long long*)d;
+    for (;;) {
+        const uint64_t base = lane0_u64(atomicAdd(claim, lane == 0 ? 64ull : 0ull));
+        if (base >= (uint64_t)n) break;
+        const int64_t pos = (int64_t)base + lane;
+        bool done = pos >= n;
+        const int32_t k = done ? 0 : by_rank[n - 1 - pos];
+        const int64_t r0 = done ? 0 : rowptr[k], r1 = done ? 0 : rowptr[k + 1];
+        const int32_t rk = done ? 0 : rank[k];
+        const int64_t t0 = wall_clock64();
+        uint32_t spins = 0;
+        while (ballot(!done) != 0) {
+            if (!done) {
+                bool ready = true;
+                for (int64_t p = r0; p < r1 && ready; ++p) {
+                    const int32_t j = col[p];
+                    if (j != k && rank[j] > rk)
+                        ready = __hip_atomic_load(dbits + j, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) != IC0_PENDING;
+                }
+                if (ready) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    double a = 0.0;
+                    for (int64_t p = r0; p < r1; ++p)
+                        if (col[p] == k) a = val[p];
+                    double dk = a;
+                    for (int64_t p = r0; p < r1; ++p) {
+                        const int32_t j = col[p];
+                        if (j == k || rank[j] < rk) continue;
+                        const double yjk = ic0_entry(yptr, ycol, yval, j, k);
+                        dk = dk - (d[j] * yjk) * yjk;
+                    }
+                    if (!(dk > 0.0)) atomicOr(err, ERR_NOT_R);
+                    int64_t q = yptr[k];
+                    for (int64_t p = r0; p < r1; ++p) {
+                        const int32_t i = col[p];
+                        if (i == k || rank[i] > rk) continue;
+                        double sv = val[p];
+                        for (int64_t p2 = r0; p2 < r1; ++p2) {
+                            const int32_t j = col[p2];
+                            if (j == k || rank[j] < rk) continue;
+                            const double yji = ic0_entry(yptr, ycol, yval, j, i);
+                            if (yji == 0.0) continue;
+                            const double yjk = ic0_entry(yptr, ycol, yval, j, k);
+                            sv = sv - (d[j] * yjk) * yji;
+                        }
+                        yval[q++] = sv / dk;
+                    }
+                    __hip_atomic_store(dbits + k, __builtin_bit_cast(unsigned long long, dk),
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    done = true;
+                }
+            }
+            // a guard against a defect: give up after the time limit (the rows left
+            // publish a quiet NaN so that the other waves drain)
+            if ((++spins & 255u) == 0 && wall_clock64() - t0 > ticks) {
+                if (!done) {
+                    atomicOr(err, ERR_WAIT);
+                    __hip_atomic_store(dbits + k, 0x7FF8000000000000ull, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    done = true;
+                }
+            }
+        }
+    }
+}
+
 int map_err(int e)
 {
     if (e & ERR_ARG) return SRW_E_ARG;
@@ -897,6 +1016,10 @@ int map_err(int e)
     if (e & ERR_STACK) {
         set_last_error("walk reuse: a walk's stack of open walks grew past its capacity");
         return SRW_E_WALK_LIMIT;
+    }
+    if (e & ERR_WAIT) {
+        set_last_error("IC(0): a row gave up waiting for a higher-ranked row");
+        return SRW_E_HIP;
     }
     return SRW_OK;
 }
@@ -1067,7 +1190,7 @@ int ordering_impl(int64_t n, uint64_t seed, int32_t* rank, hipStream_t s)
 
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                       const srw_options* opt_in, srw_factor** out, hipStream_t s,
-                      const BatchKeys* batch, const LengthRule* rule, bool asym)
+                      const BatchKeys* batch, const LengthRule* rule, bool asym, bool ic0)
 {
     srw_options opt;
     srw_default_options(&opt);
@@ -1079,6 +1202,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
     // walks-only builds
     const bool reuse = opt.reuse != 0;
     if (reuse && (opt.refill_period != 8 || opt.keep >= 2 || batch || rule)) return SRW_E_ARG;
+    // IC(0): no walks and no drop; the walk build lays out the pattern (every row's
+    // lower-ranked neighbours), then k_ic0 fills in the values, FP64 only
+    if (ic0) {
+        if (reuse || batch || rule || asym || opt.factor_precision != SRW_FP64) return SRW_E_ARG;
+        walks_per_row = NO_WALKS;
+        drop_tol = 0.0;
+    }
     const int64_t n = A->n, nnz = A->nnz;
     const int64_t nnz_off = nnz - n;
 
@@ -1179,6 +1309,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             if (!seen) FAIL(SRW_E_NOMEM);
             CHECK_HIP(hipMemsetAsync(seen, 0, n * sizeof(int32_t), s));
             k_rank_given<<<g, BLOCK, 0, s>>>(n, opt.rank, F->rank, F->by_rank, seen, err);
+        } else if (opt.ordering == SRW_ORDER_NATURAL) {
+            k_rank_natural<<<g, BLOCK, 0, s>>>(n, F->rank, F->by_rank);
         } else {
             uint64_t* keys = ALLOC(tmp, uint64_t, n);
             uint64_t* keys2 = ALLOC(tmp, uint64_t, n);
@@ -1268,6 +1400,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         const int64_t norder = nlong + nslab_rows;
         int32_t max_budget = 0;
         std::memcpy(&max_budget, &pinned[3], sizeof(int32_t));
+        // a chunk descriptor packs the first walk of a chunk into 16 bits and the tally
+        // holds a row's ends in LDS: per-row budgets above 8192 are refused here, before
+        // any walk runs
+        if (max_budget > 8192) {
+            set_last_error("srw_build_factor: a per-row walk budget exceeds 8192");
+            FAIL(SRW_E_ARG);
+        }
         k_compact<<<grid_for(long_rank, BLOCK), BLOCK, 0, s>>>(long_rank, F->by_rank, flag, pos, 0,
                                                                budget, order, chunks, SRW_WAVE);
         k_compact<<<g, BLOCK, 0, s>>>(n, nullptr, flag2, pos2, nlong, budget, order, chunks,
@@ -1523,6 +1662,28 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
                                                       drop_tol, nullptr, F->yptr, F->ycol,
                                                       (double*)F->yval, (double*)F->d);
         CHECK_HIP(hipGetLastError());
+
+        if (ic0 && n > 0) {
+            unsigned long long* claim = (unsigned long long*)ALLOC(tmp, int64_t, 1);
+            if (!claim) FAIL(SRW_E_NOMEM);
+            CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+            CHECK_HIP(hipMemsetAsync(claim, 0, sizeof(int64_t), s));
+            k_fill_u64<<<std::min(g, 2048), BLOCK, 0, s>>>(n, (unsigned long long*)F->d, IC0_PENDING);
+            int dev = 0, cus = 0;
+            CHECK_HIP(hipGetDevice(&dev));
+            CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            const int64_t claims = (n + 63) / 64;
+            const int blocks = (int)std::max<int64_t>(
+                1, std::min<int64_t>((int64_t)cus * 8, (claims + BLOCK / 64 - 1) / (BLOCK / 64)));
+            k_ic0<<<blocks, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, F->by_rank,
+                                           F->yptr, F->ycol, (double*)F->yval, (double*)F->d,
+                                           claim, err, wait_ticks(10.0));
+            CHECK_HIP(hipGetLastError());
+            CHECK_HIP(hipMemcpyAsync(&pinned[0], err, sizeof(int), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            std::memcpy(&herr, &pinned[0], sizeof(int));
+            if (herr) FAIL(map_err(herr));
+        }
 
         // ---- 7. Y^T by a stable sort of the entries on their column, then the plan
         mark(7);

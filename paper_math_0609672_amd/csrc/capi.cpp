@@ -28,7 +28,9 @@ int copy_out(T* dst, const void* src, size_t count, hipStream_t s)
 int options_ok(const srw_options* opt, int64_t n)
 {
     if (!opt) return SRW_OK;
-    if (opt->ordering != SRW_ORDER_RANDOM && opt->ordering != SRW_ORDER_GIVEN) return SRW_E_ARG;
+    if (opt->ordering != SRW_ORDER_RANDOM && opt->ordering != SRW_ORDER_GIVEN &&
+        opt->ordering != SRW_ORDER_NATURAL)
+        return SRW_E_ARG;
     if (opt->factor_precision != SRW_FP64 && opt->factor_precision != SRW_FP32) return SRW_E_ARG;
     if (opt->keep < 0 || opt->keep > 2) return SRW_E_ARG;
     const int rp = opt->refill_period;
@@ -139,6 +141,24 @@ int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, u
     if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
     try {
         return srw::build_factor_impl(A, walks_per_row, drop_tol, seed, opt, out, as_stream(stream));
+    } catch (const std::bad_alloc&) {
+        return SRW_E_NOMEM;
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
+int srw_build_ic0(const srw_csr* A, uint64_t seed, const srw_options* opt, srw_factor** out,
+                  void* stream)
+{
+    if (!out) return SRW_E_ARG;
+    *out = nullptr;
+    if (!csr_ok(A)) return SRW_E_ARG;
+    if (options_ok(opt, A->n) != SRW_OK) return SRW_E_ARG;
+    if (opt && (opt->reuse || opt->factor_precision != SRW_FP64 || opt->walks)) return SRW_E_ARG;
+    try {
+        return srw::build_factor_impl(A, 1, 0.0, seed, opt, out, as_stream(stream), nullptr,
+                                      nullptr, false, true);
     } catch (const std::bad_alloc&) {
         return SRW_E_NOMEM;
     } catch (...) {

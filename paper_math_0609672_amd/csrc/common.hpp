@@ -33,11 +33,18 @@ int hip_fail(hipError_t e, const char* what);
 // [8, 12) the solvers, [16] the adaptive budget rounds.
 int64_t* host_scratch();
 void set_last_error(const char* msg);
+// Ticks of the device's constant-rate wall clock (wall_clock64) in `seconds`, for the
+// current device; the time limit of the triangular solves' waits.
+int64_t wait_ticks(double seconds);
 const char* get_last_error();
 
 // Ground and step-limit markers in walk records / end-node lists.
 constexpr uint32_t END_GROUND = 0xFFFFFFFFu;
 constexpr uint32_t END_LIMIT = 0xFFFFFFFEu;
+
+// walks_per_row of an internal build that runs no walks: every row keeps only its
+// deterministic part (the IC(0) build lays out its pattern this way).
+constexpr int32_t NO_WALKS = -1;
 
 // |e_k| <= EXCESS_EPS * A_kk is zero excess (no path to ground).
 constexpr double EXCESS_EPS = 1e-12;

@@ -55,8 +55,6 @@ struct srw_factor {
     int64_t* mat_off = nullptr;         // device copy
     int32_t* node_mat = nullptr;        // [n] matrix of every stacked row
     srw_csr Acat{0, 0, nullptr, nullptr, nullptr};  // the stacked matrix (owned)
-    int32_t batch_per_cu = 0;           // solve grid picked by the autotuner (0 = not yet)
-    float batch_apply_ms = -1.0f;       // its measured time for one application
 
     // kept on request (srw_options.keep)
     uint2* ent = nullptr;          // [nnz-n] {neighbour, threshold}
@@ -166,7 +164,7 @@ constexpr int SRW_WALKS_ONLY = 100;
 int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                       const srw_options* opt, srw_factor** out, hipStream_t s,
                       const BatchKeys* batch = nullptr, const LengthRule* rule = nullptr,
-                      bool asym = false);
+                      bool asym = false, bool ic0 = false);
 // Asymmetric A (Section 7.1): the game of A, then the game of A^T with its ordering.
 int build_ldu_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                    const srw_options* opt, srw_factor** out, hipStream_t s);

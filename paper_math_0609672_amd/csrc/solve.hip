@@ -7,6 +7,7 @@
 // The scalars of the iteration (rho, alpha, beta, ||r||^2) live on the device; the
 // host reads ||r||^2 once per iteration for the stopping test.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 
@@ -187,9 +188,10 @@ struct Bits<int32_t> {
     static __device__ U nan_bits() { return 0u; }
 };
 
-// A wait that outlives this many polls (about a second) marks the solve failed and
-// proceeds with a NaN; the caller then reports the failure.
-constexpr uint32_t SPIN_LIMIT = 1u << 20;
+// A wait longer than wait_ticks of the wall clock marks the solve failed and proceeds
+// with a NaN; the caller then reports the failure.  The limit guards against a defect
+// (a wave waits at most for the chain of slots before its own); it is seconds, far
+// above any legitimate wait.
 
 #ifndef SRW_POLL_SLEEP
 #define SRW_POLL_SLEEP 2  // s_sleep units (64 clocks) between polls of a missing value
@@ -221,18 +223,22 @@ __device__ __forceinline__ U load_published(const U* p)
 // A wait that gives up raises *err and leaves a NaN in the missing lanes.
 template <typename T, bool LATE_HIGH>
 __device__ __forceinline__ void wait_published(typename Bits<T>::U& bits, const int32_t c,
-                                               const bool valid, const T* sol, int* err)
+                                               const bool valid, const T* sol, int* err,
+                                               int64_t ticks)
 {
     using U = typename Bits<T>::U;
     const int lane = threadIdx.x & 63;
     uint64_t miss = ballot(valid && bits == Bits<T>::sentinel);
     uint32_t spins = 0;
+    const int64_t t0 = miss ? wall_clock64() : 0;
     while (miss != 0) {
-        // give up at the limit, or at once when another wave already gave up (a failed
-        // solve then drains instead of waiting at every row)
-        const bool failed = (spins & 255u) == 255u &&
-                            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        if (++spins > SPIN_LIMIT || failed) {
+        // every 256 polls: give up past the time limit, or at once when another wave
+        // already gave up (a failed solve then drains instead of waiting at every row)
+        bool give_up = false;
+        if ((++spins & 255u) == 0)
+            give_up = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                      wall_clock64() - t0 > ticks;
+        if (give_up) {
             if (lane == 0) atomicOr(err, 1);
             if ((miss >> lane) & 1ull) bits = Bits<T>::nan_bits();
             break;
@@ -262,7 +268,8 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
                                                 const int32_t* __restrict__ slot_node,
                                                 const double* __restrict__ rhs,
                                                 const T* __restrict__ w, T* sol,
-                                                double* __restrict__ out, int* err)
+                                                double* __restrict__ out, int* err,
+                                                int64_t ticks)
 {
     using U = typename Bits<T>::U;
     const int lane = threadIdx.x & 63;
@@ -297,7 +304,7 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
                 v2 = val[p0 + lane];
             }
         }
-        wait_published<T, FWD>(bits, c, valid, sol, err);
+        wait_published<T, FWD>(bits, c, valid, sol, err, ticks);
         T acc = v * __builtin_bit_cast(T, bits);
         for (int64_t qb = q0 + 64; qb < q1; qb += 64) {  // rows longer than 64 entries
             const int64_t q = qb + lane;
@@ -305,7 +312,7 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
             const int32_t cc = ok ? col[q] : 0;
             const T vv = ok ? val[q] : T(0);
             U bb = ok ? load_published((const U*)sol + cc) : U(0);
-            wait_published<T, FWD>(bb, cc, ok, sol, err);
+            wait_published<T, FWD>(bb, cc, ok, sol, err, ticks);
             acc += vv * __builtin_bit_cast(T, bb);
         }
         acc = wave_sum(acc);
@@ -328,7 +335,7 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
 // Each wave keeps the largest level it met; one atomic per wave gives the depth.
 __global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int64_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col, int32_t* lev,
-                                                  int* depth, int* err)
+                                                  int* depth, int* err, int64_t ticks)
 {
     using U = Bits<int32_t>::U;
     const int lane = threadIdx.x & 63;
@@ -343,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int64_t* __re
             const bool ok = q < ptr[s + 1];
             const int32_t c = ok ? col[q] : 0;
             U bits = ok ? load_published((const U*)lev + c) : U(0);
-            wait_published<int32_t, true>(bits, c, ok, lev, err);
+            wait_published<int32_t, true>(bits, c, ok, lev, err, ticks);
             if (ok) m = max(m, (int)bits);
         }
         m = wave_max_i32(m) + 1;
@@ -379,6 +386,7 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
                       hipStream_t s)
 {
     int64_t n = F->n;
+    int64_t ticks = wait_ticks(5.0);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, work);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, sol);
     hipError_t e = hipGetLastError();
@@ -393,7 +401,7 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
         const T* w = nullptr;
         T* out_sol = work;
         double* out = nullptr;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
         e = coop_launch(k_trsv<T, false>, n, args, s);
         if (e != hipSuccess) return e;
     }
@@ -407,7 +415,7 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
         const T* w = work;
         T* out_sol = sol;
         double* out = z;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
         e = coop_launch(k_trsv<T, true>, n, args, s);
     }
     return e;
@@ -430,6 +438,7 @@ hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol,
 {
     const srw_factor* G = F->tgame;
     int64_t n = F->n;
+    int64_t ticks = wait_ticks(5.0);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, work);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, sol);
     hipError_t e = hipGetLastError();
@@ -444,7 +453,7 @@ hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol,
         const T* w = nullptr;
         T* out_sol = work;
         double* out = z;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
         e = coop_launch(k_trsv<T, false>, n, args, s);
         if (e != hipSuccess) return e;
     }
@@ -460,7 +469,7 @@ hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol,
         const T* w = work;
         T* out_sol = sol;
         double* out = z;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err};
+        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
         e = coop_launch(k_trsv<T, true>, n, args, s);
     }
     return e;
@@ -494,6 +503,20 @@ int red_grid(int64_t n)
 }
 
 }  // namespace
+
+int64_t wait_ticks(double seconds)
+{
+    static std::atomic<int> rate_khz[64];  // per device, 0 = not read yet
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    int khz = rate_khz[dev].load(std::memory_order_relaxed);
+    if (khz == 0) {
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;  // the 100 MHz clock of this device family
+        rate_khz[dev].store(khz, std::memory_order_relaxed);
+    }
+    return (int64_t)(seconds * 1000.0 * (double)khz);
+}
 
 hipError_t apply_factor(const srw_factor* F, const double* r, void* work, double* z, int* err,
                         hipStream_t s)
@@ -536,7 +559,8 @@ int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s)
     if (e == hipSuccess) {
         const int64_t* ptr = F->fptr;
         const int32_t* col = F->fcol;
-        void* args[] = {&n, &ptr, &col, &lev, &depth, &err};
+        int64_t ticks = wait_ticks(5.0);
+        void* args[] = {&n, &ptr, &col, &lev, &depth, &err, &ticks};
         e = coop_launch(k_levels, n, args, s);
     }
     int host[2] = {0, 0};

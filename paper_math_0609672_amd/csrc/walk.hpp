@@ -117,7 +117,7 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
     }
     tau[v] = motel / a;
     int32_t b = 0;
-    if (motel > 0.0) {
+    if (motel > 0.0 && walks_per_row != NO_WALKS) {
         b = budget_in ? budget_in[v] : walks_per_row;
         if (b < 1) b = 1;
         atomicMax(max_budget, b);

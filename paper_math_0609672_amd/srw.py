@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsrw.so")
 
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_NOT_RMATRIX, E_SINGULAR, E_WALK_LIMIT, E_NOMEM, E_HIP = -1, -2, -3, -4, -5, -6
-ORDER_RANDOM, ORDER_GIVEN = 0, 1
+ORDER_RANDOM, ORDER_GIVEN, ORDER_NATURAL = 0, 1, 2
 FP64, FP32 = 0, 1
 
 
@@ -66,6 +66,7 @@ _lib.srw_default_options.argtypes = [ctypes.POINTER(_Options)]
 _lib.srw_build_factor.argtypes = [ctypes.POINTER(_Csr), _I32, _D, _U64, ctypes.POINTER(_Options),
                                   ctypes.POINTER(_P), _P]
 _lib.srw_factor_free.argtypes = [_P]
+_lib.srw_build_ic0.argtypes = [ctypes.POINTER(_Csr), _U64, ctypes.POINTER(_Options), ctypes.POINTER(_P), _P]
 _lib.srw_factor_info.argtypes = [_P] + [_P] * 8
 _lib.srw_factor_stats.argtypes = [_P, ctypes.POINTER(_Stats)]
 _lib.srw_factor_depth.argtypes = [_P, ctypes.POINTER(_I32), _P]
@@ -98,7 +99,7 @@ _lib.srw_last_error.restype = ctypes.c_char_p
 _lib.srw_status_string.argtypes = [ctypes.c_int]
 _lib.srw_status_string.restype = ctypes.c_char_p
 
-EXPORTED = ["srw_default_options", "srw_build_factor", "srw_factor_free", "srw_factor_info",
+EXPORTED = ["srw_default_options", "srw_build_factor", "srw_build_ic0", "srw_factor_free", "srw_factor_info",
             "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
             "srw_pcg_solve", "srw_apply", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
@@ -275,6 +276,20 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
     return Factor(h.value, A.rowptr.device)
 
 
+def build_ic0(A: Matrix, seed: int = 0, *, rank="natural", solve_order: int = 2,
+              stream=None) -> Factor:
+    """srw_build_ic0: zero fill-in incomplete Cholesky in the factor's form (the ICCG
+    comparison of Section 6); natural ordering unless `rank` is a device tensor of
+    ranks or None (the random ordering of `seed`)."""
+    opt = _options(rank, None, "fp64", 0, 0, 0, False, 1, solve_order, False)
+    h = ctypes.c_void_p(0)
+    csr = A.c()
+    st = _lib.srw_build_ic0(ctypes.byref(csr), int(seed) & (2**64 - 1), ctypes.byref(opt),
+                            ctypes.byref(h), _stream(stream))
+    _check(st, "srw_build_ic0")
+    return Factor(h.value, A.rowptr.device)
+
+
 def build_factor_ldu(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None,
                      walks=None, precision: str = "fp64", max_steps: int = 0, keep: int = 0,
                      refill_period: int = 0, profile: bool = False, schedule: int = 1,
@@ -312,7 +327,11 @@ def _options(rank, walks, precision, max_steps, keep, refill_period, profile, sc
              solve_order, reuse, walk_waves=0) -> _Options:
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
-    if rank is not None:
+    if isinstance(rank, str):
+        if rank != "natural":
+            raise ValueError("rank: a device tensor of ranks, or 'natural'")
+        opt.ordering = ORDER_NATURAL
+    elif rank is not None:
         opt.ordering = ORDER_GIVEN
         opt.rank = _ptr(rank).value
     if walks is not None:

@@ -5,15 +5,21 @@ node, and for sampled rows (the 16 lowest-ranked, whose walks are the longest, a
 drawn uniformly) every walk record, the tallies and the factor row, bit-exact with the
 oracle, which computes those rows one by one.  PCG to 1e-8 and the preconditioner are
 checked through properties that hold at any size: the true residual, recomputed on the
-host, and Y^T D Y z = r for z = M^{-1} r.  The asymmetric 128^3 grid gets the same
+host, and Y^T D Y z = r for z = M^{-1} r.  Then the whole factor, built by the oracle
+with its rows split over host threads, is bit-exact with the GPU factor, and PCG takes
+the oracle's number of iterations with iterates within 1e-10.  The asymmetric 128^3 grid gets the same
 sampled check for both of its games, and the random geometric graph (n = 2,000,000,
 512 walks per row, FP32 factor under FP64 PCG to 1e-10; generated in about a minute on
 the host) for its FP32 factor rows, which must be the oracle's FP64 rows rounded once.
 The batch of 256 pruned grids (8.86M rows, 64 walks per row, 8 right-hand sides each):
 sampled blocks of the batched factor equal the single builds of their matrices, which
-are bit-exact with the oracle on sampled rows, and every one of the 2,048 systems meets
-1e-8 on its true residual.
+are bit-exact with the oracle on sampled rows, every one of the 2,048 systems meets
+1e-8 on its true residual, and the 8 systems of each of four sampled blocks (the
+smallest and largest matrices among them) match the oracle's PCG on its whole factor of
+that matrix: same iteration count, iterates within 1e-10.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -109,6 +115,40 @@ def test_grid3d_128_sampled_rows_and_pcg(srw):
     assert np.linalg.norm(back - r) <= 1e-10 * np.linalg.norm(r)
 
 
+def host_threads() -> int:
+    """Host threads for the oracle: the machine's CPU share (16 per GPU) at most."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def test_grid3d_128_whole_factor_and_pcg_match_oracle(srw):
+    # the oracle builds the whole 128^3 factor (rows split over host threads, the same
+    # per-row code); the GPU factor, built in the bench's launch configuration, must be
+    # bit-exact with it, and PCG must take the oracle's iterations with iterates within
+    # 1e-10
+    A = W.config_grid3d(128, 0)
+    n = A.n
+    Mx = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(Mx, WALKS, DROP, SEED)
+    ex = {k: np_(v) for k, v in F.export().items()}
+    ref = O.build_factor(A, WALKS, DROP, SEED, threads=host_threads())
+    assert np.array_equal(ex["rank"], ref.rank)
+    assert np.array_equal(ex["yptr"], ref.yptr)
+    assert np.array_equal(ex["ycol"], ref.ycol)
+    assert np.array_equal(ex["yval"], ref.yval)
+    assert np.array_equal(ex["d"], ref.d)
+    b = W.rhs(n, seed=0)
+    st, x, it, rel = srw.pcg_solve(Mx, F, torch.as_tensor(b, device=DEV), 1e-8)
+    F.free()
+    st_o, x_o, it_o, rel_o = O.pcg(A, ref, b, 1e-8)
+    assert st == st_o == 0
+    if it != it_o:  # the stopping test flipped on rounding: compare at the GPU's count
+        assert abs(it - it_o) <= 1, (it, it_o)
+        st_o, x_o, it_o, _ = O.pcg(A, ref, b, 0.0, max_iter=it)
+    err = np.linalg.norm(np_(x) - x_o) / np.linalg.norm(x_o)
+    assert err <= 1e-10, err
+    assert abs(rel - rel_o) <= 1e-10  # true residuals (relative to ||b||) agree
+
+
 def test_grid3d_asym_128_sampled_rows_both_games(srw):
     A = W.config_grid3d_asym(128, 0)
     n = A.n
@@ -175,3 +215,20 @@ def test_batch_256_sampled_blocks_and_pcg(srw):
         R = Bh[a:b] - S @ Xh[a:b]
         worst = max(worst, float(np.max(np.linalg.norm(R, axis=0) / np.linalg.norm(Bh[a:b], axis=0))))
     assert worst <= 1e-8
+    # the sampled blocks' 8 systems each against the oracle's PCG on the oracle's whole
+    # factor of that matrix: same iteration count, iterates within 1e-10
+    apart = 0
+    for i in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 128}):
+        A = mats[i]
+        a, b = off[i], off[i + 1]
+        Fo = O.build_factor(A, 64, 1e-3, seeds[i])
+        for j in range(8):
+            bj = Bh[a:b, j]
+            sto, xo, ito, _ = O.pcg(A, Fo, bj, 1e-8)
+            if ito != it[i, j]:
+                assert abs(ito - int(it[i, j])) <= 1, (i, j, ito, it[i, j])
+                apart += 1
+                sto, xo, ito, _ = O.pcg(A, Fo, bj, 0.0, max_iter=int(it[i, j]))
+            err = np.linalg.norm(Xh[a:b, j] - xo) / np.linalg.norm(xo)
+            assert err <= 1e-10, (i, j, err)
+    assert apart <= 2

@@ -329,6 +329,42 @@ def test_error_statuses(srw):
     assert e.value.status == srw.E_ARG
 
 
+@pytest.mark.parametrize("reuse", [False, True])
+def test_per_row_budget_above_limit_is_refused(srw, reuse):
+    # a chunk descriptor holds the first walk of a chunk in 16 bits: a budget past the
+    # limit (here 65,537 on one row) must fail before any walk runs, with or without reuse
+    good = W.config_grid2d_32()
+    M = srw.Matrix.from_host(good, DEV)
+    budget = np.full(good.n, 8, np.int32)
+    k = int(np.flatnonzero(O.table(good, O.rank(good.n, 0)).tau > 0)[0])  # a row that walks
+    for over in (65537, 8193):
+        budget[k] = over
+        with pytest.raises(srw.SrwError) as e:
+            srw.build_factor(M, 8, 0.0, 0, walks=torch.as_tensor(budget, device=DEV), reuse=reuse)
+        assert e.value.status == srw.E_ARG
+    budget[k] = 8192  # the limit itself builds
+    F = srw.build_factor(M, 8, 0.0, 0, walks=torch.as_tensor(budget, device=DEV), reuse=reuse)
+    F.free()
+
+
+def test_natural_ordering_matches_oracle(srw):
+    # rank = node id: the ordering the paper's derivations are written in
+    A, walks = CASES["grid2d_37x29"]
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, 1e-3, 4, rank="natural")
+    ref = O.build_factor(A, walks, 1e-3, 4, rk=np.arange(A.n, dtype=np.int32))
+    got = {k: np_(v) for k, v in F.export().items()}
+    assert np.array_equal(got["rank"], np.arange(A.n))
+    assert np.array_equal(got["yptr"], ref.yptr) and np.array_equal(got["ycol"], ref.ycol)
+    assert np.array_equal(got["yval"], ref.yval) and np.array_equal(got["d"], ref.d)
+    b = W.rhs(A.n, seed=2)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), 1e-8)
+    st_o, x_o, it_o, _ = O.pcg(A, ref, b, 1e-8)
+    assert st == st_o == 0 and it == it_o
+    assert np.linalg.norm(np_(x) - x_o) <= 1e-10 * np.linalg.norm(x_o)
+    F.free()
+
+
 def test_given_ordering_matches_oracle(srw):
     A, walks = CASES["grid2d_37x29"]
     rk = np.random.default_rng(3).permutation(A.n).astype(np.int32)

@@ -290,6 +290,19 @@ int srw_pcg_solve(const srw_csr* A, const srw_factor* F, const double* b, double
  * each; r is not modified). */
 int srw_apply(const srw_factor* F, const double* r, double* z, void* stream);
 
+/* srw_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * the same result bit for bit, with the triangular solves' work vectors and failure
+ * flag in a static scratch array of the library (one per device, 32 MiB + 256 B, held
+ * until the process ends) instead of stream-ordered allocations.  It calls no
+ * allocating routine.  Limit: F's rows <= SRW_NOALLOC_MAX_N, else SRW_E_ARG (see
+ * srw_last_error).  Every call on a device shares that device's scratch: calls that
+ * overlap on one device (other streams, other threads) race and must be serialised by
+ * the caller.  The call synchronises `stream` to read the solves' status (SRW_E_HIP if
+ * a solve gave up waiting). */
+#define SRW_NOALLOC_MAX_N (1 << 21)
+int srw_apply_noalloc(const srw_factor* F, const double* r, double* z, void* stream);
+
 /* Walks per row by the stopping rule of Section 5.1: walks run from row k one after
  * another until the relative error of their mean length is within delta at confidence
  * alpha, tested as delta * mean * sqrt(M) / sigma > z with z = Q^{-1}((1 - alpha) / 2)

@@ -366,6 +366,14 @@ int srw_apply(const srw_factor* F, const double* r, double* z, void* stream)
     return srw::apply_impl(const_cast<srw_factor*>(F), r, z, as_stream(stream));
 }
 
+int srw_apply_noalloc(const srw_factor* F, const double* r, double* z, void* stream)
+{
+    if (!F) return SRW_E_ARG;
+    if (F->n == 0) return SRW_OK;
+    if (!r || !z) return SRW_E_ARG;
+    return srw::apply_noalloc_impl(F, r, z, as_stream(stream));
+}
+
 int srw_adaptive_budgets(const srw_csr* A, uint64_t seed, const srw_options* opt, double delta,
                          double z, int32_t min_walks, int32_t max_walks, int32_t* walks,
                          void* stream)

@@ -179,6 +179,8 @@ int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt, doubl
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
+// srw_apply with the library's static scratch instead of allocations.
+int apply_noalloc_impl(const srw_factor* F, const double* r, double* z, hipStream_t s);
 int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);
 // Dependency level of every slot of the plan (lev, caller-allocated [n]) and the depth.
 int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s);

@@ -8,6 +8,7 @@
 // host reads ||r||^2 once per iteration for the stopping test.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 
@@ -540,6 +541,65 @@ int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s)
     (void)hipStreamSynchronize(s);
     SRW_HIP(e);
     return herr ? SRW_E_HIP : SRW_OK;
+}
+
+// ------------------------------------------------------ allocation-free application
+// Scratch of srw_apply_noalloc: the two work vectors of the triangular solves (up to
+// SRW_NOALLOC_MAX_N values each, FP64 or FP32) and the solves' failure flag.  One copy
+// per device, held until the process ends; every call on a device shares it.
+constexpr size_t NOALLOC_WORK_BYTES = 2 * (size_t)SRW_NOALLOC_MAX_N * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_WORK_BYTES + 256];
+
+namespace {
+
+// The device address of `scratch` on each device, looked up once per device with that
+// device current (the array's name in host code is a host-side stand-in, not a device
+// address).
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+hipError_t scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+__global__ void k_clear_flag(int* f) { *f = 0; }
+
+}  // namespace
+
+int apply_noalloc_impl(const srw_factor* F, const double* r, double* z, hipStream_t s)
+{
+    if (F->n > (int64_t)SRW_NOALLOC_MAX_N) {
+        set_last_error("srw_apply_noalloc: the factor has more rows than SRW_NOALLOC_MAX_N");
+        return SRW_E_ARG;
+    }
+    void* base = nullptr;
+    SRW_HIP(scratch_address(&base));
+    char* work = (char*)base;
+    int* err = (int*)(work + NOALLOC_WORK_BYTES);
+    k_clear_flag<<<1, 1, 0, s>>>(err);  // a kernel, not a memset
+    SRW_HIP(hipGetLastError());
+    SRW_HIP(apply_any(F, r, work, z, err, s));
+    int herr = 0;
+    SRW_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    SRW_HIP(hipStreamSynchronize(s));
+    if (herr) {
+        set_last_error("srw_apply_noalloc: a triangular solve gave up waiting");
+        return SRW_E_HIP;
+    }
+    return SRW_OK;
 }
 
 int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s)

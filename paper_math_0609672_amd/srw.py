@@ -77,6 +77,7 @@ _lib.srw_walk_export.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.srw_pcg_solve.argtypes = [ctypes.POINTER(_Csr), _P, _P, _D, _I32, _P, ctypes.POINTER(_I32),
                                ctypes.POINTER(_D), _P]
 _lib.srw_apply.argtypes = [_P, _P, _P, _P]
+_lib.srw_apply_noalloc.argtypes = [_P, _P, _P, _P]
 _lib.srw_ordering.argtypes = [_I64, _U64, _P, _P]
 _lib.srw_adaptive_budgets.argtypes = [ctypes.POINTER(_Csr), _U64, ctypes.POINTER(_Options), _D, _D,
                                       _I32, _I32, _P, _P]
@@ -102,10 +103,11 @@ _lib.srw_status_string.restype = ctypes.c_char_p
 EXPORTED = ["srw_default_options", "srw_build_factor", "srw_build_ic0", "srw_factor_free", "srw_factor_info",
             "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
-            "srw_pcg_solve", "srw_apply", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
+            "srw_pcg_solve", "srw_apply", "srw_apply_noalloc", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
             "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_budgets", "srw_build_factor_batched",
             "srw_batch_info", "srw_pcg_solve_batched", "srw_last_error", "srw_status_string"]
 
+NOALLOC_MAX_N = 1 << 21  # SRW_NOALLOC_MAX_N
 MLP_PARAMS = 4801
 NUM_FEATURES = 8
 
@@ -368,6 +370,16 @@ def apply(F: Factor, r: torch.Tensor, stream=None) -> torch.Tensor:
     z = torch.empty_like(r)
     st = _lib.srw_apply(F.handle, _ptr(r), _ptr(z), _stream(stream))
     _check(st, "srw_apply")
+    return z
+
+
+def apply_noalloc(F: Factor, r: torch.Tensor, z=None, stream=None) -> torch.Tensor:
+    """srw_apply_noalloc: z = (Y^T D Y)^{-1} r with the library's static scratch (no
+    device allocation by the library; z is allocated here unless given)."""
+    if z is None:
+        z = torch.empty_like(r)
+    st = _lib.srw_apply_noalloc(F.handle, _ptr(r), _ptr(z), _stream(stream))
+    _check(st, "srw_apply_noalloc")
     return z
 
 

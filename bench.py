@@ -47,6 +47,10 @@ ONES_RHS = {k for k in WORKLOADS if k.startswith("laplace3d_")}
 for _m in (64, 128):
     WORKLOADS[f"grid3d_asym_{_m}"] = ("config_grid3d_asym", dict(m=_m), 256, 1e-4, 1e-8)
 ASYM = {k for k in WORKLOADS if k.startswith("grid3d_asym_")}
+# 256 independent pruned 2D grids, n log-uniform on [1e3, 2e5], 8 right-hand sides each:
+# one batched build (one walk launch) and one batched PCG (graph-replayed iterations)
+BATCH = {"batch_256": (256, 64, 1e-3, 1e-8, 8)}  # matrices, walks/row, drop, tol, nrhs
+WORKLOADS.update({k: ("config_batch", dict(count=v[0]), v[1], v[2], v[3]) for k, v in BATCH.items()})
 
 
 def parse():
@@ -77,6 +81,9 @@ def parse():
     ap.add_argument("--reuse", action="store_true",
                     help="walk reuse (Section 5.3): the walks extracted from every walk join "
                          "the tallies of their start rows")
+    ap.add_argument("--rule", default="equal", choices=["equal", "neyman"],
+                    help="learned_128: the budget rule the network learns (equal: every row "
+                         "variance eps; neyman: least summed variance per walk step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, copy a buffer of this many MiB three times with an "
                          "elementwise kernel (known traffic, for scaling hardware byte counters)")
@@ -137,6 +144,326 @@ def cpu_baseline(A, walks, drop, seed, tol, b, two_games=False, reuse=False):
     }
 
 
+def cpu_baseline_batch(mats, seeds, walks, drop, tol, Bh, off):
+    """The batch on the CPU oracle, as it stands: every matrix's build, then every
+    (matrix, right-hand side) PCG, matrices spread over the host threads (each C call
+    releases the GIL).  Timed end to end."""
+    import threading
+
+    import oracle as O
+
+    threads = host_threads()
+    order = sorted(range(len(mats)), key=lambda i: -mats[i].n)  # largest first
+    facs = [None] * len(mats)
+    res = {}
+    lock = threading.Lock()
+    it = iter(order)
+
+    def build_worker():
+        while True:
+            with lock:
+                i = next(it, None)
+            if i is None:
+                return
+            facs[i] = O.build_factor(mats[i], walks, drop, seeds[i])
+
+    t0 = time.perf_counter()
+    pool = [threading.Thread(target=build_worker) for _ in range(threads)]
+    [t.start() for t in pool]
+    [t.join() for t in pool]
+    t1 = time.perf_counter()
+    jobs = iter([(i, j) for i in order for j in range(Bh.shape[1])])
+
+    def solve_worker():
+        while True:
+            with lock:
+                job = next(jobs, None)
+            if job is None:
+                return
+            i, j = job
+            st, x, iters, rel = O.pcg(mats[i], facs[i], Bh[off[i]:off[i + 1], j], tol)
+            res[job] = (st, iters, rel)
+
+    pool = [threading.Thread(target=solve_worker) for _ in range(threads)]
+    [t.start() for t in pool]
+    [t.join() for t in pool]
+    t2 = time.perf_counter()
+    return {
+        "value": round(t2 - t0, 3),
+        "unit": "s (oracle builds + PCG of every system to the same tolerance)",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"the whole batch: {len(mats)} matrices ({off[-1]} rows), {walks} walks per row, "
+                  f"{Bh.shape[1]} right-hand sides each; matrices and systems spread over "
+                  f"{threads} host threads",
+        "cpu_model": cpu_model(),
+        "build_s": round(t1 - t0, 3),
+        "solve_s": round(t2 - t1, 3),
+        "max_iters": max(v[1] for v in res.values()),
+        "converged": all(v[0] == 0 for v in res.values()),
+    }
+
+
+def run_batch(args):
+    """Config: 256 pruned 2D grids, 8 right-hand sides each.  One step = batched build +
+    batched PCG of all 2,048 systems to 1e-8 + free."""
+    import numpy as np
+    import torch
+
+    from paper_math_0609672_amd import metrics, srw, workloads
+
+    count, walks, drop, tol, nrhs = BATCH[args.workload]
+    if args.walks > 0:
+        walks = args.walks
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    mats = workloads.config_batch(count, seed=args.seed)
+    log(f"workload {args.workload}: {count} matrices generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    Ms = [srw.Matrix.from_host(A, dev) for A in mats]
+    seeds = [args.seed + i for i in range(count)]
+    off = np.concatenate([[0], np.cumsum([A.n for A in mats])])
+    N = int(off[-1])
+    Bh = workloads.rhs(N, nrhs=nrhs, seed=args.seed)
+    B = torch.as_tensor(Bh, device=dev)
+    X = torch.empty_like(B)
+    torch.cuda.synchronize()
+
+    def step():
+        t0 = time.perf_counter()
+        F = srw.build_factor_batched(Ms, walks, drop, seeds, precision=args.precision, profile=True)
+        t1 = time.perf_counter()
+        st, _, it, rel = srw.pcg_solve_batched(F, B, tol, 1000, X=X)
+        t2 = time.perf_counter()
+        s = F.stats()
+        F.free()
+        return dict(build_s=t1 - t0, pcg_s=t2 - t1, iters=it, rel=rel, status=st, stats=s)
+
+    for i in range(args.warmup):
+        r = step()
+        log(f"warmup {i}: build {r['build_s']:.3f} s, pcg {r['pcg_s']:.3f} s, iters <= {int(r['iters'].max())}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        runs.append(step())
+        log(f"step {i}: build {runs[-1]['build_s']:.3f} s, pcg {runs[-1]['pcg_s']:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    K = args.steps
+    s0 = runs[-1]["stats"]
+    walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in runs) / K
+    walk_bytes = 12.0 * s0["walk_steps"] + 8.0 * s0["walk_deg_sum"]
+    achieved = walk_bytes / (walk_ms * 1e-3) / 1e9
+    E = int(sum(A.nnz for A in mats))
+    C = metrics.factor_size(s0["nnz_y"], N)
+    it = runs[-1]["iters"]
+    out = {
+        "metric": METRIC,
+        "value": round(elapsed / K, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / K, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 (fp32 factor)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {count} pruned 2D grids (n log-uniform on [1e3, 2e5], "
+                        f"10% of edges removed, g U[0.1, 10], 2% grounded), N={N}, nnz={E}, "
+                        f"{nrhs} right-hand sides each, {walks} walks/row, drop {drop}, tol {tol}, "
+                        f"seed {args.seed}",
+            "global_batch": count * nrhs,
+            "parallelism": "single GPU",
+        },
+        "walk_steps_per_s": round(s0["walk_steps"] / (walk_ms * 1e-3), 1),
+        "walk_steps": s0["walk_steps"],
+        "build_s": round(sum(r["build_s"] for r in runs) / K, 4),
+        "pcg_s": round(sum(r["pcg_s"] for r in runs) / K, 4),
+        "solver": "batched pcg (graph-replayed iterations)",
+        "systems": int(it.size),
+        "pcg_iters_max": int(it.max()),
+        "pcg_iters_mean": round(float(it.mean()), 2),
+        "rel_residual_max": float(runs[-1]["rel"].max()),
+        "converged": all(r["status"] == srw.OK for r in runs),
+        "factor_C": C,
+        "C_over_N": round(C / N, 3),
+        "phase_ms": {k: round(sum(r["stats"]["phase_ms"][k] for r in runs) / K, 3) for k in srw.PHASES},
+        "roofline": {
+            "kernel": "k_walk",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "alg_bytes_per_launch": walk_bytes,
+            "avg_launch_ms": round(walk_ms, 3),
+        },
+    }
+    if not args.no_cpu:
+        log(f"cpu baseline (oracle, whole batch, {host_threads()} threads)")
+        out["cpu_baseline"] = cpu_baseline_batch(mats, seeds, walks, drop, tol, Bh, off)
+        log(f"cpu baseline: {out['cpu_baseline']['value']} s")
+    print(json.dumps(out), flush=True)
+
+
+LEARNED = {"learned_128": (128, 64, 20, 256, 1e-4, 1e-8)}  # eval m, train m, train mats, uniform walks, drop, tol
+WORKLOADS.update({k: ("config_grid3d", dict(m=v[0]), v[3], v[4], v[5]) for k, v in LEARNED.items()})
+
+
+def run_learned(args):
+    """Learned walk budgets against the plain method on the 3D grid family: the network
+    is trained on pilot factors of 20 matrices at 64^3 (library kernels: features,
+    labels, bf16 MFMA forward/backward, Adam), then serves budgets for the 128^3 matrix.
+    eps (the per-row variance target) is bisected until the learned build's PCG takes at
+    most the uniform-256 build's iterations; both are then timed end to end (features,
+    network, budgets, build, PCG, free for the learned one).  The uniform budget is the
+    fallback: the reported step is the learned pipeline only if it is faster at equal
+    iterations, and the line says which ran."""
+    import numpy as np
+    import torch
+
+    from paper_math_0609672_amd import budget as LB
+    from paper_math_0609672_amd import metrics, srw, workloads
+
+    m_eval, m_train, n_train, uni, drop, tol = LEARNED[args.workload]
+    dev = torch.device("cuda:0")
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    # training
+    t0 = time.perf_counter()
+    Xs, ys = [], []
+    for seed in range(1, n_train + 1):
+        At = workloads.config_grid3d(m_train, seed)
+        X, y = LB.pilot_rows(srw.Matrix.from_host(At, dev), seed, uni, drop, rule=args.rule)
+        Xs.append(X)
+        ys.append(y)
+    X, y = torch.cat(Xs), torch.cat(ys)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model = LB.fit(X, y, epochs=4, batch=65536, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    var_y = float(y.var())
+    loss = model.history[-1][1]
+    log(f"training: {X.shape[0]} rows from {n_train} pilot factors in {t1 - t0:.1f} s, "
+        f"fit {t2 - t1:.2f} s, loss {loss:.4f} (target variance {var_y:.4f})")
+    del X, y, Xs, ys
+
+    A = workloads.config_grid3d(m_eval, args.seed)
+    M = srw.Matrix.from_host(A, dev)
+    b = torch.as_tensor(workloads.rhs(A.n, seed=args.seed), device=dev)
+    x = torch.empty_like(b)
+
+    def run(eps=None):
+        """One end-to-end step: uniform budgets (eps None) or learned ones."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        walks = None if eps is None else LB.budgets(model, M, args.seed, eps, lo=8, hi=8192)
+        F = srw.build_factor(M, uni, drop, args.seed, walks=walks, profile=True)
+        st, _, it, rel = srw.pcg_solve(M, F, b, tol, 10000, x=x)
+        s = F.stats()
+        F.free()
+        torch.cuda.synchronize()
+        return dict(s=time.perf_counter() - t0, iters=it, rel=rel, status=st, stats=s)
+
+    run()  # warm
+    ref = run()
+    log(f"uniform {uni}: {ref['iters']} iterations, {ref['s']:.3f} s, {ref['stats']['walk_steps']:.3e} steps")
+    # bisection on log eps: the largest eps (fewest walks) whose iterations <= uniform's
+    lo, hi = np.log(1e-4), np.log(1.0)
+    best = None
+    for _ in range(10):
+        mid = 0.5 * (lo + hi)
+        r = run(float(np.exp(mid)))
+        ok = r["status"] == srw.OK and r["iters"] <= ref["iters"]
+        log(f"eps {np.exp(mid):.3e}: {r['iters']} iterations, {r['s']:.3f} s, "
+            f"{r['stats']['walk_steps']:.3e} steps{' (ok)' if ok else ''}")
+        if ok:
+            best = (float(np.exp(mid)), r)
+            lo = mid
+        else:
+            hi = mid
+    eps = best[0] if best else None
+    # timed steps: both methods, alternating
+    K = args.steps
+    learned, uniform = [], []
+    for i in range(args.warmup):
+        run(eps)
+        run()
+    for i in range(K):
+        if eps is not None:
+            learned.append(run(eps))
+        uniform.append(run())
+    t_u = float(np.median([r["s"] for r in uniform]))
+    t_l = float(np.median([r["s"] for r in learned])) if learned else float("inf")
+    use_learned = t_l < t_u
+    main = learned if use_learned else uniform
+    s0 = main[-1]["stats"]
+    walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in main) / K
+    walk_bytes = 12.0 * s0["walk_steps"] + 8.0 * s0["walk_deg_sum"]
+    achieved = walk_bytes / (walk_ms * 1e-3) / 1e9
+    C = metrics.factor_size(s0["nnz_y"], A.n)
+    out = {
+        "metric": METRIC,
+        "value": round(min(t_l, t_u), 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * min(t_l, t_u), 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (network bf16, fp32 accumulation)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: network 8-64-64-1 trained on {n_train} matrices of the 3D grid "
+                        f"family at {m_train}^3 ({args.rule} rule), evaluated at {m_eval}^3 (n={A.n}) "
+                        f"against uniform {uni} walks/row at equal PCG iterations; drop {drop}, "
+                        f"tol {tol}, seed {args.seed}",
+            "global_batch": 1,
+            "parallelism": "single GPU",
+        },
+        "ran": "learned budgets" if use_learned else "uniform budgets (fallback: the learned "
+                                                       "budgets were not faster at equal iterations)",
+        "learned_s": round(t_l, 4) if learned else None,
+        "uniform_s": round(t_u, 4),
+        "speedup_vs_plain": round(t_u / t_l, 4) if learned else None,
+        "eps": eps,
+        "pcg_iters_learned": learned[-1]["iters"] if learned else None,
+        "pcg_iters_uniform": uniform[-1]["iters"],
+        "rel_residual_learned": learned[-1]["rel"] if learned else None,
+        "rel_residual_uniform": uniform[-1]["rel"],
+        "walk_steps_learned": learned[-1]["stats"]["walk_steps"] if learned else None,
+        "walk_steps_uniform": uniform[-1]["stats"]["walk_steps"],
+        "factor_C": C,
+        "train": {"pilot_s": round(t1 - t0, 3),
+                  "fit_s": round(t2 - t1, 3), "loss": loss, "target_var": var_y},
+        "roofline": {
+            "kernel": "k_walk",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "alg_bytes_per_launch": walk_bytes,
+            "avg_launch_ms": round(walk_ms, 3),
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 WALK_SOURCES = ("paper_math_0609672_amd/csrc/walk.hpp", "paper_math_0609672_amd/csrc/common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_traffic.json")
 
@@ -172,6 +499,13 @@ def main():
         print("bench.py measures one GPU only: the walk build and PCG of this library run on a "
               "single MI355X; it has no multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload in BATCH:
+        run_batch(args)
+        return
+    if args.workload in LEARNED:
+        run_learned(args)
+        return
 
     import numpy as np
     import torch

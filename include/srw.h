@@ -108,6 +108,16 @@ typedef struct {
                                   0 = 8.  Fewer walks in flight than the chip can hold
                                   see shorter memory latency per step, which bounds
                                   the longest walks; results do not depend on it     */
+    int32_t one_step_exact;    /* 1 (default): the exact one-step treatment of
+                                  Section 5.2 (eqs. newy, newz: the first step goes
+                                  to a higher-ranked neighbour, rows without one are
+                                  exact and walk none); 0: the plain estimator of
+                                  eqs. yzdetail and d -- every row walks, every step
+                                  (the first included) follows the game, one-step
+                                  walks count, Y_ki = -H'_ki / M' and
+                                  D_k = M' A_kk / J'_k.  0 is a test mode (both reach
+                                  the same limit); it needs reuse = 0 and is refused
+                                  by the batched, two-game and adaptive entry points */
 } srw_options;
 
 void srw_default_options(srw_options* opt);
@@ -227,6 +237,14 @@ int srw_table_export(const srw_factor* F, int32_t* nbr, uint32_t* thr, uint32_t*
 int srw_tally_export(const srw_factor* F, uint32_t* walks, uint64_t* J, uint32_t* G,
                      uint64_t* steps, uint64_t* visits_sq, int64_t* h_off, int32_t* hlen,
                      int32_t* h_end, uint32_t* h_cnt, void* stream);
+
+/* Per-row statistics of the walks behind the tallies (needs keep >= 1), device float64
+ * outputs over nodes, either may be NULL: visit_var = sample variance of the stays at
+ * the start node per walk, (sum v^2 - J'^2 / M') / (M' - 1) (NaN if M' < 2), the
+ * spread behind D of eq. d; len_mean = mean walk length steps / M' (NaN if M' = 0), the
+ * quantity the stopping rule of Section 5.1 averages.  The pilot statistics from which
+ * per-row walk budgets are set. */
+int srw_walk_stats(const srw_factor* F, double* visit_var, double* len_mean, void* stream);
 
 /* Per-walk records (needs keep == 2): walk w of row k sits at rec_off[k] + w
  * (rec_off int64[n]); end int32 (-1 = ground), visits uint32, length uint32.

@@ -71,6 +71,8 @@ def lib():
         L.srwo_apply.argtypes = [i64, P, P, P, P, P, P, P, P]
         L.srwo_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, dbl, i32, P, P, P]
         L.srwo_ic0.argtypes = [i64, P, P, P, P, P, P, P, P, P]
+        L.srwo_walk_rows_plain.argtypes = [i64, P, P, P, P, P, u64, i64, P, P, P, P, P, P]
+        L.srwo_factor_plain.argtypes = [i64, P, P, P, P, P, P, P, P, P, dbl, P, P, P, P]
         _lib = L
     return _lib
 
@@ -332,6 +334,22 @@ class Factor:
         return Y
 
 
+def walk_stats(wk: Walks):
+    """Per listed row: the sample variance of the stays at the start over the row's walks
+    (NaN below two walks) and the mean walk length (NaN without walks), straight from
+    the walk records."""
+    var = np.full(wk.rows.size, np.nan)
+    mean = np.full(wk.rows.size, np.nan)
+    for r in range(wk.rows.size):
+        s = slice(wk.rec_off[r], wk.rec_off[r + 1])
+        v = wk.visits[s].astype(np.float64)
+        if v.size >= 2:
+            var[r] = np.var(v, ddof=1)
+        if v.size >= 1:
+            mean[r] = wk.length[s].astype(np.float64).mean()
+    return var, mean
+
+
 def assemble(A, rk, tb: Table, tl: Tallies, rows: np.ndarray, drop_tol: float) -> Factor:
     """Factor rows from tallies of the listed rows (all rows when rows = arange(n))."""
     n = A.n
@@ -356,9 +374,51 @@ def assemble(A, rk, tb: Table, tl: Tallies, rows: np.ndarray, drop_tol: float) -
     return Factor(n, np.asarray(rk, np.int32), yptr, ycol[:nnz], yval[:nnz], d[:n], tb)
 
 
+def walk_rows_plain(A, rk, tb: Table, seed: int, rows, budget, threads: int = 1) -> Walks:
+    """Walks of the plain estimator (eq. yzdetail, no one-step treatment): every listed
+    row runs its budget, each walk stepping by the full game from its first step."""
+    rows = _c(rows, np.int64)
+    budget = np.broadcast_to(np.asarray(budget, np.int32), rows.shape).copy()
+    rec_off = np.zeros(rows.size + 1, np.int64)
+    np.cumsum(budget, out=rec_off[1:])
+    tot = max(int(rec_off[-1]), 1)
+    end = np.zeros(tot, np.int32)
+    vis = np.zeros(tot, np.uint32)
+    ln = np.zeros(tot, np.uint32)
+    rowptr = _c(A.rowptr, np.int64)
+    rkc = _c(rk, np.int32)
+
+    def run(a, b):
+        st = lib().srwo_walk_rows_plain(A.n, _p(rowptr), _p(tb.nbr), _p(tb.thr), _p(tb.grounded),
+                                        _p(rkc), seed, b - a, _at(rows, a), _at(budget, a),
+                                        _at(rec_off, a), _p(end), _p(vis), _p(ln))
+        assert st == OK
+
+    _over_rows(rows.size, threads, run)
+    n = int(rec_off[-1])
+    return Walks(rows, budget, rec_off, end[:n], vis[:n], ln[:n])
+
+
+def assemble_plain(A, tl: Tallies, drop_tol: float, rk) -> Factor:
+    """Factor of the plain estimator from tallies over all rows (eqs. yzdetail, d)."""
+    n = A.n
+    yptr = np.zeros(n + 1, np.int64)
+    args = [n, _p(_c(A.rowptr, np.int64)), _p(_c(A.col, np.int32)), _p(_c(A.val, np.float64)),
+            _p(tl.walks), _p(tl.J), _p(tl.h_off), _p(tl.hlen), _p(tl.h_end), _p(tl.h_cnt),
+            float(drop_tol), _p(yptr)]
+    assert lib().srwo_factor_plain(*args, None, None, None) == OK
+    nnz = int(yptr[-1])
+    ycol = np.zeros(max(nnz, 1), np.int32)
+    yval = np.zeros(max(nnz, 1))
+    d = np.zeros(max(n, 1))
+    assert lib().srwo_factor_plain(*args, _p(ycol), _p(yval), _p(d)) == OK
+    return Factor(n, np.asarray(rk, np.int32), yptr, ycol[:nnz], yval[:nnz], d[:n])
+
+
 def build_factor(A, walks_per_row, drop_tol: float, seed: int, rk=None,
-                 reuse: bool = False, threads: int = 1) -> Factor:
-    """The whole preconditioning phase of Algorithm 1 on the CPU.  `walks_per_row` is
+                 reuse: bool = False, threads: int = 1, one_step_exact: bool = True) -> Factor:
+    """The whole preconditioning phase of Algorithm 1 on the CPU (one_step_exact=False:
+    the plain estimator of eqs. yzdetail and d, every step random).  `walks_per_row` is
     an int (uniform) or an int array over nodes (per-row budgets, each >= 1).  With
     reuse, every walk also contributes the walks Algorithm "reuse" extracts from it
     (Section 5.3) to the tallies of their start nodes.  threads > 1 runs the rows'
@@ -367,6 +427,13 @@ def build_factor(A, walks_per_row, drop_tol: float, seed: int, rk=None,
     rk = rank(A.n, seed) if rk is None else np.asarray(rk, np.int32)
     tb = table(A, rk)
     rows = np.arange(A.n, dtype=np.int64)
+    if not one_step_exact:  # the plain estimator of eqs. yzdetail and d
+        assert not reuse
+        wk = walk_rows_plain(A, rk, tb, seed, rows, walks_per_row, threads=threads)
+        tl = tally(wk, threads=threads)
+        F = assemble_plain(A, tl, drop_tol, rk)
+        F.table, F.walks, F.tallies = tb, wk, tl
+        return F
     if reuse:
         wk = records_to_walks(A.n, walk_rows_reuse(A, rk, tb, seed, rows, walks_per_row))
     else:

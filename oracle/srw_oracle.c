@@ -1089,3 +1089,92 @@ int srwo_ic0(int64_t n, const int64_t* rowptr, const int32_t* col, const double*
     }
     return SRWO_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* The plain estimator: eq. yzdetail with eq. d, without the exact one-step  */
+/* treatment of Section 5.2 (a test mode: both must reach the same limit).   */
+/* ------------------------------------------------------------------------- */
+
+/* Walk w of row k by the full game of Section 2.1 from its first step on: every step,
+ * the first included, leaves the current node by its thresholds (ground when the row
+ * is grounded and u passes every threshold); the walk ends at ground or at the first
+ * node ranked below k, after one step if the first step already gets there.  Draw t
+ * (t = 0 for the first step) is srwo_draw(seed, k, w, t).  visits counts the stays at
+ * k, the start included; length is the number of steps. */
+void srwo_walk_plain(int64_t n, const int64_t* rowptr, const int32_t* nbr, const uint32_t* thr,
+                     const unsigned char* grounded, const int32_t* rank, uint64_t seed,
+                     int64_t k, int64_t w, int32_t* end_out, uint32_t* visits_out,
+                     uint32_t* length_out)
+{
+    (void)n;
+    int64_t cur = k;
+    uint32_t visits = 1;
+    for (uint64_t t = 0;; t++) {
+        uint32_t u = srwo_draw(seed, k, w, t);
+        int64_t base = rowptr[cur] - cur;
+        int64_t deg = rowptr[cur + 1] - rowptr[cur] - 1;
+        int64_t next = -2;
+        for (int64_t m = 0; m < deg; m++)
+            if (u < thr[base + m]) { next = nbr[base + m]; break; }
+        if (next == -2) next = grounded[cur] ? -1 : nbr[base + deg - 1];
+        if (next == -1) {
+            *end_out = -1; *visits_out = visits; *length_out = (uint32_t)(t + 1);
+            return;
+        }
+        if (rank[next] < rank[k]) {
+            *end_out = (int32_t)next; *visits_out = visits; *length_out = (uint32_t)(t + 1);
+            return;
+        }
+        if (next == k) visits++;
+        cur = next;
+    }
+}
+
+/* srwo_walk_rows for the plain estimator: every listed row runs budget[r] walks. */
+int srwo_walk_rows_plain(int64_t n, const int64_t* rowptr, const int32_t* nbr,
+                         const uint32_t* thr, const unsigned char* grounded, const int32_t* rank,
+                         uint64_t seed, int64_t nrows, const int64_t* rows, const int32_t* budget,
+                         const int64_t* rec_off, int32_t* end, uint32_t* visits, uint32_t* length)
+{
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t k = rows[r];
+        if (k < 0 || k >= n) return SRWO_E_ARG;
+        for (int64_t w = 0; w < budget[r]; w++)
+            srwo_walk_plain(n, rowptr, nbr, thr, grounded, rank, seed, k, w,
+                            &end[rec_off[r] + w], &visits[rec_off[r] + w], &length[rec_off[r] + w]);
+    }
+    return SRWO_OK;
+}
+
+/* Factor rows of the plain estimator from the tallies of its walks (M = walks[k] > 0
+ * for every row): eq. yzdetail gives Y_ki = -H'_{k,i} / M for every end node i, and
+ * eq. d gives D_k = M A_kk / J'_k (J' counts the start).  Entries with
+ * |Y_ki| < drop_tol are dropped; ascending column id.  Two calls as srwo_factor. */
+int srwo_factor_plain(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                      const uint32_t* walks, const uint64_t* J, const int64_t* h_off,
+                      const int32_t* hlen, const int32_t* h_end, const uint32_t* h_cnt,
+                      double drop_tol, int64_t* yptr, int32_t* ycol, double* yval, double* d)
+{
+    if (!ycol) yptr[0] = 0;
+    for (int64_t k = 0; k < n; k++) {
+        double a = 0.0;
+        for (int64_t p = rowptr[k]; p < rowptr[k + 1]; p++)
+            if (col[p] == k) a = val[p];
+        uint32_t M = walks[k];
+        if (M == 0) return SRWO_E_ARG;
+        int64_t kept = 0;
+        for (int32_t h = 0; h < hlen[k]; h++) {
+            double y = -((double)h_cnt[h_off[k] + h] / (double)M);
+            if (!(fabs(y) < drop_tol)) {
+                if (ycol) {
+                    ycol[yptr[k] + kept] = h_end[h_off[k] + h];
+                    yval[yptr[k] + kept] = y;
+                }
+                kept++;
+            }
+        }
+        if (!ycol) yptr[k + 1] = yptr[k] + kept;
+        else d[k] = ((double)M * a) / (double)J[k];
+    }
+    return SRWO_OK;
+}

@@ -315,9 +315,20 @@ __global__ void k_zero_u64(unsigned long long* a, int n)
     if ((int)threadIdx.x < n) a[threadIdx.x] = 0ull;
 }
 
+// A row of the multi-right-hand-side solves takes RG lanes: a wave solves 64 / RG rows
+// at a time (the batch's rows are short, about nine entries), each lane summing the
+// entries j, j + RG, ... of its row over all right-hand sides, the RG partial sums then
+// added by a butterfly within the row's lanes.  A wave claims `chunk` consecutive slots
+// (a multiple of 64 / RG) and solves them 64 / RG at a time, in order; within a round
+// the rows wait and finish independently (a row may wait for another row of the same
+// round).  A lane polls the values it is missing itself.
+//
 // wait_ticks: wall-clock ticks (constant-rate counter) after which a wait gives up --
 // a guard against a defect, far above any legitimate wait (a claimed slot waits at
 // most for the slots claimed before it).
+constexpr int RG = 8;
+constexpr int RPW = 64 / RG;  // rows of a wave in flight
+
 template <typename T, bool FWD>
 __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs, int32_t chunk,
                                                       const int64_t* __restrict__ ptr,
@@ -332,6 +343,7 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs, int32
 {
     using U = typename MBits<T>::U;
     const int lane = threadIdx.x & 63;
+    const int grp = lane / RG, j = lane % RG;
     for (;;) {
         // every lane executes the atomic (lane 0 adds the chunk) and the claim is read
         // from lane 0 as a scalar, so the loop exit below is a uniform branch
@@ -339,90 +351,94 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs, int32
             lane0_u64(atomicAdd(claim, lane == 0 ? (unsigned long long)chunk : 0ull));
         if (base >= (uint64_t)n) break;
         const int64_t stop = std::min<int64_t>((int64_t)base + chunk, n);
-        for (int64_t i = (int64_t)base; i < stop; ++i) {
-            const int64_t s = FWD ? i : n - 1 - i;
-            const int64_t q0 = ptr[s], q1 = ptr[s + 1];
+        for (int64_t r0 = (int64_t)base; r0 < stop; r0 += RPW) {
+            const int64_t i = r0 + grp;
+            bool done = i >= stop;
+            const int64_t s = done ? 0 : (FWD ? i : n - 1 - i);
+            int64_t qc = done ? 0 : ptr[s];
+            const int64_t q1 = done ? 0 : ptr[s + 1];
             T acc[MAXR];
 #pragma unroll
-            for (int j = 0; j < MAXR; ++j) acc[j] = T(0);
-            for (int64_t qb = q0; qb < q1; qb += 64) {
-                const int64_t q = qb + lane;
-                const bool ok = q < q1;
-                const int32_t c = ok ? col[q] : 0;
-                const T a = ok ? val[q] : T(0);
-                const U* src = (const U*)sol + (int64_t)c * nrhs;
-                U bits[MAXR];
-                bool miss_mine = false;
+            for (int jr = 0; jr < MAXR; ++jr) acc[jr] = T(0);
+            U bits[MAXR];
+            T a = T(0);
+            int32_t c = 0;
+            bool loaded = false;
+            uint32_t spins = 0;
+            const int64_t t0 = wall_clock64();
+            while (ballot(!done) != 0) {
+                const bool ok = !done && qc + j < q1;
+                if (!done && !loaded) {
+                    c = ok ? col[qc + j] : 0;
+                    a = ok ? val[qc + j] : T(0);
+                    const U* src = (const U*)sol + (int64_t)c * nrhs;
 #pragma unroll
-                for (int j = 0; j < MAXR; ++j) {
-                    bits[j] = (ok && j < nrhs) ? mload(src + j) : U(0);
-                    miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
+                    for (int jr = 0; jr < MAXR; ++jr)
+                        bits[jr] = (ok && jr < nrhs) ? mload(src + jr) : U(0);
+                    loaded = true;
                 }
-                uint64_t miss = ballot(miss_mine);
-                uint32_t spins = 0;
-                const int64_t t0 = miss ? wall_clock64() : 0;
-                while (miss != 0) {
+                bool miss = false;
+#pragma unroll
+                for (int jr = 0; jr < MAXR; ++jr)
+                    miss = miss || (ok && jr < nrhs && bits[jr] == MBits<T>::sentinel);
+                const uint64_t mb = ballot(miss);
+                const bool gmiss = ((mb >> (grp * RG)) & ((1ull << RG) - 1)) != 0;
+                bool finishing = false;
+                if (!done && !gmiss) {  // the row's current entries are all there
+#pragma unroll
+                    for (int jr = 0; jr < MAXR; ++jr) acc[jr] += a * __builtin_bit_cast(T, bits[jr]);
+                    qc += RG;
+                    loaded = false;
+                    finishing = qc >= q1;
+                }
+                if (ballot(finishing) != 0) {
+                    const int32_t node = finishing ? slot_node[s] : 0;
+                    const T dv = (FWD && finishing) ? dslot[s] : T(1);
+#pragma unroll
+                    for (int jr = 0; jr < MAXR; ++jr) {
+                        T v = acc[jr];
+                        v += __shfl_xor(v, 4, 64);
+                        v += __shfl_xor(v, 2, 64);
+                        v += __shfl_xor(v, 1, 64);
+                        if (finishing && j == 0 && jr < nrhs) {
+                            const T base_v = FWD ? w[s * nrhs + jr] / dv : (T)rhs[(int64_t)node * nrhs + jr];
+                            const T x = base_v - v;
+                            __hip_atomic_store((U*)sol + s * nrhs + jr, __builtin_bit_cast(U, x),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if (out) out[(int64_t)node * nrhs + jr] = (double)x;
+                        }
+                    }
+                    if (finishing) done = true;
+                }
+                if (!done && gmiss) {
                     // every 256 polls: give up past the time limit, or at once when
                     // another wave already gave up (a failed solve then drains)
-                    bool give_up = false, failed = false;
                     if ((++spins & 255u) == 0) {
-                        failed = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-                        give_up = failed || wall_clock64() - t0 > wait_ticks;
-                    }
-                    if (give_up) {
-                        // the slot this wave waited for (every lane takes part in the max)
-                        const bool mine_d = (miss >> lane) & 1ull;
-                        const int key_d = wave_max_i(mine_d ? (FWD ? c : -c) : INT_MIN);
-                        const int32_t lead_d = FWD ? key_d : -key_d;
-                        if (lane == 0) {
-                            atomicOr(err, 1);
-                            // the first wave to reach the limit records where it waited:
-                            // err[2..6] = direction, slot, awaited slot, awaited value
-                            // still absent, chunk
-                            if (!failed && atomicCAS(err + 1, 0, 1) == 0) {
-                                err[2] = FWD ? 1 : 0;
-                                err[3] = (int)s;
-                                err[4] = lead_d;
-                                err[5] = mload((const U*)sol + (int64_t)lead_d * nrhs + (nrhs - 1)) ==
-                                         MBits<T>::sentinel;
-                                err[6] = chunk;
+                        const bool failed =
+                            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                        if (failed || wall_clock64() - t0 > wait_ticks) {
+                            if (j == 0) {
+                                atomicOr(err, 1);
+                                // the first to give up records where it waited: err[2..6] =
+                                // direction, slot, awaited slot, value absent, chunk
+                                if (!failed && atomicCAS(err + 1, 0, 1) == 0) {
+                                    err[2] = FWD ? 1 : 0;
+                                    err[3] = (int)s;
+                                    err[4] = c;
+                                    err[5] = 1;
+                                    err[6] = chunk;
+                                }
                             }
+#pragma unroll
+                            for (int jr = 0; jr < MAXR; ++jr)
+                                if (bits[jr] == MBits<T>::sentinel) bits[jr] = MBits<T>::nan_bits();
                         }
-#pragma unroll
-                        for (int j = 0; j < MAXR; ++j)
-                            if (bits[j] == MBits<T>::sentinel) bits[j] = MBits<T>::nan_bits();
-                        break;
                     }
-                    const bool mine = (miss >> lane) & 1ull;
-                    const int key = wave_max_i(mine ? (FWD ? c : -c) : INT_MIN);
-                    const int32_t lead = FWD ? key : -key;
-                    const U lb = mload((const U*)sol + (int64_t)lead * nrhs + (nrhs - 1));
-                    if (lb == MBits<T>::sentinel) {
-                        __builtin_amdgcn_s_sleep(2);
-                        continue;
-                    }
-                    miss_mine = false;
+                    __builtin_amdgcn_s_sleep(2);
+                    const U* src = (const U*)sol + (int64_t)c * nrhs;
 #pragma unroll
-                    for (int j = 0; j < MAXR; ++j) {
-                        if (mine && j < nrhs && bits[j] == MBits<T>::sentinel) bits[j] = mload(src + j);
-                        miss_mine = miss_mine || (ok && j < nrhs && bits[j] == MBits<T>::sentinel);
-                    }
-                    miss = ballot(miss_mine);
-                }
-#pragma unroll
-                for (int j = 0; j < MAXR; ++j) acc[j] += a * __builtin_bit_cast(T, bits[j]);
-            }
-            const int32_t node = slot_node[s];
-#pragma unroll
-            for (int j = 0; j < MAXR; ++j) {
-                if (j >= nrhs) continue;
-                const T sum = wave_sum(acc[j]);
-                if (lane == 0) {
-                    const T base_v = FWD ? w[s * nrhs + j] / dslot[s] : (T)rhs[(int64_t)node * nrhs + j];
-                    const T x = base_v - sum;
-                    __hip_atomic_store((U*)sol + s * nrhs + j, __builtin_bit_cast(U, x),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (out) out[(int64_t)node * nrhs + j] = (double)x;
+                    for (int jr = 0; jr < MAXR; ++jr)
+                        if (ok && jr < nrhs && bits[jr] == MBits<T>::sentinel) bits[jr] = mload(src + jr);
                 }
             }
         }
@@ -755,13 +771,13 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     Sched sched = tuned_schedule(key);
     if (e == hipSuccess && sched.per_cu == 0) {
         float best = 1e30f;
-        Sched best_s{8, 16};
+        Sched best_s{8, RPW * 16};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
         CK(apply_b(F, W, best_s, s));  // warm
         for (int cap : {8, 4, 2}) {
-            for (int chunk : {4, 16, 64}) {
+            for (int chunk : {RPW * 4, RPW * 16, RPW * 64}) {
                 if (e != hipSuccess) break;
                 const Sched cand{cap, chunk};
                 CK(hipEventRecord(e0, s));

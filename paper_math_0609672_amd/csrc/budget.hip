@@ -476,6 +476,35 @@ int features_impl(const srw_csr* A, const int32_t* rank, float* feat, hipStream_
     return SRW_OK;
 }
 
+// Per-row walk statistics from the tallies (Section 3.1 counts): the sample variance of
+// the stays at the start, (sum v^2 - J'^2 / M') / (M' - 1), and the mean walk length
+// steps / M'.  NaN where a row has too few walks (M' < 2 for the variance, M' = 0 for
+// the mean).
+__global__ void k_walk_stats(int64_t n, const int32_t* __restrict__ budget,
+                             const uint64_t* __restrict__ J, const uint64_t* __restrict__ vsq,
+                             const uint64_t* __restrict__ steps, double* __restrict__ var,
+                             double* __restrict__ mean_len)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double M = (double)budget[k];
+    if (var) {
+        const double j = (double)J[k];
+        var[k] = budget[k] >= 2 ? ((double)vsq[k] - (j * j) / M) / (M - 1.0) : __builtin_nan("");
+    }
+    if (mean_len) mean_len[k] = budget[k] >= 1 ? (double)steps[k] / M : __builtin_nan("");
+}
+
+int walk_stats_impl(const srw_factor* F, double* var, double* mean_len, hipStream_t s)
+{
+    if (F->n == 0) return SRW_OK;
+    k_walk_stats<<<grid_for(F->n, BLOCK), BLOCK, 0, s>>>(F->n, F->budget, F->tJ, F->tvsq, F->tsteps,
+                                                       var, mean_len);
+    SRW_HIP(hipGetLastError());
+    SRW_HIP(hipStreamSynchronize(s));
+    return SRW_OK;
+}
+
 int labels_impl(const srw_factor* F, int per_step, double* label, hipStream_t s)
 {
     if (F->n == 0) return SRW_OK;

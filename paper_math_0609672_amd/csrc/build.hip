@@ -705,7 +705,7 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
                          const int32_t* __restrict__ budget, const uint64_t* __restrict__ J,
                          const int64_t* __restrict__ h_off, const int32_t* __restrict__ hlen,
                          const uint32_t* __restrict__ h_end, const uint32_t* __restrict__ h_cnt,
-                         double drop_tol, int32_t* __restrict__ ynnz,
+                         double drop_tol, int32_t plain, int32_t* __restrict__ ynnz,
                          const int64_t* __restrict__ yptr, int32_t* __restrict__ ycol,
                          T* __restrict__ yval, T* __restrict__ dout)
 {
@@ -725,6 +725,22 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
     int32_t h = 0;
     int64_t kept = 0;
     const int64_t out0 = FILL ? yptr[k] : 0;
+    if (plain) {
+        // eq. yzdetail: Y_ki = -H'_ki / M' for every end node i; eq. d: D = M' a / J'
+        for (; h < H; ++h) {
+            const double y = -((double)h_cnt[hb + h] / (double)M);
+            if (!(fabs(y) < drop_tol)) {
+                if (FILL) {
+                    ycol[out0 + kept] = (int32_t)h_end[hb + h];
+                    yval[out0 + kept] = (T)y;
+                }
+                ++kept;
+            }
+        }
+        if (FILL) dout[k] = (T)(((double)M * a) / (double)J[k]);
+        else ynnz[k] = (int32_t)kept;
+        return;
+    }
     for (;;) {
         while (p < r1 && (col[p] == k || rank[col[p]] > rk)) ++p;
         const uint32_t ci = p < r1 ? (uint32_t)col[p] : 0xFFFFFFFFu;
@@ -1208,7 +1224,11 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (reuse || batch || rule || asym || opt.factor_precision != SRW_FP64) return SRW_E_ARG;
         walks_per_row = NO_WALKS;
         drop_tol = 0.0;
+        opt.one_step_exact = 1;
     }
+    // the plain estimator of eqs. yzdetail and d: every row walks from its own record
+    const bool plain = opt.one_step_exact == 0;
+    if (plain && (reuse || batch || rule || asym)) return SRW_E_ARG;
     const int64_t n = A->n, nnz = A->nnz;
     const int64_t nnz_off = nnz - n;
 
@@ -1360,8 +1380,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         mark(2);
         CHECK_HIP(hipMemsetAsync(maxb, 0, sizeof(int32_t), s));
         k_table<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, grounded, walks_per_row,
-                                    opt.walks, rline, n_lines, (uint32_t*)recs, ent, mthr, tau,
-                                    budget, maxb);
+                                    opt.walks, plain ? 1 : 0, rline, n_lines, (uint32_t*)recs, ent,
+                                    mthr, tau, budget, maxb);
         CHECK_HIP(hipGetLastError());
 
         // record offsets (node order) and the segmented chunk list
@@ -1420,8 +1440,10 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         ChunkDesc* cdesc = ALLOC(tmp, ChunkDesc, n_chunks);
         if (!cdesc) FAIL(SRW_E_NOMEM);
         k_set_last<<<1, 1, 0, s>>>(chunk_off, norder, n_chunks);
+        // a walk's first step reads the row's start record (higher-ranked neighbours
+        // only), or for the plain estimator the row's own record
         k_chunks<<<grid_for(norder, BLOCK), BLOCK, 0, s>>>(
-            norder, nlong, order, chunk_off, budget, rline, n_lines, F->rank, rec_off, seed,
+            norder, nlong, order, chunk_off, budget, rline, plain ? 0 : n_lines, F->rank, rec_off, seed,
             batch ? batch->node_mat : nullptr, batch ? batch->mat_off : nullptr,
             batch ? batch->mat_seed : nullptr, cdesc);
         k_seg_bounds<<<1, 1, 0, s>>>(n, nlong, nslab_rows, pos2, chunk_off, bounds);
@@ -1636,8 +1658,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         mark(6);
         k_factor<double, false><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
                                                     budget, tJ, h_off, hlen, h_end, h_cnt,
-                                                    drop_tol, ynnz, nullptr, nullptr, nullptr,
-                                                    nullptr);
+                                                    drop_tol, plain ? 1 : 0, ynnz, nullptr,
+                                                    nullptr, nullptr, nullptr);
         CHECK_HIP(exclusive_scan_i32_to_i64(ynnz, F->yptr, n, st, s));
         k_read_last<<<1, 1, 0, s>>>(F->yptr, ynnz, n, tot + 0);
         CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1654,13 +1676,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (fp32)
             k_factor<float, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
                                                      budget, tJ, h_off, hlen, h_end, h_cnt,
-                                                     drop_tol, nullptr, F->yptr, F->ycol,
-                                                     (float*)F->yval, (float*)F->d);
+                                                     drop_tol, plain ? 1 : 0, nullptr, F->yptr,
+                                                     F->ycol, (float*)F->yval, (float*)F->d);
         else
             k_factor<double, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
                                                       budget, tJ, h_off, hlen, h_end, h_cnt,
-                                                      drop_tol, nullptr, F->yptr, F->ycol,
-                                                      (double*)F->yval, (double*)F->d);
+                                                      drop_tol, plain ? 1 : 0, nullptr, F->yptr,
+                                                      F->ycol, (double*)F->yval, (double*)F->d);
         CHECK_HIP(hipGetLastError());
 
         if (ic0 && n > 0) {

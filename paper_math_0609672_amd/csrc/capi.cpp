@@ -41,6 +41,8 @@ int options_ok(const srw_options* opt, int64_t n)
     if (opt->reuse != 0 && opt->reuse != 1) return SRW_E_ARG;
     if (opt->reuse && (opt->keep == 2 || (rp != 0 && rp != 8))) return SRW_E_ARG;
     if (opt->walk_waves != 0 && (opt->walk_waves < 4 || opt->walk_waves > 64)) return SRW_E_ARG;
+    if (opt->one_step_exact != 0 && opt->one_step_exact != 1) return SRW_E_ARG;
+    if (!opt->one_step_exact && opt->reuse) return SRW_E_ARG;
     return SRW_OK;
 }
 
@@ -63,6 +65,7 @@ void srw_default_options(srw_options* opt)
     opt->solve_order = 2;
     opt->reuse = 0;
     opt->walk_waves = 0;
+    opt->one_step_exact = 1;
 }
 
 
@@ -82,6 +85,7 @@ int srw_build_factor_batched(int32_t nmat, const srw_csr* A, int32_t walks_per_r
     if (!(drop_tol >= 0.0) || !std::isfinite(drop_tol)) return SRW_E_ARG;
     if (options_ok(opt, total) != SRW_OK) return SRW_E_ARG;
     if (opt && opt->ordering != SRW_ORDER_RANDOM) return SRW_E_ARG;  // one ordering per matrix
+    if (opt && !opt->one_step_exact) return SRW_E_ARG;                // the plain estimator: single builds
     if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
     if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
     srw_options o;
@@ -176,6 +180,7 @@ int srw_build_factor_ldu(const srw_csr* A, int32_t walks_per_row, double drop_to
     if (!csr_ok(A)) return SRW_E_ARG;
     if (!(drop_tol >= 0.0) || !std::isfinite(drop_tol)) return SRW_E_ARG;
     if (options_ok(opt, A->n) != SRW_OK) return SRW_E_ARG;
+    if (opt && !opt->one_step_exact) return SRW_E_ARG;  // the plain estimator: single builds
     if ((!opt || !opt->walks) && walks_per_row < 1) return SRW_E_ARG;
     if (walks_per_row > 8192 || walks_per_row < 0) return SRW_E_ARG;
     try {
@@ -382,6 +387,7 @@ int srw_adaptive_budgets(const srw_csr* A, uint64_t seed, const srw_options* opt
     if (!(delta > 0.0) || !std::isfinite(delta) || !(z > 0.0) || !std::isfinite(z)) return SRW_E_ARG;
     if (min_walks < 2 || max_walks < min_walks || max_walks > 8192) return SRW_E_ARG;
     if (options_ok(opt, A->n) != SRW_OK) return SRW_E_ARG;
+    if (opt && !opt->one_step_exact) return SRW_E_ARG;  // the Section 5.1 rule runs the exact-one-step walks
     srw_options o;
     srw_default_options(&o);
     if (opt) o = *opt;
@@ -413,6 +419,12 @@ int srw_budget_labels(const srw_factor* F, int32_t per_step, double* label, void
     if (!F || F->keep < 1 || (per_step != 0 && per_step != 1)) return SRW_E_ARG;
     if (F->n > 0 && !label) return SRW_E_ARG;
     return srw::labels_impl(F, per_step, label, as_stream(stream));
+}
+
+int srw_walk_stats(const srw_factor* F, double* visit_var, double* len_mean, void* stream)
+{
+    if (!F || F->keep < 1) return SRW_E_ARG;
+    return srw::walk_stats_impl(F, visit_var, len_mean, as_stream(stream));
 }
 
 int srw_mlp_forward(const float* params, const float* mu_sd, const float* features, int64_t n,

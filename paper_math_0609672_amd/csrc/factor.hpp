@@ -193,6 +193,7 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
                      double* X, int32_t* iters, double* rel, int32_t use_graph, hipStream_t s);
 int features_impl(const srw_csr* A, const int32_t* rank, float* feat, hipStream_t s);
 int labels_impl(const srw_factor* F, int per_step, double* label, hipStream_t s);
+int walk_stats_impl(const srw_factor* F, double* var, double* mean_len, hipStream_t s);
 int mlp_forward_impl(const float* P, const float* musd, const float* feat, int64_t n, float* out,
                      hipStream_t s);
 int mlp_train_impl(float* P, float* m, float* v, int32_t step, float lr, const float* musd,

@@ -49,7 +49,7 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
                         const int32_t* __restrict__ col, const double* __restrict__ val,
                         const int32_t* __restrict__ rank, const uint8_t* __restrict__ grounded,
                         int32_t walks_per_row, const int32_t* __restrict__ budget_in,
-                        const int64_t* __restrict__ rline, int64_t n_lines,
+                        int32_t plain, const int64_t* __restrict__ rline, int64_t n_lines,
                         uint32_t* __restrict__ recs, uint2* __restrict__ ent,
                         uint32_t* __restrict__ mthr, double* __restrict__ tau,
                         int32_t* __restrict__ budget, int32_t* max_budget)
@@ -117,7 +117,9 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
     }
     tau[v] = motel / a;
     int32_t b = 0;
-    if (motel > 0.0 && walks_per_row != NO_WALKS) {
+    // walking rows: those with a higher-ranked neighbour (the others are exact), or
+    // every row for the plain estimator
+    if ((motel > 0.0 || plain) && walks_per_row != NO_WALKS) {
         b = budget_in ? budget_in[v] : walks_per_row;
         if (b < 1) b = 1;
         atomicMax(max_budget, b);
@@ -139,10 +141,11 @@ struct ChunkDesc {
 static_assert(sizeof(ChunkDesc) == 32, "chunk descriptors are 32 bytes");
 
 // chunk descriptors of the rows in schedule order: consecutive walks of a row, SRW_WAVE
-// per chunk for the first nlong rows, CHUNK_WALKS for the others
+// per chunk for the first nlong rows, CHUNK_WALKS for the others; a walk starts from
+// line sline_base + rline[v] (the start records, or 0: the rows' own records)
 __global__ void k_chunks(int64_t norder, int64_t nlong, const int32_t* __restrict__ order,
                          const int64_t* __restrict__ chunk_off, const int32_t* __restrict__ budget,
-                         const int64_t* __restrict__ rline, int64_t n_lines,
+                         const int64_t* __restrict__ rline, int64_t sline_base,
                          const int32_t* __restrict__ rank, const int64_t* __restrict__ rec_off,
                          uint64_t seed, const int32_t* __restrict__ node_mat,
                          const int64_t* __restrict__ mat_off, const uint64_t* __restrict__ mat_seed,
@@ -160,7 +163,7 @@ __global__ void k_chunks(int64_t norder, int64_t nlong, const int32_t* __restric
         d.key = (uint32_t)(v - mat_off[mi]);
         d.seed = mat_seed[mi];
     }
-    d.sline = (uint32_t)(n_lines + rline[v]);
+    d.sline = (uint32_t)(sline_base + rline[v]);
     d.rank = (uint32_t)rank[v];
     d.rec = (uint64_t)rec_off[v];
     for (int64_t c = chunk_off[j]; c < chunk_off[j + 1]; ++c) {

@@ -40,7 +40,7 @@ class _Options(ctypes.Structure):
                 ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("solve_order", ctypes.c_int32), ("reuse", ctypes.c_int32),
-                ("walk_waves", ctypes.c_int32)]
+                ("walk_waves", ctypes.c_int32), ("one_step_exact", ctypes.c_int32)]
 
 
 NUM_PHASES = 8
@@ -83,6 +83,7 @@ _lib.srw_adaptive_budgets.argtypes = [ctypes.POINTER(_Csr), _U64, ctypes.POINTER
                                       _I32, _I32, _P, _P]
 _lib.srw_row_features.argtypes = [ctypes.POINTER(_Csr), _P, _P, _P]
 _lib.srw_budget_labels.argtypes = [_P, _I32, _P, _P]
+_lib.srw_walk_stats.argtypes = [_P, _P, _P, _P]
 _lib.srw_mlp_forward.argtypes = [_P, _P, _P, _I64, _P, _P]
 _lib.srw_mlp_train_step.argtypes = [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _I64, _P, _P, _P]
 _lib.srw_mlp_budgets.argtypes = [_P, _I64, _D, _I32, _I32, _P, _P]
@@ -103,7 +104,7 @@ _lib.srw_status_string.restype = ctypes.c_char_p
 EXPORTED = ["srw_default_options", "srw_build_factor", "srw_build_ic0", "srw_factor_free", "srw_factor_info",
             "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
-            "srw_pcg_solve", "srw_apply", "srw_apply_noalloc", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
+            "srw_pcg_solve", "srw_apply", "srw_apply_noalloc", "srw_walk_stats", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
             "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_budgets", "srw_build_factor_batched",
             "srw_batch_info", "srw_pcg_solve_batched", "srw_last_error", "srw_status_string"]
 
@@ -265,11 +266,13 @@ def _check(st: int, what: str):
 def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, rank=None, walks=None,
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
                  profile: bool = False, schedule: int = 1, solve_order: int = 2,
-                 reuse: bool = False, walk_waves: int = 0, stream=None) -> Factor:
+                 reuse: bool = False, walk_waves: int = 0, one_step_exact: bool = True,
+                 stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A (with reuse, the
-    walks extracted by Algorithm "reuse" of Section 5.3 join the tallies)."""
+    walks extracted by Algorithm "reuse" of Section 5.3 join the tallies; with
+    one_step_exact=False, the plain estimator of eqs. yzdetail and d)."""
     opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-                   solve_order, reuse, walk_waves)
+                   solve_order, reuse, walk_waves, one_step_exact)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),
@@ -326,7 +329,7 @@ def bicgstab_solve(A: Matrix, F, b: torch.Tensor, tol: float, max_iter: int = 10
 
 
 def _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-             solve_order, reuse, walk_waves=0) -> _Options:
+             solve_order, reuse, walk_waves=0, one_step_exact=True) -> _Options:
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
     if isinstance(rank, str):
@@ -347,6 +350,7 @@ def _options(rank, walks, precision, max_steps, keep, refill_period, profile, sc
     opt.solve_order = int(solve_order)
     opt.reuse = 1 if reuse else 0
     opt.walk_waves = int(walk_waves)
+    opt.one_step_exact = 1 if one_step_exact else 0
     return opt
 
 
@@ -421,6 +425,16 @@ def row_features(A: Matrix, rank: torch.Tensor, stream=None) -> torch.Tensor:
     _check(_lib.srw_row_features(ctypes.byref(csr), _ptr(rank), _ptr(f), _stream(stream)),
            "srw_row_features")
     return f
+
+
+def walk_stats(F: Factor, stream=None):
+    """srw_walk_stats: (visit variance, mean walk length) per row, float64 device
+    tensors (the factor must be built with keep >= 1)."""
+    n = F.info()["n"]
+    var = torch.empty(n, dtype=torch.float64, device=F.device)
+    mean = torch.empty(n, dtype=torch.float64, device=F.device)
+    _check(_lib.srw_walk_stats(F.handle, _ptr(var), _ptr(mean), _stream(stream)), "srw_walk_stats")
+    return var, mean
 
 
 def budget_labels(F: Factor, per_step: bool = False, stream=None) -> torch.Tensor:

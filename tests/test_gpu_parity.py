@@ -347,6 +347,60 @@ def test_per_row_budget_above_limit_is_refused(srw, reuse):
     F.free()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_plain_estimator_bit_exact(srw, name):
+    # one_step_exact = 0: eq. yzdetail with eq. d, every step random, one-step walks
+    # counted; every row walks
+    A, walks = CASES[name]
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, 1e-3, 21, keep=2, one_step_exact=False)
+    ref = O.build_factor(A, walks, 1e-3, 21, one_step_exact=False)
+    rec = F.records()
+    off = np_(rec["rec_off"])
+    assert np.array_equal(off, ref.walks.rec_off[:-1])
+    assert np.array_equal(np_(rec["end"]), ref.walks.end)
+    assert np.array_equal(np_(rec["visits"]).view(np.uint32), ref.walks.visits)
+    assert np.array_equal(np_(rec["length"]).view(np.uint32), ref.walks.length)
+    tl = F.tallies()
+    assert np.array_equal(np_(tl["walks"]).view(np.uint32), ref.tallies.walks)
+    assert np.array_equal(np_(tl["J"]).view(np.uint64), ref.tallies.J)
+    got = {k: np_(v) for k, v in F.export().items()}
+    for k in ("yptr", "ycol", "yval", "d"):
+        assert np.array_equal(got[k], getattr(ref, k)), k
+    b = W.rhs(A.n, seed=3)
+    st, x, it, rel = srw.pcg_solve(M, F, torch.as_tensor(b, device=DEV), 1e-8)
+    st_o, x_o, it_o, _ = O.pcg(A, ref, b, 1e-8)
+    assert st == st_o == 0 and it == it_o
+    assert np.linalg.norm(np_(x) - x_o) <= 1e-10 * np.linalg.norm(x_o)
+    F.free()
+
+
+@pytest.mark.parametrize("name", ["grid3d_12", "random_3000"])
+def test_walk_stats_match_the_records(srw, name):
+    # sample variance of the stays and mean length per row, from the tallies on the GPU,
+    # against numpy over the oracle's walk records of the same rows
+    A, walks = CASES[name]
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, 1e-3, 5, keep=1)
+    var, mean = (np_(t) for t in srw.walk_stats(F))
+    ref = O.build_factor(A, walks, 1e-3, 5)
+    rv, rm = O.walk_stats(ref.walks)
+    assert np.array_equal(np.isnan(var), np.isnan(rv)) and np.array_equal(np.isnan(mean), np.isnan(rm))
+    ok = ~np.isnan(rv)
+    assert np.allclose(var[ok], rv[ok], rtol=1e-12, atol=1e-12)
+    ok = ~np.isnan(rm)
+    assert np.allclose(mean[ok], rm[ok], rtol=1e-14, atol=0)
+    F.free()
+
+
+def test_plain_estimator_refused_where_it_does_not_apply(srw):
+    A, walks = CASES["grid2d_32"]
+    M = srw.Matrix.from_host(A, DEV)
+    with pytest.raises(srw.SrwError) as e:
+        srw.build_factor(M, walks, 1e-3, 1, one_step_exact=False, reuse=True)
+    assert e.value.status == srw.E_ARG
+
+
 def test_natural_ordering_matches_oracle(srw):
     # rank = node id: the ordering the paper's derivations are written in
     A, walks = CASES["grid2d_37x29"]

@@ -53,6 +53,10 @@ BATCH = {"batch_256": (256, 64, 1e-3, 1e-8, 8)}  # matrices, walks/row, drop, to
 WORKLOADS.update({k: ("config_batch", dict(count=v[0]), v[1], v[2], v[3]) for k, v in BATCH.items()})
 
 
+# workloads on which the walk kernel's unlocked refill periods (1, 2, 4) may be timed
+SMALL_REFILL_OK = {"grid2d_32", "grid3d_64"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -606,6 +610,11 @@ def main():
               "single MI355X; it has no multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
 
+    if args.refill in (1, 2, 4) and args.workload not in SMALL_REFILL_OK:
+        print(f"bench.py: refill periods below 8 run only on {sorted(SMALL_REFILL_OK)}: a "
+              "full-size run with refill period 1 once printed nothing for 180 s and its "
+              "cause is not established.", file=sys.stderr)
+        sys.exit(2)
     if args.workload in BATCH:
         run_batch(args)
         return

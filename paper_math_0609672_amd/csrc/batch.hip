@@ -323,9 +323,17 @@ __global__ void k_zero_u64(unsigned long long* a, int n)
 // the rows wait and finish independently (a row may wait for another row of the same
 // round).  A lane polls the values it is missing itself.
 //
+// In-order claims guarantee progress, not speed.  A wave cannot start a round before
+// its earlier rounds are done, so with many waves each holding a long claim, rows whose
+// values are ready queue behind rows that wait: the solve time grows steeply with
+// waves x claim length (measured on 8.6 M slots, 8 right-hand sides, claims of 512
+// slots: 108, 196 and 459 ms at 2, 4 and 5 blocks per CU, against 13 ms at 2 blocks
+// per CU with 32-slot claims).  The tuner therefore tries only short claims on a
+// grid of at most two blocks per CU (see pcg_batched_impl).
+//
 // wait_ticks: wall-clock ticks (constant-rate counter) after which a wait gives up --
-// a guard against a defect, far above any legitimate wait (a claimed slot waits at
-// most for the slots claimed before it).
+// a guard against a defect, set far above the solve time of every schedule the tuner
+// tries.
 constexpr int RG = 8;
 constexpr int RPW = 64 / RG;  // rows of a wave in flight
 
@@ -771,13 +779,13 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     Sched sched = tuned_schedule(key);
     if (e == hipSuccess && sched.per_cu == 0) {
         float best = 1e30f;
-        Sched best_s{8, RPW * 16};
+        Sched best_s{2, RPW * 4};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
         CK(apply_b(F, W, best_s, s));  // warm
-        for (int cap : {8, 4, 2}) {
-            for (int chunk : {RPW * 4, RPW * 16, RPW * 64}) {
+        for (int cap : {2, 1}) {
+            for (int chunk : {RPW * 2, RPW * 4, RPW * 8}) {
                 if (e != hipSuccess) break;
                 const Sched cand{cap, chunk};
                 CK(hipEventRecord(e0, s));

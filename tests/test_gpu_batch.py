@@ -170,6 +170,39 @@ def test_batched_pcg_matches_oracle(srw, precision):
     F.free()
 
 
+def test_batched_pcg_fp32_factor(srw):
+    """Batched PCG with an FP32 factor: every system meets the tolerance by its true
+    residual and takes the iterations of the single FP32 build's PCG within two (the
+    FP32 substitutions sum in another order, and their rounding, about 1e-7, can move
+    a stopping test that lands near the tolerance); both calls (the first tunes the
+    solve schedule) agree."""
+    mats = batch_mats()
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    F = srw.build_factor_batched(Ms, 64, 1e-3, SEEDS, precision="fp32")
+    _, off = srw.batch_info(F)
+    N = off[-1]
+    Bh = np.random.default_rng(9).standard_normal((N, 8))
+    B = torch.as_tensor(Bh, device=DEV)
+    res = [srw.pcg_solve_batched(F, B, 1e-8, 500) for _ in range(2)]
+    for st, X, it, rel in res:
+        assert st == srw.OK
+    assert np.array_equal(np_(res[0][1]), np_(res[1][1]))
+    _, X, it, rel = res[1]
+    Xh = np_(X)
+    for i, A in enumerate(mats):
+        S = A.to_scipy()
+        a, b = off[i], off[i + 1]
+        Fi = srw.build_factor(Ms[i], 64, 1e-3, SEEDS[i], precision="fp32")
+        for j in range(Bh.shape[1]):
+            bj, xj = Bh[a:b, j], Xh[a:b, j]
+            true_rel = np.linalg.norm(bj - S @ xj) / np.linalg.norm(bj)
+            assert true_rel <= 1e-8, (i, j, true_rel)
+            st1, _, it1, _ = srw.pcg_solve(Ms[i], Fi, torch.as_tensor(bj, device=DEV), 1e-8, 500)
+            assert st1 == srw.OK and abs(int(it[i, j]) - it1) <= 2, (i, j, it[i, j], it1)
+        Fi.free()
+    F.free()
+
+
 def test_batched_rejects_given_ordering_and_bad_nrhs(srw):
     mats = batch_mats()[:2]
     Ms = [srw.Matrix.from_host(A, DEV) for A in mats]

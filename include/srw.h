@@ -421,6 +421,33 @@ int srw_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step
                        const float* mu_sd, const float* features, const float* target,
                        int64_t n, float* grad, float* loss, void* stream);
 
+/* srw_mlp_train_step on the rows rows[0..n) of features [n_rows][8] and target
+ * [n_rows] (a minibatch drawn from the whole training set without copying it; a row may
+ * appear more than once).  Returns SRW_E_ARG, with nothing queued, if a listed row lies
+ * outside [0, n_rows); the check synchronises the stream. */
+int srw_mlp_train_step_rows(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                            const float* mu_sd, const float* features, const float* target,
+                            int64_t n_rows, const int32_t* rows, int64_t n, float* grad,
+                            float* loss, void* stream);
+
+/* Training set of the budget network from one matrix: the rows whose label (from
+ * srw_budget_labels, float64[n], device) is finite and positive, in row order.
+ * x_out float32 [count][8] = their features (srw_row_features), y_out float32[count] =
+ * log(label), halved when per_step = 1 (labels per walk step: the budgets then follow
+ * the square root of the label, the least summed variance per step).  x_out and y_out
+ * hold n rows; *count (host) receives the rows kept.  Synchronises the stream. */
+int srw_budget_targets(const double* label, const float* features, int64_t n, int32_t per_step,
+                       float* x_out, float* y_out, int64_t* count, void* stream);
+
+/* Statistics of a training set of n >= 1 rows: mu_sd float32[16] = per-feature mean of
+ * features [n][8], then the sample standard deviation (divisor n - 1; at least 1e-6; 1
+ * when n = 1) -- the input scaling of the network; target_mean float32[1] = the mean of
+ * target float32[n] (the output bias a fit starts from).  target and target_mean are
+ * both given or both NULL.  Sums in float64 in a fixed order; device outputs, ordered on
+ * the stream. */
+int srw_mlp_standardize(const float* features, const float* target, int64_t n, float* mu_sd,
+                        float* target_mean, void* stream);
+
 /* walks int32[n] = clamp(ceil(exp(pred) / eps), lo, hi): per-row budgets for
  * srw_options.walks (rows with tau = 0 take no walks regardless). */
 int srw_mlp_budgets(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi,

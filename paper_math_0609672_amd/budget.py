@@ -40,15 +40,12 @@ def pilot_rows(M: srw.Matrix, seed: int, walks: int, drop_tol: float, rule: str 
     from a pilot factor with `walks` walks per row."""
     if rule not in RULES:
         raise ValueError(rule)
+    per_step = rule == "neyman"
     F = srw.build_factor(M, walks, drop_tol, seed, keep=1)
-    lab = srw.budget_labels(F, per_step=(rule == "neyman"))
+    lab = srw.budget_labels(F, per_step=per_step)
     F.free()
     feat = srw.row_features(M, srw.ordering(M.n, seed, M.rowptr.device))
-    ok = torch.isfinite(lab) & (lab > 0)
-    y = torch.log(lab[ok])
-    if rule == "neyman":
-        y = 0.5 * y
-    return feat[ok], y.to(torch.float32)
+    return srw.budget_targets(lab, feat, per_step)
 
 
 def init_params(seed: int, device) -> torch.Tensor:
@@ -68,29 +65,28 @@ def init_params(seed: int, device) -> torch.Tensor:
 
 def fit(X: torch.Tensor, y: torch.Tensor, *, epochs: int = 4, batch: int = 65536,
         lr: float = 2e-3, seed: int = 0, log_every: int = 50) -> Model:
-    """Adam on the mean squared error of log(label), minibatches of `batch` rows drawn
-    by a seeded permutation per epoch.  The output bias starts at the mean target."""
+    """Adam on the mean squared error of log(label), minibatches of `batch` rows taken
+    in the order of a seeded random permutation per epoch (srw_ordering's ranks, which
+    are one) and gathered inside the training kernel.  Input scaling and the output
+    bias's start (the mean target) come from srw_mlp_standardize."""
     dev = X.device
-    mu = X.mean(dim=0)
-    sd = X.std(dim=0).clamp_min(1e-6)
-    mu_sd = torch.cat([mu, sd]).to(torch.float32).contiguous()
+    X = X.contiguous()
+    y = y.contiguous()
+    mu_sd, y_mean = srw.mlp_standardize(X, y)
     P = init_params(seed, dev)
-    P[-1] = y.mean()
+    P[-1:].copy_(y_mean)
     m = torch.zeros_like(P)
     v = torch.zeros_like(P)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    g = torch.Generator(device="cpu").manual_seed(int(seed) + 1)
     hist = []
     step = 0
     n = X.shape[0]
-    for _ in range(epochs):
-        perm = torch.randperm(n, generator=g).to(dev)
+    for epoch in range(epochs):
+        perm = srw.ordering(n, (int(seed) << 16) + epoch + 1, dev)
         for s in range(0, n, batch):
-            idx = perm[s:s + batch]
-            xb = X[idx].contiguous()
-            yb = y[idx].contiguous()
             step += 1
-            srw.mlp_train_step(P, mu_sd, xb, yb, adam_m=m, adam_v=v, step=step, lr=lr, loss=loss)
+            srw.mlp_train_step_rows(P, mu_sd, X, y, perm[s:s + batch], adam_m=m, adam_v=v,
+                                    step=step, lr=lr, loss=loss)
             if step % log_every == 0 or step == 1:
                 hist.append((step, float(loss.item())))
     hist.append((step, float(loss.item())))

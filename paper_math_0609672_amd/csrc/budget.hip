@@ -289,8 +289,10 @@ struct WaveLds {
 __global__ __launch_bounds__(BLOCK) void k_mlp_grad(const float* __restrict__ P,
                                                     const float* __restrict__ musd,
                                                     const float* __restrict__ feat,
-                                                    const float* __restrict__ target, int64_t n,
-                                                    float inv_total, float* __restrict__ part)
+                                                    const float* __restrict__ target,
+                                                    const int32_t* __restrict__ rows,
+                                                    int64_t n_rows, int64_t n, float inv_total,
+                                                    float* __restrict__ part)
 {
     __shared__ MlpShared sh;
     __shared__ WaveLds wl[BLOCK / 64];
@@ -309,8 +311,12 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_grad(const float* __restrict__ P,
     float gb3 = 0.0f, sse = 0.0f;
 
     for (int64_t t = w0; t < ntile; t += nw) {
-        const int64_t row = t * 16 + c;
-        const bool valid = row < n;
+        const int64_t i = t * 16 + c;
+        // the i-th row given: rows[i] of the arrays, or row i without a list (the caller
+        // has checked the list; a row outside the arrays would count as absent)
+        const int64_t r = i < n ? (rows ? (int64_t)rows[i] : i) : -1;
+        const bool valid = r >= 0 && r < n_rows;
+        const int64_t row = valid ? r : 0;
         Tile T;
         tile_forward(sh, feat, musd, row, valid, T);
         const float err = valid ? T.y - target[row] : 0.0f;
@@ -524,22 +530,180 @@ int mlp_forward_impl(const float* P, const float* musd, const float* feat, int64
     return SRW_OK;
 }
 
+// *bad = 1 if a listed row lies outside [0, n_rows)
+__global__ void k_check_rows(int64_t n, const int32_t* __restrict__ rows, int64_t n_rows, int* bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (rows[i] < 0 || (int64_t)rows[i] >= n_rows)) *bad = 1;
+}
+
 int mlp_train_impl(float* P, float* m, float* v, int32_t step, float lr, const float* musd,
-                   const float* feat, const float* target, int64_t n, float* grad, float* loss,
-                   hipStream_t s)
+                   const float* feat, const float* target, const int32_t* rows, int64_t n_rows,
+                   int64_t n, float* grad, float* loss, hipStream_t s)
 {
     if (n == 0) return SRW_OK;
+    if (rows) {  // the list is checked before any training work is queued
+        int* bad = nullptr;
+        int hbad = 0;
+        SRW_HIP(hipMallocAsync((void**)&bad, sizeof(int), s));
+        hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            k_check_rows<<<grid_for(n, BLOCK), BLOCK, 0, s>>>(n, rows, n_rows, bad);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFreeAsync(bad, s);
+        SRW_HIP(e);
+        if (hbad) return SRW_E_ARG;
+    } else {
+        n_rows = n;
+    }
     const int grid = mlp_grid(n);
     const int64_t nparts = std::min<int64_t>((int64_t)grid * (BLOCK / 64), (n + 15) / 16);
     float* part = nullptr;
     SRW_HIP(hipMallocAsync((void**)&part, nparts * PART * sizeof(float), s));
     const float inv = 1.0f / (float)n;
-    k_mlp_grad<<<grid, BLOCK, 0, s>>>(P, musd, feat, target, n, inv, part);
+    k_mlp_grad<<<grid, BLOCK, 0, s>>>(P, musd, feat, target, rows, n_rows, n, inv, part);
     k_mlp_reduce<<<(NPARAM + 1 + 255) / 256, 256, 0, s>>>(part, nparts, inv, P, m, v, m != nullptr,
                                                           step, lr, 0.9f, 0.999f, 1e-8f, grad,
                                                           loss);
     hipError_t e = hipGetLastError();
     (void)hipFreeAsync(part, s);
+    SRW_HIP(e);
+    return SRW_OK;
+}
+
+// ------------------------------------------------ training set from the labels
+// A row enters the training set when its label is finite and positive; its target is
+// log(label), halved for the per-step (Neyman) rule: budgets then follow sqrt(label).
+__global__ void k_target_flags(int64_t n, const double* __restrict__ label, int32_t* __restrict__ flag)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double l = label[k];
+    flag[k] = (l > 0.0 && l < __builtin_inf()) ? 1 : 0;  // false for NaN
+}
+
+// Kept rows in row order: features copied, target written at the row's position.
+__global__ void k_target_scatter(int64_t n, const double* __restrict__ label,
+                                 const float* __restrict__ feat, const int32_t* __restrict__ flag,
+                                 const int64_t* __restrict__ pos, int half,
+                                 float* __restrict__ x_out, float* __restrict__ y_out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || !flag[k]) return;
+    const int64_t j = pos[k];
+    const double t = log(label[k]);
+    y_out[j] = (float)(half ? 0.5 * t : t);
+    for (int f = 0; f < NF; ++f) x_out[j * NF + f] = feat[k * NF + f];
+}
+
+// Per-feature sums over a fixed block of rows per workgroup, in float64: pass 0 the
+// values, pass 1 the squared deviations from mean (written by pass 0's finish).  Each
+// workgroup writes NF partials; one workgroup adds them in workgroup order.
+constexpr int STD_BLOCKS = 256;
+
+// Column NF of the sums is the target (pass 0 only; 0 without targets).
+constexpr int NS = NF + 1;
+
+__global__ __launch_bounds__(BLOCK) void k_feat_partials(int64_t n, const float* __restrict__ feat,
+                                                         const float* __restrict__ target,
+                                                         const double* __restrict__ mean,
+                                                         double* __restrict__ part)
+{
+    __shared__ double red[BLOCK / 64][NS];
+    double acc[NS];
+    for (int f = 0; f < NS; ++f) acc[f] = 0.0;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = std::min<int64_t>(n, r0 + per);
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+        for (int f = 0; f < NF; ++f) {
+            const double x = (double)feat[r * NF + f];
+            acc[f] += mean ? (x - mean[f]) * (x - mean[f]) : x;
+        }
+        if (!mean && target) acc[NF] += (double)target[r];
+    }
+    for (int f = 0; f < NS; ++f) acc[f] = wave_sum(acc[f]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int f = 0; f < NS; ++f) red[w][f] = acc[f];
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double t = 0.0;
+        for (int i = 0; i < BLOCK / 64; ++i) t += red[i][threadIdx.x];
+        part[(int64_t)blockIdx.x * NS + threadIdx.x] = t;
+    }
+}
+
+// pass 0: mean = sum / n (and the target mean).  pass 1: sd = sqrt(ss / (n - 1)), at
+// least 1e-6 (1 for a single row); mu_sd (float32) = mean then sd.
+__global__ void k_feat_finish(int64_t n, int nparts, const double* __restrict__ part,
+                              double* __restrict__ mean, int pass, float* __restrict__ mu_sd,
+                              float* __restrict__ target_mean)
+{
+    const int f = threadIdx.x;
+    if (f >= NS) return;
+    double t = 0.0;
+    for (int i = 0; i < nparts; ++i) t += part[(int64_t)i * NS + f];
+    if (pass == 0) {
+        if (f == NF) {
+            if (target_mean) *target_mean = (float)(t / (double)n);
+            return;
+        }
+        mean[f] = t / (double)n;
+        mu_sd[f] = (float)mean[f];
+        return;
+    }
+    if (f == NF) return;
+    const double sd = n >= 2 ? sqrt(t / (double)(n - 1)) : 1.0;
+    mu_sd[NF + f] = (float)(sd > 1e-6 ? sd : 1e-6);
+}
+
+int budget_targets_impl(const double* label, const float* feat, int64_t n, int half, float* x_out,
+                        float* y_out, int64_t* count, hipStream_t s)
+{
+    *count = 0;
+    if (n == 0) return SRW_OK;
+    const size_t tb = scan_tmp_bytes(n);
+    char* ws = nullptr;
+    const size_t o_pos = ((size_t)n * 4 + 255) & ~(size_t)255;
+    const size_t o_tmp = o_pos + (((size_t)(n + 1) * 8 + 255) & ~(size_t)255);
+    SRW_HIP(hipMallocAsync((void**)&ws, o_tmp + tb + 256, s));
+    int32_t* flag = (int32_t*)ws;
+    int64_t* pos = (int64_t*)(ws + o_pos);
+    const unsigned g = (unsigned)grid_for(n, BLOCK);
+    k_target_flags<<<g, BLOCK, 0, s>>>(n, label, flag);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = exclusive_scan_i32_to_i64(flag, pos, n, ws + o_tmp, s);
+    if (e == hipSuccess) {
+        k_target_scatter<<<g, BLOCK, 0, s>>>(n, label, feat, flag, pos, half, x_out, y_out);
+        e = hipGetLastError();
+    }
+    int64_t last[1] = {0};
+    int32_t lastf[1] = {0};
+    if (e == hipSuccess) e = hipMemcpyAsync(last, pos + n - 1, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lastf, flag + n - 1, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(ws, s);
+    SRW_HIP(e);
+    *count = last[0] + lastf[0];
+    return SRW_OK;
+}
+
+int mlp_standardize_impl(const float* feat, const float* target, int64_t n, float* mu_sd,
+                         float* target_mean, hipStream_t s)
+{
+    double* ws = nullptr;
+    SRW_HIP(hipMallocAsync((void**)&ws, (STD_BLOCKS * NS + NF) * sizeof(double), s));
+    double* mean = ws + STD_BLOCKS * NS;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(STD_BLOCKS, (n + BLOCK - 1) / BLOCK));
+    for (int pass = 0; pass < 2; ++pass) {
+        k_feat_partials<<<nb, BLOCK, 0, s>>>(n, feat, target, pass ? mean : nullptr, ws);
+        k_feat_finish<<<1, 64, 0, s>>>(n, nb, ws, mean, pass, mu_sd, target_mean);
+    }
+    hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(ws, s);
     SRW_HIP(e);
     return SRW_OK;
 }

@@ -443,8 +443,37 @@ int srw_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step
     if ((adam_m == nullptr) != (adam_v == nullptr)) return SRW_E_ARG;
     if (adam_m && (step < 1 || !(lr > 0.0f) || !std::isfinite(lr))) return SRW_E_ARG;
     if (n > 0 && (!params || !mu_sd || !features || !target)) return SRW_E_ARG;
-    return srw::mlp_train_impl(params, adam_m, adam_v, step, lr, mu_sd, features, target, n, grad,
-                               loss, as_stream(stream));
+    return srw::mlp_train_impl(params, adam_m, adam_v, step, lr, mu_sd, features, target, nullptr,
+                               n, n, grad, loss, as_stream(stream));
+}
+
+int srw_mlp_train_step_rows(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                            const float* mu_sd, const float* features, const float* target,
+                            int64_t n_rows, const int32_t* rows, int64_t n, float* grad,
+                            float* loss, void* stream)
+{
+    if (n < 0 || n_rows < 0) return SRW_E_ARG;
+    if ((adam_m == nullptr) != (adam_v == nullptr)) return SRW_E_ARG;
+    if (adam_m && (step < 1 || !(lr > 0.0f) || !std::isfinite(lr))) return SRW_E_ARG;
+    if (n > 0 && (!params || !mu_sd || !features || !target || !rows)) return SRW_E_ARG;
+    return srw::mlp_train_impl(params, adam_m, adam_v, step, lr, mu_sd, features, target, rows,
+                               n_rows, n, grad, loss, as_stream(stream));
+}
+
+int srw_budget_targets(const double* label, const float* features, int64_t n, int32_t per_step,
+                       float* x_out, float* y_out, int64_t* count, void* stream)
+{
+    if (n < 0 || !count || (per_step != 0 && per_step != 1)) return SRW_E_ARG;
+    if (n > 0 && (!label || !features || !x_out || !y_out)) return SRW_E_ARG;
+    return srw::budget_targets_impl(label, features, n, per_step, x_out, y_out, count,
+                                    as_stream(stream));
+}
+
+int srw_mlp_standardize(const float* features, const float* target, int64_t n, float* mu_sd,
+                        float* target_mean, void* stream)
+{
+    if (n < 1 || !features || !mu_sd || (!target) != (!target_mean)) return SRW_E_ARG;
+    return srw::mlp_standardize_impl(features, target, n, mu_sd, target_mean, as_stream(stream));
 }
 
 int srw_mlp_budgets(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi,

@@ -197,8 +197,12 @@ int walk_stats_impl(const srw_factor* F, double* var, double* mean_len, hipStrea
 int mlp_forward_impl(const float* P, const float* musd, const float* feat, int64_t n, float* out,
                      hipStream_t s);
 int mlp_train_impl(float* P, float* m, float* v, int32_t step, float lr, const float* musd,
-                   const float* feat, const float* target, int64_t n, float* grad, float* loss,
-                   hipStream_t s);
+                   const float* feat, const float* target, const int32_t* rows, int64_t n_rows,
+                   int64_t n, float* grad, float* loss, hipStream_t s);
+int budget_targets_impl(const double* label, const float* feat, int64_t n, int half, float* x_out,
+                        float* y_out, int64_t* count, hipStream_t s);
+int mlp_standardize_impl(const float* feat, const float* target, int64_t n, float* mu_sd,
+                         float* target_mean, hipStream_t s);
 int budgets_impl(const float* pred, int64_t n, double eps, int32_t lo, int32_t hi, int32_t* walks,
                  hipStream_t s);
 

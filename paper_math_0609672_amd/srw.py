@@ -86,6 +86,10 @@ _lib.srw_budget_labels.argtypes = [_P, _I32, _P, _P]
 _lib.srw_walk_stats.argtypes = [_P, _P, _P, _P]
 _lib.srw_mlp_forward.argtypes = [_P, _P, _P, _I64, _P, _P]
 _lib.srw_mlp_train_step.argtypes = [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _I64, _P, _P, _P]
+_lib.srw_mlp_train_step_rows.argtypes = [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _I64, _P,
+                                         _I64, _P, _P, _P]
+_lib.srw_budget_targets.argtypes = [_P, _P, _I64, _I32, _P, _P, ctypes.POINTER(_I64), _P]
+_lib.srw_mlp_standardize.argtypes = [_P, _P, _I64, _P, _P, _P]
 _lib.srw_mlp_budgets.argtypes = [_P, _I64, _D, _I32, _I32, _P, _P]
 _lib.srw_build_factor_batched.argtypes = [_I32, _P, _I32, _D, _P, ctypes.POINTER(_Options),
                                           ctypes.POINTER(_P), _P]
@@ -105,7 +109,8 @@ EXPORTED = ["srw_default_options", "srw_build_factor", "srw_build_ic0", "srw_fac
             "srw_factor_stats", "srw_factor_depth",
             "srw_factor_export", "srw_table_export", "srw_tally_export", "srw_walk_export",
             "srw_pcg_solve", "srw_apply", "srw_apply_noalloc", "srw_walk_stats", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
-            "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_budgets", "srw_build_factor_batched",
+            "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_train_step_rows", "srw_budget_targets",
+            "srw_mlp_standardize", "srw_mlp_budgets", "srw_build_factor_batched",
             "srw_batch_info", "srw_pcg_solve_batched", "srw_last_error", "srw_status_string"]
 
 NOALLOC_MAX_N = 1 << 21  # SRW_NOALLOC_MAX_N
@@ -467,6 +472,44 @@ def mlp_train_step(params: torch.Tensor, mu_sd: torch.Tensor, features: torch.Te
     _check(_lib.srw_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
                                    _ptr(mu_sd), _ptr(features), _ptr(target), int(n), _ptr(grad),
                                    _ptr(loss), _stream(stream)), "srw_mlp_train_step")
+
+
+def mlp_train_step_rows(params: torch.Tensor, mu_sd: torch.Tensor, features: torch.Tensor,
+                        target: torch.Tensor, rows: torch.Tensor, *, adam_m=None, adam_v=None,
+                        step: int = 1, lr: float = 1e-3, grad=None, loss=None,
+                        stream=None) -> None:
+    """srw_mlp_train_step_rows: srw_mlp_train_step on the listed rows (int32) of
+    features / target, gathered inside the kernel."""
+    _check(_lib.srw_mlp_train_step_rows(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
+                                        float(lr), _ptr(mu_sd), _ptr(features), _ptr(target),
+                                        int(features.shape[0]), _ptr(rows), int(rows.shape[0]),
+                                        _ptr(grad), _ptr(loss), _stream(stream)),
+           "srw_mlp_train_step_rows")
+
+
+def budget_targets(label: torch.Tensor, features: torch.Tensor, per_step: bool, stream=None):
+    """srw_budget_targets: (features, targets) of the rows with a finite positive
+    label, in row order; targets log(label), halved with per_step."""
+    n = label.shape[0]
+    x = torch.empty((n, NUM_FEATURES), dtype=torch.float32, device=label.device)
+    y = torch.empty(n, dtype=torch.float32, device=label.device)
+    cnt = _I64(0)
+    _check(_lib.srw_budget_targets(_ptr(label), _ptr(features), int(n), 1 if per_step else 0,
+                                   _ptr(x), _ptr(y), ctypes.byref(cnt), _stream(stream)),
+           "srw_budget_targets")
+    return x[:cnt.value], y[:cnt.value]
+
+
+def mlp_standardize(features: torch.Tensor, target: torch.Tensor | None = None, stream=None):
+    """srw_mlp_standardize: float32[16] per-feature mean, then sample standard
+    deviation (at least 1e-6); with a target, also its mean (float32[1]):
+    returns mu_sd, or (mu_sd, target_mean)."""
+    dev = features.device
+    mu_sd = torch.empty(2 * NUM_FEATURES, dtype=torch.float32, device=dev)
+    tm = torch.empty(1, dtype=torch.float32, device=dev) if target is not None else None
+    _check(_lib.srw_mlp_standardize(_ptr(features), _ptr(target), int(features.shape[0]),
+                                    _ptr(mu_sd), _ptr(tm), _stream(stream)), "srw_mlp_standardize")
+    return mu_sd if target is None else (mu_sd, tm)
 
 
 def mlp_budgets(pred: torch.Tensor, eps: float, lo: int, hi: int, stream=None) -> torch.Tensor:

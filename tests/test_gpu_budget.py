@@ -181,6 +181,87 @@ def test_adam_steps_match_oracle(srw):
         q = unflat(after)  # continue from the device's float32 parameters
 
 
+def test_train_step_rows_equals_gathered_batch(srw):
+    """Training on a row list equals training on the gathered copy of those rows, bit
+    for bit (same tiles, same order), over three Adam steps; a row outside the arrays is
+    refused before anything is queued."""
+    p = random_net(11)
+    X, mu, sd, t = random_inputs(5000, 12)
+    musd = torch.as_tensor(np.concatenate([mu, sd]), device=DEV)
+    Xd, td = torch.as_tensor(X, device=DEV), torch.as_tensor(t, device=DEV)
+    rows = np.random.default_rng(13).integers(0, 5000, 1777).astype(np.int32)
+    rows[:3] = [0, 4999, 0]  # ends of the arrays, and a repeat
+    rd = torch.as_tensor(rows, device=DEV)
+    Xg, tg = Xd[rd.long()].contiguous(), td[rd.long()].contiguous()
+    outs = []
+    for gathered in (False, True):
+        P = torch.as_tensor(flat(p).astype(np.float32), device=DEV)
+        m = torch.zeros(4801, dtype=torch.float32, device=DEV)
+        v = torch.zeros(4801, dtype=torch.float32, device=DEV)
+        loss = torch.empty(1, dtype=torch.float32, device=DEV)
+        for step in (1, 2, 3):
+            if gathered:
+                srw.mlp_train_step(P, musd, Xg, tg, adam_m=m, adam_v=v, step=step, lr=1e-2, loss=loss)
+            else:
+                srw.mlp_train_step_rows(P, musd, Xd, td, rd, adam_m=m, adam_v=v, step=step,
+                                        lr=1e-2, loss=loss)
+        torch.cuda.synchronize()
+        outs.append((np_(P), np_(m), np_(v), np_(loss)))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    P = torch.as_tensor(flat(p).astype(np.float32), device=DEV)
+    for bad in (-1, 5000):
+        rb = rd.clone()
+        rb[100] = bad
+        with pytest.raises(srw.SrwError):
+            srw.mlp_train_step_rows(P, musd, Xd, td, rb)
+    assert np.array_equal(np_(P), flat(p).astype(np.float32))
+
+
+@pytest.mark.parametrize("per_step", [False, True])
+def test_budget_targets_match_definition(srw, per_step):
+    """Rows with a finite positive label, in row order; target log(label), halved per
+    step."""
+    rng = np.random.default_rng(21)
+    n = 10007
+    lab = np.exp(rng.uniform(-20, 5, n))
+    lab[rng.random(n) < 0.1] = np.nan
+    lab[:6] = [0.0, -1.0, np.inf, -np.inf, np.nan, 5e-324]
+    feat = rng.standard_normal((n, 8)).astype(np.float32)
+    x, y = srw.budget_targets(torch.as_tensor(lab, device=DEV), torch.as_tensor(feat, device=DEV),
+                              per_step)
+    keep = np.isfinite(lab) & (lab > 0)
+    ref_y = np.log(lab[keep]) * (0.5 if per_step else 1.0)
+    assert x.shape[0] == keep.sum() and y.shape[0] == keep.sum()
+    assert np.array_equal(np_(x), feat[keep])
+    assert np.array_equal(np_(y), ref_y.astype(np.float32))
+    # nothing kept
+    x0, y0 = srw.budget_targets(torch.full((5,), np.nan, dtype=torch.float64, device=DEV),
+                                torch.as_tensor(feat[:5], device=DEV), per_step)
+    assert x0.shape[0] == 0 and y0.shape[0] == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 777, 300001])
+def test_mlp_standardize_matches_definition(srw, n):
+    """Per-feature mean and sample standard deviation (n - 1; at least 1e-6; 1 for one
+    row) and the target mean, to float32 rounding of the float64 statistics."""
+    rng = np.random.default_rng(n)
+    X = (rng.standard_normal((n, 8)) * rng.uniform(0.1, 5.0, 8) + rng.uniform(-3, 3, 8))
+    X[:, 5] = 2.5  # a constant feature: sd floored at 1e-6
+    X = X.astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    mu_sd, tm = srw.mlp_standardize(torch.as_tensor(X, device=DEV), torch.as_tensor(t, device=DEV))
+    X64 = X.astype(np.float64)
+    mu = X64.mean(axis=0)
+    sd = X64.std(axis=0, ddof=1) if n > 1 else np.ones(8)
+    sd = np.maximum(sd, 1e-6)
+    got = np_(mu_sd).astype(np.float64)
+    assert np.allclose(got[:8], mu.astype(np.float32), rtol=2e-7, atol=1e-6 * np.abs(X64).max())
+    assert np.allclose(got[8:], sd.astype(np.float32), rtol=2e-6)
+    assert abs(float(np_(tm)[0]) - t.astype(np.float64).mean()) <= 1e-6 * (1 + np.abs(t).max())
+    assert np.array_equal(np_(srw.mlp_standardize(torch.as_tensor(X, device=DEV))), np_(mu_sd))
+
+
 def test_budgets_match_oracle(srw):
     rng = np.random.default_rng(4)
     pred = rng.uniform(-8, 6, 5001).astype(np.float32)

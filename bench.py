@@ -80,6 +80,9 @@ def parse():
                          "(fp32 <-> fp64) and report it under ext_precision")
     ap.add_argument("--walks", type=int, default=0,
                     help="walks per row instead of the workload's (0 keeps the workload's)")
+    ap.add_argument("--head-rows", type=int, default=0,
+                    help="rows of the triangular solves' dense head (0 = the library default, "
+                         "-1 = none)")
     ap.add_argument("--walk-waves", type=int, default=0,
                     help="waves per CU of the persistent walk kernel (0 = the library default)")
     ap.add_argument("--reuse", action="store_true",
@@ -647,6 +650,7 @@ def main():
     asym = args.workload in ASYM
     build = srw.build_factor_ldu if asym else srw.build_factor
     solve = srw.bicgstab_solve if asym else srw.pcg_solve
+    head = {} if asym else {"head_rows": args.head_rows}  # two-game builds take no head
 
     def step():
         t0 = time.perf_counter()
@@ -656,7 +660,7 @@ def main():
         F = build(M, walks, drop, args.seed, precision=args.precision,
                   refill_period=args.refill, schedule=args.schedule,
                   solve_order=args.solve_order, profile=True, walks=budgets,
-                  reuse=args.reuse, walk_waves=args.walk_waves)
+                  reuse=args.reuse, walk_waves=args.walk_waves, **head)
         t1 = time.perf_counter()
         st, _, it, rel = solve(M, F, b, tol, 10000, x=x)
         t2 = time.perf_counter()
@@ -685,7 +689,7 @@ def main():
     s0 = runs[-1]["stats"]
     F = build(M, walks, drop, args.seed, precision=args.precision,
               refill_period=args.refill, schedule=args.schedule,
-              solve_order=args.solve_order, reuse=args.reuse, walk_waves=args.walk_waves)
+              solve_order=args.solve_order, reuse=args.reuse, walk_waves=args.walk_waves, **head)
     depth = F.depth()  # reported only; outside the timed steps
     F.free()
     walk_ms = sum(r["stats"]["phase_ms"]["walk"] for r in runs) / K
@@ -752,6 +756,7 @@ def main():
         "M1": metrics.m1(C, E, N),
         "M2": metrics.m1(C, E, N) * iters,
         "solve_depth": depth,
+        "solve_head_rows": 0 if asym or args.head_rows < 0 else min(A.n, args.head_rows or 4096),
         "phase_ms": phases,
         "roofline": {
             "kernel": "k_walk_reuse" if args.reuse else "k_walk",
@@ -769,12 +774,12 @@ def main():
         other = "fp32" if args.precision == "fp64" else "fp64"
         x_main = x.clone()
         F2 = build(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
-                   schedule=args.schedule, solve_order=args.solve_order)
+                   schedule=args.schedule, solve_order=args.solve_order, **head)
         F2.free()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F2 = build(M, walks, drop, args.seed, precision=other, refill_period=args.refill,
-                   schedule=args.schedule, solve_order=args.solve_order)
+                   schedule=args.schedule, solve_order=args.solve_order, **head)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         st2, x2, it2, rel2 = solve(M, F2, b, tol, 10000)

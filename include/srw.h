@@ -118,7 +118,22 @@ typedef struct {
                                   D_k = M' A_kk / J'_k.  0 is a test mode (both reach
                                   the same limit); it needs reuse = 0 and is refused
                                   by the batched, two-game and adaptive entry points */
+    int32_t head_rows;         /* the triangular solves' dense head: the lowest-ranked
+                                  h rows, whose long chain of dependencies (their
+                                  walks end at one another) would otherwise be solved
+                                  level by level, get the explicit inverse of their
+                                  diagonal block of Y (computed once by the build,
+                                  2 x h(h+1)/2 values) and are solved by two dense
+                                  products; the other rows are substituted as before.
+                                  0 (default) = min(n, 4096); -1 = none; 1..16384 =
+                                  min(n, that), lowered in steps of 64 rows where a
+                                  workgroup's LDS cannot hold one column of the
+                                  head's values (8 B per row).  Single builds only
+                                  (batched and two-game builds take none).  Results
+                                  agree with the substitution to rounding            */
 } srw_options;
+
+#define SRW_HEAD_MAX 16384  /* largest srw_options.head_rows */
 
 void srw_default_options(srw_options* opt);
 

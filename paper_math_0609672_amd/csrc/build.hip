@@ -881,13 +881,14 @@ __global__ void k_gather_slots(int64_t n, const int32_t* __restrict__ slot_node,
 }
 
 // (level, node) pairs of a rank-ordered plan, listed by slot, so a stable sort on the
-// level keeps rank order inside each level.
-__global__ void k_level_keys(int64_t n, const int32_t* __restrict__ slot_node,
+// level keeps rank order inside each level.  The first h slots (the dense head) take
+// key 0 and the others level + 1: the head stays first, in rank order.
+__global__ void k_level_keys(int64_t n, int64_t h, const int32_t* __restrict__ slot_node,
                              const int32_t* __restrict__ lev, uint32_t* key, uint32_t* val)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    key[s] = (uint32_t)lev[s];
+    key[s] = s < h ? 0u : (uint32_t)lev[s] + 1u;
     val[s] = (uint32_t)slot_node[s];
 }
 
@@ -1747,6 +1748,12 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipGetLastError());
         }
 
+        // the solves' dense head (single builds): the lowest-ranked rows
+        const int64_t head =
+            (batch || asym || rule || opt.head_rows < 0)
+                ? 0
+                : std::min<int64_t>(n, head_rows_fit(opt.head_rows == 0 ? HEAD_DEFAULT
+                                                                        : (int64_t)opt.head_rows));
         // solve plan: rows of Y and Y^T by slot, starting from the rank order
         F->slot_node = ALLOC(keep, int32_t, n);
         F->node_slot = ALLOC(keep, int32_t, n);
@@ -1799,9 +1806,9 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             status = dag_levels(F, lev, &depth, s);
             if (status) goto done;
             F->depth = depth;
-            k_level_keys<<<g, BLOCK, 0, s>>>(n, F->slot_node, lev, lkey, lval);
+            k_level_keys<<<g, BLOCK, 0, s>>>(n, head, F->slot_node, lev, lkey, lval);
             int bits = 8;
-            while (bits < 32 && ((int64_t)1 << bits) <= depth) bits += 8;
+            while (bits < 32 && ((int64_t)1 << bits) <= (int64_t)depth + 1) bits += 8;
             uint32_t* ko;
             uint32_t* vo;
             CHECK_HIP(radix_sort_u32(lkey, lval, lkey2, lval2, n, bits, rt, &ko, &vo, s));
@@ -1818,6 +1825,23 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
                 k_gather_slots<double><<<g, BLOCK, 0, s>>>(n, F->slot_node, (const double*)F->d,
                                                            (double*)F->dslot);
             CHECK_HIP(hipGetLastError());
+        }
+        if (head > 0) {
+            const size_t hb = (size_t)(head * (head + 1) / 2) * vbytes;
+            F->head = head;
+            F->hx = ALLOC(keep, char, hb);
+            F->hxt = ALLOC(keep, char, hb);
+            int* herr = ALLOC(tmp, int, 1);
+            if (!F->hx || !F->hxt || !herr) FAIL(SRW_E_NOMEM);
+            CHECK_HIP(head_inverse_launch(F, herr, s));
+            CHECK_HIP(hipMemcpyAsync(&pinned[0], herr, sizeof(int), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            int he = 0;
+            std::memcpy(&he, &pinned[0], sizeof(int));
+            if (he) {
+                set_last_error("the dense head's inverse gave up waiting");
+                FAIL(SRW_E_HIP);
+            }
         }
         mark(8);
         CHECK_HIP(hipStreamSynchronize(s));

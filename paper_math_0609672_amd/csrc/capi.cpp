@@ -43,6 +43,7 @@ int options_ok(const srw_options* opt, int64_t n)
     if (opt->walk_waves != 0 && (opt->walk_waves < 4 || opt->walk_waves > 64)) return SRW_E_ARG;
     if (opt->one_step_exact != 0 && opt->one_step_exact != 1) return SRW_E_ARG;
     if (!opt->one_step_exact && opt->reuse) return SRW_E_ARG;
+    if (opt->head_rows < -1 || opt->head_rows > SRW_HEAD_MAX) return SRW_E_ARG;
     return SRW_OK;
 }
 
@@ -66,6 +67,7 @@ void srw_default_options(srw_options* opt)
     opt->reuse = 0;
     opt->walk_waves = 0;
     opt->one_step_exact = 1;
+    opt->head_rows = 0;
 }
 
 

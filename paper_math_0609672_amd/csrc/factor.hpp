@@ -41,6 +41,13 @@ struct srw_factor {
     int32_t* bcol = nullptr;       // [nnz_y] slots, source rank descending in a row
     void* bval = nullptr;          // [nnz_y]
     void* dslot = nullptr;         // [n] D by slot
+    // dense head: the first `head` slots (the lowest ranks, in rank order) are solved
+    // with X, the inverse of their diagonal block of Y (unit lower triangular), packed
+    // by rows (row i: X[i][0..i] at i(i+1)/2), and its transpose packed by rows (row j:
+    // X[j..head-1][j] at j head - j(j-1)/2)
+    int64_t head = 0;
+    void* hx = nullptr;
+    void* hxt = nullptr;
 
     // longest dependency chain of the triangular solves, -1 until srw_factor_depth
     int32_t depth = -1;
@@ -87,6 +94,9 @@ struct srw_factor {
 };
 
 namespace srw {
+
+// rows of the triangular solves' dense head when srw_options.head_rows is 0
+constexpr int64_t HEAD_DEFAULT = 4096;
 
 // Device allocation tracked by an owner list (freed together).  With a stream the
 // blocks come from the stream-ordered pool (hipMallocAsync / hipFreeAsync), so the
@@ -179,6 +189,12 @@ int adaptive_impl(const srw_csr* A, uint64_t seed, const srw_options* opt, doubl
 int pcg_impl(const srw_csr* A, srw_factor* F, const double* b, double tol, int32_t max_iter,
              double* x, int32_t* iters, double* rel_residual, hipStream_t s);
 int apply_impl(srw_factor* F, const double* r, double* z, hipStream_t s);
+// X and X^T of F's dense head (F->head > 0; F->hx, F->hxt allocated, the solve plan
+// built).  err: device scratch; *err != 0 afterwards if a wait gave up.
+hipError_t head_inverse_launch(const srw_factor* F, int* err, hipStream_t s);
+// The largest head of at most h rows whose inverse this device can build (one column of
+// the head's values must fit in a workgroup's LDS).
+int64_t head_rows_fit(int64_t h);
 // srw_apply with the library's static scratch instead of allocations.
 int apply_noalloc_impl(const srw_factor* F, const double* r, double* z, hipStream_t s);
 int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);

@@ -261,8 +261,10 @@ __device__ __forceinline__ void wait_published(typename Bits<T>::U& bits, const 
     }
 }
 
+// The substitution covers the slots h..n-1 (the first h slots are the dense head, done
+// by the head kernels: before the forward rows, after the backward ones).
 template <typename T, bool FWD>
-__global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __restrict__ ptr,
+__global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, int64_t h, const int64_t* __restrict__ ptr,
                                                 const int32_t* __restrict__ col,
                                                 const T* __restrict__ val,
                                                 const T* __restrict__ dslot,
@@ -277,9 +279,10 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
     const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
     const int64_t wid =
         (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wid >= n) return;  // whole wave
+    const int64_t m = n - h;  // rows substituted
+    if (wid >= m) return;  // whole wave
     // the wave's next row, loaded one row ahead: bounds and first 64 entries
-    int64_t s = FWD ? wid : n - 1 - wid;
+    int64_t s = FWD ? h + wid : n - 1 - wid;
     int64_t q0 = ptr[s], q1 = ptr[s + 1];
     int32_t c = 0;
     T v = T(0);
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
         c = col[q0 + lane];
         v = val[q0 + lane];
     }
-    for (int64_t i = wid; i < n; i += nw) {
+    for (int64_t i = wid; i < m; i += nw) {
         const bool valid = q0 + lane < q1;
         U bits = valid ? load_published((const U*)sol + c) : U(0);
         const int32_t node = slot_node[s];
@@ -296,8 +299,8 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, const int64_t* __rest
         int64_t s2 = 0, p0 = 0, p1 = 0;
         int32_t c2 = 0;
         T v2 = T(0);
-        if (i2 < n) {
-            s2 = FWD ? i2 : n - 1 - i2;
+        if (i2 < m) {
+            s2 = FWD ? h + i2 : n - 1 - i2;
             p0 = ptr[s2];
             p1 = ptr[s2 + 1];
             if (p0 + lane < p1) {
@@ -362,6 +365,174 @@ __global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int64_t* __re
     if (lane == 0 && wid < n) atomicMax(depth, wmax);
 }
 
+// ----------------------------------------------------------------- dense head
+// The lowest-ranked rows carry most of the dependency chain (their walks end at one
+// another): at 128^3 the first 4,096 ranks hold 402 of the 1,147 levels.  Those rows
+// are solved with X, the inverse of their diagonal block of Y (unit lower triangular),
+// by two dense products per application instead of level by level.
+//   backward:  c_i = r_node(i) - sum over the row's Y^T entries on slots >= h of w,
+//              w_head = X^T c
+//   forward:   z_head = X (w_head / D_head)
+// X is packed by rows (row i: X[i][0..i] at i(i+1)/2); X^T packed by rows too (row j:
+// X[j..h-1][j] at j h - j(j-1)/2).
+__host__ __device__ __forceinline__ int64_t head_roff(int64_t i) { return i * (i + 1) / 2; }
+__host__ __device__ __forceinline__ int64_t head_toff(int64_t j, int64_t h)
+{
+    return j * h - j * (j - 1) / 2;
+}
+
+// X[i][j] = [i == j] - sum over the entries q of row i of Y: Y_iq X[q][j] (Y X = I).
+// W consecutive columns of X are one workgroup's: it takes the rows c0..h-1 (the rows
+// above are zero on these columns) in increasing order, dealt to its waves in turn,
+// and keeps the columns' values of those rows in LDS.  A row waits for its dependency
+// rows through flags in LDS; they are rows of the same workgroup, finished by waves
+// that are all resident and take their rows in increasing order, so the lowest
+// unfinished row can always finish.  The workgroups never wait for one another.
+// A row's entries are summed lane by lane (64 at a time) and then across the wave by
+// a butterfly: a fixed order.
+constexpr int HINV_WAVES = 16;  // waves of a workgroup
+
+template <typename T, int W>
+__global__ __launch_bounds__(64 * HINV_WAVES) void k_head_inverse(int64_t h,
+                                                                 const int64_t* __restrict__ ptr,
+                                                                 const int32_t* __restrict__ col,
+                                                                 const T* __restrict__ val, T* X,
+                                                                 int* err, int64_t ticks)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int64_t c0 = (int64_t)W * blockIdx.x;
+    const int64_t rows = h - c0;
+    unsigned int* done = (unsigned int*)lds;              // bit r: row c0 + r finished
+    const int64_t nwords = (rows + 31) / 32;
+    T* xv = (T*)(lds + ((nwords * 4 + 15) & ~(int64_t)15));  // [rows][W]
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int64_t k = threadIdx.x; k < nwords; k += blockDim.x) done[k] = 0u;
+    __syncthreads();
+    const int64_t t0 = wall_clock64();
+    bool failed = false;
+    for (int64_t i = c0 + wv; i < h; i += HINV_WAVES) {
+        T acc[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc[k] = T(0);
+        const int64_t q1 = ptr[i + 1];
+        for (int64_t qb = ptr[i]; qb < q1; qb += 64) {
+            const bool has = qb + lane < q1;
+            const int32_t q = has ? col[qb + lane] : -1;
+            const bool dep = q >= c0;  // rows below c0 are zero on these columns
+            const int64_t r = dep ? (int64_t)q - c0 : 0;
+            uint32_t spins = 0;
+            while (ballot(dep && !failed &&
+                          ((__hip_atomic_load(&done[r >> 5], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP) >> (r & 31)) & 1u) == 0u) != 0) {
+                if ((++spins & 255u) == 0 && wall_clock64() - t0 > ticks) {
+                    if (lane == 0) atomicOr(err, 1);
+                    failed = true;  // finishes with what is there; the build fails
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (dep) {
+                const T y = val[qb + lane];
+#pragma unroll
+                for (int k = 0; k < W; ++k) acc[k] = acc[k] + y * xv[r * W + k];
+            }
+        }
+        T x[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int64_t j = c0 + k;
+            const T sk = wave_sum(acc[k]);
+            x[k] = j > i ? T(0) : (j == i ? T(1) : T(0)) - sk;
+        }
+        if (lane < W) {
+            T mine = x[0];
+#pragma unroll
+            for (int k = 1; k < W; ++k) mine = lane == k ? x[k] : mine;
+            const int64_t j = c0 + lane;
+            xv[(i - c0) * W + lane] = mine;
+            if (j <= i) X[head_roff(i) + j] = mine;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) atomicOr(&done[(i - c0) >> 5], 1u << ((i - c0) & 31));
+    }
+}
+
+// LDS bytes of the workgroup that starts at column c0 (the first is the largest).
+__host__ __device__ inline size_t head_inverse_lds(int64_t h, int W)
+{
+    const int64_t words = (h + 31) / 32;
+    return (size_t)((words * 4 + 15) & ~(int64_t)15) + (size_t)h * W * 8;
+}
+
+// X^T from X through 64 x 64 tiles in LDS; one workgroup per tile (I, J), J <= I.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_head_transpose(int64_t h, const T* __restrict__ X,
+                                                          T* __restrict__ XT)
+{
+    __shared__ T tile[64][65];
+    int64_t b = blockIdx.x, I = 0;
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;  // tile row: the last I with I(I+1)/2 <= b
+    const int64_t J = b - I * (I + 1) / 2;
+    for (int k = threadIdx.x; k < 64 * 64; k += BLOCK) {
+        const int r = k >> 6, c = k & 63;
+        const int64_t i = 64 * I + r, j = 64 * J + c;
+        tile[r][c] = (i < h && j <= i) ? X[head_roff(i) + j] : T(0);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 64 * 64; k += BLOCK) {
+        const int c = k >> 6, r = k & 63;  // consecutive threads: consecutive i
+        const int64_t i = 64 * I + r, j = 64 * J + c;
+        if (i < h && j <= i) XT[head_toff(j, h) + (i - j)] = tile[r][c];
+    }
+}
+
+// c_i (into c) for the head slots: one wave per slot.  w holds the backward solution
+// on the slots >= h.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_head_rhs(int64_t h, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const T* __restrict__ val,
+                                                    const int32_t* __restrict__ slot_node,
+                                                    const double* __restrict__ rhs,
+                                                    const T* __restrict__ w, T* __restrict__ c)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    if (i >= h) return;  // whole wave
+    T acc = T(0);
+    for (int64_t q = ptr[i] + lane; q < ptr[i + 1]; q += 64) {
+        const int32_t k = col[q];
+        if (k >= h) acc += val[q] * w[k];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) c[i] = (T)rhs[slot_node[i]] - acc;
+}
+
+// One wave per row r of the packed matrix M: FWD, row r of X times (w / D) over the
+// head; otherwise row r of X^T times c[r..h-1].  Results to y (and by node to out).
+template <typename T, bool FWD>
+__global__ __launch_bounds__(BLOCK) void k_head_mv(int64_t h, const T* __restrict__ M,
+                                                   const T* __restrict__ v,
+                                                   const T* __restrict__ dslot,
+                                                   const int32_t* __restrict__ slot_node,
+                                                   T* __restrict__ y, double* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    if (r >= h) return;  // whole wave
+    const T* row = M + (FWD ? head_roff(r) : head_toff(r, h));
+    const int64_t len = FWD ? r + 1 : h - r;
+    T acc = T(0);
+    for (int64_t k = lane; k < len; k += 64)
+        acc += row[k] * (FWD ? v[k] / dslot[k] : v[r + k]);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        y[r] = acc;
+        if (FWD && out) out[slot_node[r]] = (double)acc;
+    }
+}
+
 // Grid of a cooperative launch: every block resident at once (occupancy x CUs),
 // capped at the blocks the work can use.
 template <typename K>
@@ -387,12 +558,14 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
                       hipStream_t s)
 {
     int64_t n = F->n;
+    int64_t h = F->head;
     int64_t ticks = wait_ticks(5.0);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, work);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, sol);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    {
+    const unsigned hg = (unsigned)((h + BLOCK / 64 - 1) / (BLOCK / 64));
+    if (n > h) {
         const int64_t* ptr = F->bptr;
         const int32_t* col = F->bcol;
         const T* val = (const T*)F->bval;
@@ -402,11 +575,22 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
         const T* w = nullptr;
         T* out_sol = work;
         double* out = nullptr;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
-        e = coop_launch(k_trsv<T, false>, n, args, s);
+        void* args[] = {&n, &h, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err,
+                        &ticks};
+        e = coop_launch(k_trsv<T, false>, n - h, args, s);
         if (e != hipSuccess) return e;
     }
-    {
+    if (h > 0) {
+        // backward head (c in sol's head slots, then w_head), forward head
+        k_head_rhs<T><<<hg, BLOCK, 0, s>>>(h, F->bptr, F->bcol, (const T*)F->bval, F->slot_node, r,
+                                           work, sol);
+        k_head_mv<T, false><<<hg, BLOCK, 0, s>>>(h, (const T*)F->hxt, sol, nullptr, nullptr, work,
+                                                 nullptr);
+        k_head_mv<T, true><<<hg, BLOCK, 0, s>>>(h, (const T*)F->hx, work, (const T*)F->dslot,
+                                                F->slot_node, sol, z);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (n > h) {
         const int64_t* ptr = F->fptr;
         const int32_t* col = F->fcol;
         const T* val = (const T*)F->fval;
@@ -416,8 +600,9 @@ hipError_t apply_plan(const srw_factor* F, const double* r, T* work, T* sol, dou
         const T* w = work;
         T* out_sol = sol;
         double* out = z;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
-        e = coop_launch(k_trsv<T, true>, n, args, s);
+        void* args[] = {&n, &h, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err,
+                        &ticks};
+        e = coop_launch(k_trsv<T, true>, n - h, args, s);
     }
     return e;
 }
@@ -439,6 +624,7 @@ hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol,
 {
     const srw_factor* G = F->tgame;
     int64_t n = F->n;
+    int64_t h = 0;  // the games' factors take no dense head
     int64_t ticks = wait_ticks(5.0);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, work);
     k_fill_sentinel<T><<<fill_grid(n), BLOCK, 0, s>>>(n, sol);
@@ -454,7 +640,8 @@ hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol,
         const T* w = nullptr;
         T* out_sol = work;
         double* out = z;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
+        void* args[] = {&n, &h, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err,
+                        &ticks};
         e = coop_launch(k_trsv<T, false>, n, args, s);
         if (e != hipSuccess) return e;
     }
@@ -470,7 +657,8 @@ hipError_t apply_ldu_plan(const srw_factor* F, const double* r, T* work, T* sol,
         const T* w = work;
         T* out_sol = sol;
         double* out = z;
-        void* args[] = {&n, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err, &ticks};
+        void* args[] = {&n, &h, &ptr, &col, &val, &dslot, &slot_node, &rhs, &w, &out_sol, &out, &err,
+                        &ticks};
         e = coop_launch(k_trsv<T, true>, n, args, s);
     }
     return e;
@@ -517,6 +705,60 @@ int64_t wait_ticks(double seconds)
         rate_khz[dev].store(khz, std::memory_order_relaxed);
     }
     return (int64_t)(seconds * 1000.0 * (double)khz);
+}
+
+int64_t head_rows_fit(int64_t h)
+{
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    while (h > 0 && head_inverse_lds(h, 1) > (size_t)lds_max) h -= 64;
+    return h > 0 ? h : 0;
+}
+
+hipError_t head_inverse_launch(const srw_factor* F, int* err, hipStream_t s)
+{
+    int64_t h = F->head;
+    if (h <= 0) return hipSuccess;
+    int64_t ticks = wait_ticks(10.0);
+    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+    if (e != hipSuccess) return e;
+    int dev = 0, lds_max = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) !=
+        hipSuccess)
+        return e;
+    // the widest column group whose rows fit in one workgroup's LDS (sized for doubles)
+    int W = 0;
+    for (int w : {4, 2, 1})
+        if (!W && head_inverse_lds(h, w) <= (size_t)lds_max) W = w;
+    if (!W) return hipErrorInvalidValue;  // head_rows is capped so that one column fits
+    const unsigned groups = (unsigned)((h + W - 1) / W);
+    const size_t lds = head_inverse_lds(h, W);
+    const int64_t nb = (h + 63) / 64;  // tile rows of the transpose
+    const unsigned tiles = (unsigned)(nb * (nb + 1) / 2);
+#define HEAD_INV(T, WW)                                                                            \
+    do {                                                                                           \
+        e = hipFuncSetAttribute((const void*)k_head_inverse<T, WW>,                               \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+        if (e != hipSuccess) return e;                                                             \
+        k_head_inverse<T, WW><<<groups, 64 * HINV_WAVES, lds, s>>>(                                \
+            h, F->fptr, F->fcol, (const T*)F->fval, (T*)F->hx, err, ticks);                         \
+    } while (0)
+    if (F->precision == SRW_FP32) {
+        if (W == 4) HEAD_INV(float, 4);
+        else if (W == 2) HEAD_INV(float, 2);
+        else HEAD_INV(float, 1);
+        k_head_transpose<float><<<tiles, BLOCK, 0, s>>>(h, (const float*)F->hx, (float*)F->hxt);
+    } else {
+        if (W == 4) HEAD_INV(double, 4);
+        else if (W == 2) HEAD_INV(double, 2);
+        else HEAD_INV(double, 1);
+        k_head_transpose<double><<<tiles, BLOCK, 0, s>>>(h, (const double*)F->hx, (double*)F->hxt);
+    }
+#undef HEAD_INV
+    return hipGetLastError();
 }
 
 hipError_t apply_factor(const srw_factor* F, const double* r, void* work, double* z, int* err,

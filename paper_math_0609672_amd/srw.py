@@ -40,7 +40,8 @@ class _Options(ctypes.Structure):
                 ("keep", ctypes.c_int32), ("refill_period", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("solve_order", ctypes.c_int32), ("reuse", ctypes.c_int32),
-                ("walk_waves", ctypes.c_int32), ("one_step_exact", ctypes.c_int32)]
+                ("walk_waves", ctypes.c_int32), ("one_step_exact", ctypes.c_int32),
+                ("head_rows", ctypes.c_int32)]
 
 
 NUM_PHASES = 8
@@ -272,12 +273,13 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
                  precision: str = "fp64", max_steps: int = 0, keep: int = 0, refill_period: int = 0,
                  profile: bool = False, schedule: int = 1, solve_order: int = 2,
                  reuse: bool = False, walk_waves: int = 0, one_step_exact: bool = True,
-                 stream=None) -> Factor:
+                 head_rows: int = 0, stream=None) -> Factor:
     """srw_build_factor: the random-walk incomplete LDL^T factor of A (with reuse, the
     walks extracted by Algorithm "reuse" of Section 5.3 join the tallies; with
-    one_step_exact=False, the plain estimator of eqs. yzdetail and d)."""
+    one_step_exact=False, the plain estimator of eqs. yzdetail and d).  head_rows: the
+    solves' dense head (0 automatic, -1 none)."""
     opt = _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-                   solve_order, reuse, walk_waves, one_step_exact)
+                   solve_order, reuse, walk_waves, one_step_exact, head_rows)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_factor(ctypes.byref(csr), int(walks_per_row), float(drop_tol), int(seed) & (2**64 - 1),
@@ -287,11 +289,11 @@ def build_factor(A: Matrix, walks_per_row: int, drop_tol: float, seed: int, *, r
 
 
 def build_ic0(A: Matrix, seed: int = 0, *, rank="natural", solve_order: int = 2,
-              stream=None) -> Factor:
+              head_rows: int = 0, stream=None) -> Factor:
     """srw_build_ic0: zero fill-in incomplete Cholesky in the factor's form (the ICCG
     comparison of Section 6); natural ordering unless `rank` is a device tensor of
     ranks or None (the random ordering of `seed`)."""
-    opt = _options(rank, None, "fp64", 0, 0, 0, False, 1, solve_order, False)
+    opt = _options(rank, None, "fp64", 0, 0, 0, False, 1, solve_order, False, head_rows=head_rows)
     h = ctypes.c_void_p(0)
     csr = A.c()
     st = _lib.srw_build_ic0(ctypes.byref(csr), int(seed) & (2**64 - 1), ctypes.byref(opt),
@@ -334,7 +336,7 @@ def bicgstab_solve(A: Matrix, F, b: torch.Tensor, tol: float, max_iter: int = 10
 
 
 def _options(rank, walks, precision, max_steps, keep, refill_period, profile, schedule,
-             solve_order, reuse, walk_waves=0, one_step_exact=True) -> _Options:
+             solve_order, reuse, walk_waves=0, one_step_exact=True, head_rows=0) -> _Options:
     opt = _Options()
     _lib.srw_default_options(ctypes.byref(opt))
     if isinstance(rank, str):
@@ -356,6 +358,7 @@ def _options(rank, walks, precision, max_steps, keep, refill_period, profile, sc
     opt.reuse = 1 if reuse else 0
     opt.walk_waves = int(walk_waves)
     opt.one_step_exact = 1 if one_step_exact else 0
+    opt.head_rows = int(head_rows)
     return opt
 
 

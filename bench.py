@@ -312,11 +312,15 @@ def run_batch(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, args.precision, s0["walk_waves"]),
             "alg_bytes_per_launch": walk_bytes,
             "avg_launch_ms": round(walk_ms, 3),
         },
     }
+    if out["roofline"]["traffic"]:
+        hbm = out["roofline"]["traffic"] / (walk_ms * 1e-3) / 1e9
+        out["roofline"]["hbm_measured_gbs"] = round(hbm, 1)
+        out["roofline"]["hbm_measured_frac"] = round(hbm / HBM_PEAK_GBS, 4)
     if not args.no_cpu:
         log(f"cpu baseline (oracle, whole batch, {host_threads()} threads)")
         out["cpu_baseline"] = cpu_baseline_batch(mats, seeds, walks, drop, tol, Bh, off)
@@ -592,17 +596,20 @@ def walk_source_sha():
 
 
 def measured_traffic(workload, precision, walk_waves):
-    """HBM bytes per walk launch from the committed counter summary, if it was taken
-    on this workload with the walk kernel's current source and grid; else None."""
+    """HBM bytes per walk launch from the committed counter summaries (one record per
+    workload), if one was taken on this workload with the walk kernel's current source
+    and grid; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            records = json.load(f).get("records", [])
+    except (OSError, ValueError, AttributeError):
         return None
-    if (t.get("source_sha256") != walk_source_sha() or t.get("workload") != workload
-            or t.get("precision") != precision or t.get("walk_waves_per_cu") != walk_waves):
-        return None
-    return t.get("traffic_bytes")
+    sha = walk_source_sha()
+    for t in records:
+        if (t.get("source_sha256") == sha and t.get("workload") == workload
+                and t.get("precision") == precision and t.get("walk_waves_per_cu") == walk_waves):
+            return t.get("traffic_bytes")
+    return None
 
 
 def main():

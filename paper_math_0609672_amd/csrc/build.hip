@@ -1355,15 +1355,34 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         // walk records: line offsets from an exclusive scan of the lines per node
         int32_t* nlines = ALLOC(tmp, int32_t, n);
         int64_t* rline = ALLOC(tmp, int64_t, n);
+        uint8_t* kbv = ALLOC(tmp, uint8_t, n);
         int64_t* ltot = ALLOC(tmp, int64_t, 1);
         void* lst = ALLOC(tmp, char, scan_tmp_bytes(n));
-        if (!nlines || !rline || !ltot || !lst) FAIL(SRW_E_NOMEM);
-        k_rec_lines<<<g, BLOCK, 0, s>>>(n, A->rowptr, nlines);
-        CHECK_HIP(exclusive_scan_i32_to_i64(nlines, rline, n, lst, s));
-        k_read_last<<<1, 1, 0, s>>>(rline, nlines, n, ltot);
-        CHECK_HIP(hipMemcpyAsync(&pinned[0], ltot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        CHECK_HIP(hipStreamSynchronize(s));
-        const int64_t n_lines = pinned[0];
+        if (!nlines || !rline || !kbv || !ltot || !lst) FAIL(SRW_E_NOMEM);
+        // bucket lines for the wide nodes where they fit, unless the main lines would
+        // pass 2^LINE_KB_SHIFT (then the plain layout)
+        int32_t bucketing = 1;
+        int64_t n_lines = 0;
+        int32_t* anyb = ALLOC(tmp, int32_t, 1);
+        if (!anyb) FAIL(SRW_E_NOMEM);
+        for (;;) {
+            CHECK_HIP(hipMemsetAsync(anyb, 0, sizeof(int32_t), s));
+            k_rec_lines<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, bucketing, nlines, kbv,
+                                            anyb);
+            CHECK_HIP(exclusive_scan_i32_to_i64(nlines, rline, n, lst, s));
+            k_read_last<<<1, 1, 0, s>>>(rline, nlines, n, ltot);
+            CHECK_HIP(hipMemcpyAsync(&pinned[0], ltot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipMemcpyAsync(&pinned[1], anyb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            CHECK_HIP(hipStreamSynchronize(s));
+            n_lines = pinned[0];
+            int32_t any = 0;
+            std::memcpy(&any, &pinned[1], sizeof(int32_t));
+            if (!bucketing || n_lines <= (int64_t)LINE_MASK) {
+                bucketing = bucketing && any;  // the walk kernel decodes line words only then
+                break;
+            }
+            bucketing = 0;
+        }
         if (2 * n_lines >= (int64_t)UINT32_MAX) FAIL(SRW_E_ARG);  // line indices are 32-bit
         // walk records, then start records of the same shape
         uint4* recs = ALLOC(tmp, uint4, 2 * n_lines * 4);
@@ -1381,7 +1400,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         mark(2);
         CHECK_HIP(hipMemsetAsync(maxb, 0, sizeof(int32_t), s));
         k_table<<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, grounded, walks_per_row,
-                                    opt.walks, plain ? 1 : 0, rline, n_lines, (uint32_t*)recs, ent,
+                                    opt.walks, plain ? 1 : 0, rline, kbv, bucketing, n_lines,
+                                    (uint32_t*)recs, ent,
                                     mthr, tau, budget, maxb);
         CHECK_HIP(hipGetLastError());
 
@@ -1444,7 +1464,8 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         // a walk's first step reads the row's start record (higher-ranked neighbours
         // only), or for the plain estimator the row's own record
         k_chunks<<<grid_for(norder, BLOCK), BLOCK, 0, s>>>(
-            norder, nlong, order, chunk_off, budget, rline, plain ? 0 : n_lines, F->rank, rec_off, seed,
+            norder, nlong, order, chunk_off, budget, rline, kbv, plain ? 0 : n_lines, F->rank, rec_off,
+            seed,
             batch ? batch->node_mat : nullptr, batch ? batch->mat_off : nullptr,
             batch ? batch->mat_seed : nullptr, cdesc);
         k_seg_bounds<<<1, 1, 0, s>>>(n, nlong, nslab_rows, pos2, chunk_off, bounds);
@@ -1491,13 +1512,20 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             void (*kern)(WalkArgs) = nullptr;
             if (reuse) {
-                kern = k_walk_reuse;
+                kern = bucketing ? k_walk_reuse<true> : k_walk_reuse<false>;
+            } else if (bucketing) {
+                switch (opt.refill_period) {
+                    case 2: kern = k_walk<2, true>; break;
+                    case 4: kern = k_walk<4, true>; break;
+                    case 8: kern = k_walk<8, true>; break;
+                    default: kern = k_walk<1, true>; break;
+                }
             } else {
                 switch (opt.refill_period) {
-                    case 2: kern = k_walk<2>; break;
-                    case 4: kern = k_walk<4>; break;
-                    case 8: kern = k_walk<8>; break;
-                    default: kern = k_walk<1>; break;
+                    case 2: kern = k_walk<2, false>; break;
+                    case 4: kern = k_walk<4, false>; break;
+                    case 8: kern = k_walk<8, false>; break;
+                    default: kern = k_walk<1, false>; break;
                 }
             }
             // persistent grid of walk_waves waves per CU (at most what fits)

@@ -24,14 +24,77 @@
 // weights) over the cumulative higher-ranked weight cm_m, word 3 is the last
 // higher-ranked neighbour's line and the grounded flag is clear.  The first step is
 // then the same select-and-load as every other step.
+//
+// Bucket lines.  A node of degree 7..BUCKET_MAX_DEG whose draw range [0, 2^32) splits
+// into B = 2^kb equal parts (kb = 3..6) that each meet at most six entries' threshold
+// intervals also gets B bucket lines, placed before its first line: bucket line b
+// holds the record's header and, in words 4..15 as in a narrow record, the entries
+// (entry order, zero-width ones left out) whose intervals meet [b 2^(32-kb),
+// (b+1) 2^(32-kb)).  The chosen entry of a draw in that range is among them, so the
+// selection is the narrow one.  A walk that moves to such a node usually holds its
+// next draw already (draws come in blocks of eight) and loads the bucket line of that
+// draw: one dependent load per step instead of two.  At the last step of a block the
+// next draw is not generated yet, and the walk loads the first line as before.  The
+// line words of entries (and word 3) carry the target's kb in their top bits when the
+// records are bucketed (all main lines below 2^LINE_KB_SHIFT).
 constexpr int REC_WORDS = 16;
+constexpr uint32_t LINE_KB_SHIFT = 27;
+constexpr uint32_t LINE_MASK = (1u << LINE_KB_SHIFT) - 1u;
+constexpr int64_t BUCKET_MAX_DEG = 64;
+constexpr uint32_t DESC_INLINE = 0x40000000u;  // the line's pairs are in words 4..15
 
-__global__ void k_rec_lines(int64_t n, const int64_t* __restrict__ rowptr, int32_t* lines)
+// Most entries (of nonzero width) that meet one of the 2^kb draw ranges of node v.
+__device__ uint32_t bucket_load(int64_t v, int64_t r0, int64_t r1, const int32_t* __restrict__ col,
+                                const double* __restrict__ val, double a, uint32_t kb)
+{
+    const uint32_t sh = 32u - kb;
+    uint32_t prev = 0u, cur = 0u, cnt = 0u, mx = 0u;
+    double c = 0.0;
+    for (int64_t p = r0; p < r1; ++p) {
+        if (col[p] == v) continue;
+        c = c + (-val[p]);
+        const uint32_t thr = threshold32(c, a);
+        if (thr > prev) {  // the entry's draws: [prev, thr)
+            const uint32_t bl = prev >> sh, bh = (thr - 1u) >> sh;
+            if (bl != cur) {
+                mx = max(mx, cnt);
+                cur = bl;
+                cnt = 0u;
+            }
+            ++cnt;
+            if (bh != bl) {
+                mx = max(mx, cnt);
+                cur = bh;
+                cnt = 1u;
+            }
+        }
+        prev = thr;
+    }
+    return max(mx, cnt);
+}
+
+// Lines per record and the bucket exponent kb of every node (0: no bucket lines);
+// *any_bucket |= 1 if some node has bucket lines.
+__global__ void k_rec_lines(int64_t n, const int64_t* __restrict__ rowptr,
+                            const int32_t* __restrict__ col, const double* __restrict__ val,
+                            int32_t bucketing, int32_t* __restrict__ lines, uint8_t* __restrict__ kbv,
+                            int32_t* any_bucket)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int64_t deg = rowptr[v + 1] - rowptr[v] - 1;
-    lines[v] = (int32_t)(deg <= 6 ? 1 : 1 + (deg + 7) / 8);
+    const int64_t r0 = rowptr[v], r1 = rowptr[v + 1];
+    const int64_t deg = r1 - r0 - 1;
+    uint32_t kb = 0u;
+    if (bucketing && deg > 6 && deg <= BUCKET_MAX_DEG) {
+        double a = 0.0;
+        for (int64_t p = r0; p < r1; ++p)
+            if (col[p] == v) a = val[p];
+        for (uint32_t k = 3u; k <= 6u && kb == 0u; ++k)
+            if (bucket_load(v, r0, r1, col, val, a, k) <= 6u) kb = k;
+    }
+    kbv[v] = (uint8_t)kb;
+    if (kb) atomicOr(any_bucket, 1);
+    lines[v] = (int32_t)((kb ? (1 << kb) : 0) + (deg <= 6 ? 1 : 1 + (deg + 7) / 8));
 }
 
 // a wide record's summary words: the last threshold of each of its first twelve
@@ -45,11 +108,21 @@ __device__ __forceinline__ void wide_summary(uint32_t* rec, uint32_t m)
     }
 }
 
+// the line word of an entry that moves to node j: its first record line, with its
+// bucket exponent in the top bits when the records are bucketed
+__device__ __forceinline__ uint32_t line_word(const int64_t* __restrict__ rline,
+                                              const uint8_t* __restrict__ kbv, int32_t bucketing,
+                                              int32_t j)
+{
+    return (uint32_t)rline[j] | (bucketing ? (uint32_t)kbv[j] << LINE_KB_SHIFT : 0u);
+}
+
 __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
                         const int32_t* __restrict__ col, const double* __restrict__ val,
                         const int32_t* __restrict__ rank, const uint8_t* __restrict__ grounded,
                         int32_t walks_per_row, const int32_t* __restrict__ budget_in,
-                        int32_t plain, const int64_t* __restrict__ rline, int64_t n_lines,
+                        int32_t plain, const int64_t* __restrict__ rline,
+                        const uint8_t* __restrict__ kbv, int32_t bucketing, int64_t n_lines,
                         uint32_t* __restrict__ recs, uint2* __restrict__ ent,
                         uint32_t* __restrict__ mthr, double* __restrict__ tau,
                         int32_t* __restrict__ budget, int32_t* max_budget)
@@ -65,8 +138,10 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
         else if (rank[j] > rv) motel = motel + (-val[p]);
     }
     const int64_t start = r0 - v;
-    uint32_t* rec = recs + (size_t)rline[v] * REC_WORDS;
-    uint32_t* srec = recs + (size_t)(n_lines + rline[v]) * REC_WORDS;
+    const uint32_t kb = kbv[v];
+    const int64_t first = rline[v] + (kb ? (1 << kb) : 0);  // the first line, after the buckets
+    uint32_t* rec = recs + (size_t)first * REC_WORDS;
+    uint32_t* srec = recs + (size_t)(n_lines + first) * REC_WORDS;
     const uint32_t deg = (uint32_t)(r1 - r0 - 1);
     const bool wide = deg > 6;
     double c = 0.0, cm = 0.0;
@@ -76,7 +151,7 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
         if (j == v) continue;
         const double w = -val[p];
         c = c + w;
-        const uint32_t line = (uint32_t)rline[j];
+        const uint32_t line = line_word(rline, kbv, bucketing, j);
         if (rank[j] > rv) {
             cm = cm + w;
             last_motel_line = line;
@@ -94,14 +169,50 @@ __global__ void k_table(int64_t n, const int64_t* __restrict__ rowptr,
         ++m;
     }
     const uint32_t flags = grounded[v] ? DESC_GROUNDED : 0u;
+    const uint32_t inl = wide ? 0u : DESC_INLINE;
     rec[0] = (uint32_t)rv;
-    rec[1] = m | flags;
+    rec[1] = m | flags | inl;
     rec[2] = (uint32_t)v;
     rec[3] = last_line;
     srec[0] = (uint32_t)rv;
-    srec[1] = m;
+    srec[1] = m | inl;
     srec[2] = (uint32_t)v;
     srec[3] = last_motel_line;
+    if (kb) {
+        // bucket lines: the header, then the entries meeting each draw range in order
+        const uint32_t B = 1u << kb, sh = 32u - kb;
+        uint32_t* bl0 = recs + (size_t)rline[v] * REC_WORDS;
+        for (uint32_t b = 0; b < B; ++b) {
+            uint32_t* L = bl0 + (size_t)b * REC_WORDS;
+            L[0] = (uint32_t)rv;
+            L[1] = m | flags | DESC_INLINE;
+            L[2] = (uint32_t)v;
+            L[3] = last_line;
+            for (int q = 4; q < REC_WORDS; ++q) L[q] = 0u;
+        }
+        uint32_t prev = 0u, cur = 0u, slot = 0u;
+        double cc = 0.0;
+        for (int64_t p = r0; p < r1; ++p) {
+            const int32_t j = col[p];
+            if (j == v) continue;
+            cc = cc + (-val[p]);
+            const uint32_t thr = threshold32(cc, a);
+            if (thr > prev) {
+                const uint32_t lw = line_word(rline, kbv, bucketing, j);
+                for (uint32_t b = prev >> sh; b <= ((thr - 1u) >> sh); ++b) {
+                    if (b != cur) {
+                        cur = b;
+                        slot = 0u;
+                    }
+                    uint32_t* L = bl0 + (size_t)b * REC_WORDS;
+                    L[4 + 2 * slot] = thr;
+                    L[5 + 2 * slot] = lw;
+                    ++slot;
+                }
+            }
+            prev = thr;
+        }
+    }
     if (wide) {
         wide_summary(rec, m);
         wide_summary(srec, m);
@@ -142,10 +253,12 @@ static_assert(sizeof(ChunkDesc) == 32, "chunk descriptors are 32 bytes");
 
 // chunk descriptors of the rows in schedule order: consecutive walks of a row, SRW_WAVE
 // per chunk for the first nlong rows, CHUNK_WALKS for the others; a walk starts from
-// line sline_base + rline[v] (the start records, or 0: the rows' own records)
+// the first line of the start record (sline_base: the start records) or, with
+// sline_base 0, of the row's own record
 __global__ void k_chunks(int64_t norder, int64_t nlong, const int32_t* __restrict__ order,
                          const int64_t* __restrict__ chunk_off, const int32_t* __restrict__ budget,
-                         const int64_t* __restrict__ rline, int64_t sline_base,
+                         const int64_t* __restrict__ rline, const uint8_t* __restrict__ kbv,
+                         int64_t sline_base,
                          const int32_t* __restrict__ rank, const int64_t* __restrict__ rec_off,
                          uint64_t seed, const int32_t* __restrict__ node_mat,
                          const int64_t* __restrict__ mat_off, const uint64_t* __restrict__ mat_seed,
@@ -163,7 +276,7 @@ __global__ void k_chunks(int64_t norder, int64_t nlong, const int32_t* __restric
         d.key = (uint32_t)(v - mat_off[mi]);
         d.seed = mat_seed[mi];
     }
-    d.sline = (uint32_t)(sline_base + rline[v]);
+    d.sline = (uint32_t)(sline_base + rline[v] + (kbv[v] ? (1 << kbv[v]) : 0));
     d.rank = (uint32_t)rank[v];
     d.rec = (uint64_t)rec_off[v];
     for (int64_t c = chunk_off[j]; c < chunk_off[j + 1]; ++c) {
@@ -277,7 +390,7 @@ __device__ __forceinline__ void emit_walks(const WalkArgs& a, bool em, uint32_t 
 #ifndef SRW_WALK_WAVES
 #define SRW_WALK_WAVES 4  // waves per SIMD the register budget is cut for (the grid runs 2)
 #endif
-template <int R, bool REUSE>
+template <int R, bool REUSE, bool BUCKETS>
 __device__ __forceinline__ void walk_body(const WalkArgs& a)
 {
     const int lane = __lane_id();
@@ -390,13 +503,16 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
 
         const uint32_t deg = (!LOCK || active) ? (r0.y & DESC_DEG_MASK) : 0u;
         degsum += deg;
+        // an idle lane takes the in-line path: it loads nothing more
+        const bool inl = (LOCK && !active) || (r0.y & DESC_INLINE) != 0u;
         // The next node is the first entry m with u < threshold_m; the words of the
-        // record's first line are held in registers.
+        // line held (a narrow record, a bucket line, or a wide record's first line)
+        // are in registers.
         const uint32_t e[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
                                 r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
         uint32_t next_line = 0;
         bool found = false;
-        if (deg <= 6) {
+        if (inl) {
             // entries 0..5 in words 4..15, scanned from the top with selects (the
             // lowest hit is taken last): no branches.  Unused entries are zero words,
             // and no u is below a zero threshold.
@@ -438,6 +554,14 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         // keeps the load below unconditional
         const bool to_ground = !found && (r0.y & DESC_GROUNDED) != 0;
         if (!found) next_line = e[3];
+        if constexpr (BUCKETS) {
+            // the line word: a bucketed target's bucket line for the next draw (q0,
+            // unless this step ends the block of eight), else its first line
+            const uint32_t kb = next_line >> LINE_KB_SHIFT;
+            const uint32_t base = next_line & LINE_MASK;
+            const bool have_next = ((LOCK ? iter : (uint32_t)t) & 7u) != 7u;
+            next_line = kb == 0u ? base : base + (have_next ? (q0 >> (32u - kb)) : (1u << kb));
+        }
         if (LOCK && !active) next_line = 0;
         const uint4* lp = a.recs + (size_t)next_line * 4;
         r0 = lp[0];
@@ -538,14 +662,16 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
     }
 }
 
-template <int R>
+// BUCKETS: some records have bucket lines (line words carry bucket exponents)
+template <int R, bool BUCKETS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_WAVES))) void k_walk(WalkArgs a)
 {
-    walk_body<R, false>(a);
+    walk_body<R, false, BUCKETS>(a);
 }
 
 // walk reuse keeps the stack top in registers as well: a larger register budget
+template <bool BUCKETS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_reuse(WalkArgs a)
 {
-    walk_body<8, true>(a);
+    walk_body<8, true, BUCKETS>(a);
 }

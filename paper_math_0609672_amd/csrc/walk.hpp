@@ -31,12 +31,13 @@
 // holds the record's header and, in words 4..15 as in a narrow record, the entries
 // (entry order, zero-width ones left out) whose intervals meet [b 2^(32-kb),
 // (b+1) 2^(32-kb)).  The chosen entry of a draw in that range is among them, so the
-// selection is the narrow one.  A walk that moves to such a node usually holds its
-// next draw already (draws come in blocks of eight) and loads the bucket line of that
-// draw: one dependent load per step instead of two.  At the last step of a block the
-// next draw is not generated yet, and the walk loads the first line as before.  The
-// line words of entries (and word 3) carry the target's kb in their top bits when the
-// records are bucketed (all main lines below 2^LINE_KB_SHIFT).
+// selection is the narrow one.  A walk that moves to such a node holds its next draw
+// already (the walk kernel makes each block of eight draws one step ahead) and loads
+// the bucket line of that draw: one dependent load per step instead of two.  The line
+// words of entries (and word 3) carry the target's kb in their top bits when the
+// records are bucketed (all main lines below 2^LINE_KB_SHIFT).  The first line and the
+// continuation lines stay: a walk of the plain estimator starts from its row's own
+// record.
 constexpr int REC_WORDS = 16;
 constexpr uint32_t LINE_KB_SHIFT = 27;
 constexpr uint32_t LINE_MASK = (1u << LINE_KB_SHIFT) - 1u;
@@ -491,7 +492,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         // iteration count agree mod 8 and the random block refresh is wave-uniform.
         constexpr bool LOCK = !REUSE && R == 8;
         if (LOCK || active) {  // structured: the lanes rejoin before the next refill's ballots
-        if ((LOCK ? (iter & 7u) : (uint32_t)(t & 7)) == 0) {
+        // draws: step t's is the word t mod 8 of the Philox block t div 8.  With bucket
+        // lines a walk needs its next draw during a step, so the next block is made at
+        // the block's last step and the first block when the walk starts.
+        const uint32_t phase = LOCK ? (iter & 7u) : (uint32_t)(t & 7);
+        if (phase == 0 && (!BUCKETS || t == 0)) {
             const u64x4 b = philox4x64_10(t >> 3, w, key, STREAM_WALK, seedw, 0);
             q0 = (uint32_t)b.x0; q1 = (uint32_t)(b.x0 >> 32);
             q2 = (uint32_t)b.x1; q3 = (uint32_t)(b.x1 >> 32);
@@ -500,6 +505,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         }
         const uint32_t u = q0;
         q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7;
+        if constexpr (BUCKETS) {
+            if (phase == 7) {  // q0 becomes the next step's draw
+                const u64x4 b = philox4x64_10((t + 1) >> 3, w, key, STREAM_WALK, seedw, 0);
+                q0 = (uint32_t)b.x0; q1 = (uint32_t)(b.x0 >> 32);
+                q2 = (uint32_t)b.x1; q3 = (uint32_t)(b.x1 >> 32);
+                q4 = (uint32_t)b.x2; q5 = (uint32_t)(b.x2 >> 32);
+                q6 = (uint32_t)b.x3; q7 = (uint32_t)(b.x3 >> 32);
+            }
+        }
 
         const uint32_t deg = (!LOCK || active) ? (r0.y & DESC_DEG_MASK) : 0u;
         degsum += deg;
@@ -555,12 +569,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
         const bool to_ground = !found && (r0.y & DESC_GROUNDED) != 0;
         if (!found) next_line = e[3];
         if constexpr (BUCKETS) {
-            // the line word: a bucketed target's bucket line for the next draw (q0,
-            // unless this step ends the block of eight), else its first line
+            // the line word: a bucketed target's bucket line for the next draw (q0),
+            // else its first line
             const uint32_t kb = next_line >> LINE_KB_SHIFT;
             const uint32_t base = next_line & LINE_MASK;
-            const bool have_next = ((LOCK ? iter : (uint32_t)t) & 7u) != 7u;
-            next_line = kb == 0u ? base : base + (have_next ? (q0 >> (32u - kb)) : (1u << kb));
+            next_line = kb == 0u ? base : base + (q0 >> (32u - kb));
         }
         if (LOCK && !active) next_line = 0;
         const uint4* lp = a.recs + (size_t)next_line * 4;

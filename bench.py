@@ -486,12 +486,16 @@ def run_learned(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         walks = None if eps is None else LB.budgets(model, M, args.seed, eps, lo=8, hi=8192)
-        F = srw.build_factor(M, uni, drop, args.seed, walks=walks, profile=True)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        F = srw.build_factor(M, uni, drop, args.seed, walks=walks, profile=True,
+                             head_rows=args.head_rows)
         st, _, it, rel = srw.pcg_solve(M, F, b, tol, 10000, x=x)
         s = F.stats()
         F.free()
         torch.cuda.synchronize()
-        return dict(s=time.perf_counter() - t0, iters=it, rel=rel, status=st, stats=s)
+        return dict(s=time.perf_counter() - t0, budget_s=t_b - t0, iters=it, rel=rel, status=st,
+                    stats=s)
 
     run()  # warm
     ref = run()
@@ -564,6 +568,11 @@ def run_learned(args):
         "walk_steps_learned": learned[-1]["stats"]["walk_steps"] if learned else None,
         "walk_steps_uniform": uniform[-1]["stats"]["walk_steps"],
         "factor_C": C,
+        "budget_s_learned": round(float(np.median([r["budget_s"] for r in learned])), 4)
+        if learned else None,
+        "phase_ms_learned": {k: round(v, 2) for k, v in learned[-1]["stats"]["phase_ms"].items()}
+        if learned else None,
+        "phase_ms_uniform": {k: round(v, 2) for k, v in uniform[-1]["stats"]["phase_ms"].items()},
         "train": {"pilot_s": round(t1 - t0, 3),
                   "fit_s": round(t2 - t1, 3), "loss": loss, "target_var": var_y},
         "roofline": {
@@ -763,7 +772,7 @@ def main():
         "M1": metrics.m1(C, E, N),
         "M2": metrics.m1(C, E, N) * iters,
         "solve_depth": depth,
-        "solve_head_rows": 0 if asym or args.head_rows < 0 else min(A.n, args.head_rows or 4096),
+        "solve_head_rows": s0.get("head_rows", 0),
         "phase_ms": phases,
         "roofline": {
             "kernel": "k_walk_reuse" if args.reuse else "k_walk",

@@ -252,6 +252,22 @@ __global__ void k_compact(int64_t count, const int32_t* __restrict__ rows_or_nul
     chunks[base + pos[i]] = (budget[v] + cs - 1) / cs;
 }
 
+// flag[i] = 1 for the rows whose budget lies in (lo, hi]
+__global__ void k_budget_class(int64_t n, const int32_t* __restrict__ budget, int32_t lo,
+                               int32_t hi, int32_t* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = budget[i] > lo && budget[i] <= hi;
+}
+
+// the flagged rows, in row order, at their exclusive-scan positions
+__global__ void k_scatter_rows(int64_t n, const int32_t* __restrict__ flag,
+                               const int64_t* __restrict__ pos, int32_t* __restrict__ rows)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) rows[pos[i]] = (int32_t)i;
+}
+
 __global__ void k_read_last(const int64_t* scan, const int32_t* last_in, int64_t n, int64_t* out)
 {
     out[0] = n > 0 ? scan[n - 1] + (int64_t)last_in[n - 1] : 0;
@@ -327,10 +343,13 @@ __global__ __launch_bounds__(64) void k_length_rule(int64_t n, const int32_t* __
 }
 
 // --------------------------------------------------------------------- tallies
-// One wave per row, rows in a grid-stride loop.  LDS: P sort keys (P = power of two >=
-// budget) + P run heads.  Launched with one workgroup per row: on a 3D grid (2.1M
-// rows, 256 walks each) that takes 6.8 ms, a chip-sized grid looping over rows 8.5 ms.
-__global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restrict__ budget,
+// One wave per row, rows in a grid-stride loop over `rows` (all rows when null).  LDS:
+// P sort keys + P run heads, P a power of two >= every listed row's budget; a row sorts
+// only the smallest power of two (at least 64) that holds its own walks.  Launched with
+// one workgroup per row: on a 3D grid (2.1M rows, 256 walks each) that takes 6.8 ms, a
+// chip-sized grid looping over rows 8.5 ms.
+__global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restrict__ rows,
+                                              const int32_t* __restrict__ budget,
                                               const int64_t* __restrict__ rec_off,
                                               const uint32_t* rec_end,
                                               const uint32_t* rec_vis,
@@ -345,8 +364,10 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
     uint32_t* key = lds;
     uint32_t* head = lds + P;
     const int lane = threadIdx.x;
-    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    for (int64_t kk = blockIdx.x; kk < n; kk += gridDim.x) {
+    const int64_t k = rows ? rows[kk] : kk;
     const int m = budget[k];
+    if (m > P) continue;  // not this launch's row (the caller checks that none is left)
     if (m == 0) {  // exact row: no walks
         if (lane == 0) {
             J[k] = 0;
@@ -358,9 +379,11 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
         continue;
     }
     const int64_t base = rec_off[k];
+    int Pk = 64;
+    while (Pk < m) Pk <<= 1;
     uint64_t jv = 0, sl = 0, vq = 0;
     uint32_t g = 0;
-    for (int i = lane; i < P; i += 64) {
+    for (int i = lane; i < Pk; i += 64) {
         uint32_t e = END_GROUND;
         if (i < m) {
             e = rec_end[base + i];
@@ -378,9 +401,9 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
     g = wave_sum(g);
     __syncthreads();
     // bitonic sort, ascending (ground markers sort last)
-    for (int size = 2; size <= P; size <<= 1) {
+    for (int size = 2; size <= Pk; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = lane; i < (P >> 1); i += 64) {
+            for (int i = lane; i < (Pk >> 1); i += 64) {
                 // stride is a power of two: pair i's lower index without a division
                 const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));
                 const int hi = lo + stride;
@@ -422,11 +445,14 @@ __global__ __launch_bounds__(64) void k_tally(int64_t n, const int32_t* __restri
 }
 
 // The same tallies for budgets up to 2048 walks, without sorting every end node: the
-// ends go into an LDS hash table of 2P slots (linear probing, counts by atomic add),
-// the distinct ones (about C/N of them) are compacted in slot order and only those are
-// sorted, as (node << 32 | count).  The H list is then the same as k_tally's.
-// LDS: 2P keys + 2P counts (u32) + P pairs (u64).
-__global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __restrict__ budget,
+// ends go into an LDS hash table (linear probing, counts by atomic add) of twice the
+// smallest power of two >= the row's budget slots, at least 128; the distinct ends
+// (about C/N of them) are compacted in slot order and only those are sorted, as
+// (node << 32 | count).  The H list is then the same as k_tally's.  One workgroup per
+// entry of `rows` (per row when null); rows whose budget exceeds P are left to another
+// launch.  LDS: 2P keys + 2P counts (u32) + P pairs (u64).
+__global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ budget,
                                                    const int64_t* __restrict__ rec_off,
                                                    const uint32_t* rec_end,
                                                    const uint32_t* rec_vis,
@@ -439,17 +465,19 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
                                                    uint32_t* h_cnt)
 {
     extern __shared__ __align__(16) uint64_t lds64[];
-    const int HS = 2 * P;                      // table slots, a power of two
     uint64_t* cp = lds64;                      // [P] compacted (node << 32 | count)
-    uint32_t* tk = (uint32_t*)(lds64 + P);     // [HS] keys, END_GROUND = empty
-    uint32_t* tc = tk + HS;                    // [HS] counts
-    const int64_t k = blockIdx.x;
-    if (k >= n) return;
+    uint32_t* tk = (uint32_t*)(lds64 + P);     // [2P] keys, END_GROUND = empty
+    uint32_t* tc = tk + 2 * P;                 // [2P] counts
+    if ((int64_t)blockIdx.x >= n) return;
+    const int64_t k = rows ? rows[blockIdx.x] : blockIdx.x;
     const int m = budget[k];
     const int64_t base = rec_off[k];
     // both scalar loads leave before the branch on m (one round trip, not two)
     asm volatile("" ::"s"(base));
     const int lane = threadIdx.x;
+    if (m > P) return;  // not this launch's row (the caller checks that none is left)
+    int HS = 128;  // table slots, a power of two >= 2m
+    while (HS < 2 * m) HS <<= 1;
     if (m == 0) {  // exact row: no walks
         if (lane == 0) {
             J[k] = 0;
@@ -506,7 +534,7 @@ __global__ __launch_bounds__(64) void k_tally_hash(int64_t n, const int32_t* __r
                 continue;
             }
             uint32_t h = (e * 0x9E3779B1u) >> (32 - hbits);
-            for (;;) {  // at most m of the 2P >= 2m slots are taken: an empty one is reached
+            for (;;) {  // at most m of the HS >= 2m slots are taken: an empty one is reached
                 const uint32_t prev = atomicCAS(&tk[h], END_GROUND, e);
                 if (prev == END_GROUND) {
                     const int at = atomicAdd(&nused, 1);
@@ -878,6 +906,24 @@ __global__ void k_gather_slots(int64_t n, const int32_t* __restrict__ slot_node,
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < n) dst[s] = src[slot_node[s]];
+}
+
+// The largest head h <= hmax (h = hmax or a multiple of 64) with h * fptr[h] <= cost:
+// fptr, the rank-ordered plan's row starts, grows with h, and so does the product.
+__global__ void k_head_bound(const int64_t* __restrict__ fptr, int64_t hmax, int64_t cost,
+                             int64_t* out)
+{
+    if (hmax * fptr[hmax] <= cost) {
+        *out = hmax;
+        return;
+    }
+    int64_t lo = 0, hi = hmax / 64;  // in units of 64 rows: lo fits, hi does not
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (64 * mid * fptr[64 * mid] <= cost) lo = mid;
+        else hi = mid;
+    }
+    *out = 64 * lo;
 }
 
 // (level, node) pairs of a rank-ordered plan, listed by slot, so a stable sort on the
@@ -1654,19 +1700,51 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         } else if (max_budget > 0) {
             int P = 64;
             while (P < max_budget) P <<= 1;
-            if (P <= 2048) {
-                const size_t lds = (size_t)P * sizeof(uint64_t) + (size_t)(4 * P) * sizeof(uint32_t);
-                k_tally_hash<<<(unsigned)n, 64, lds, s>>>(n, budget, rec_off, rec_end, rec_vis,
-                                                         rec_len, P, tJ, tG, tsteps, tvsq, hlen,
-                                                         h_end, h_cnt);
-            } else {
-                const size_t lds = (size_t)(2 * P) * sizeof(uint32_t);
-                if (lds > 64 * 1024) FAIL(SRW_E_ARG);  // budgets above 8192 walks per row
-                k_tally<<<(unsigned)n, 64, lds, s>>>(n, budget, rec_off, rec_end, rec_vis,
-                                                    rec_len, P, tJ, tG, tsteps, tvsq, hlen, h_end,
-                                                    h_cnt);
-            }
+            // Budget classes, each launched with the LDS of its largest budget so that
+            // rows with few walks keep a CU's occupancy: up to 256 walks (every row,
+            // those above skip), up to 2048 and up to 8192 (hash table, then sort),
+            // the last two over compacted row lists.
+            const int P0 = std::min(P, 256);
+            const size_t lds0 = (size_t)P0 * sizeof(uint64_t) + (size_t)(4 * P0) * sizeof(uint32_t);
+            k_tally_hash<<<(unsigned)n, 64, lds0, s>>>(n, nullptr, budget, rec_off, rec_end, rec_vis,
+                                                      rec_len, P0, tJ, tG, tsteps, tvsq, hlen,
+                                                      h_end, h_cnt);
             CHECK_HIP(hipGetLastError());
+            if (P > 256) {
+                int32_t* cflag = ALLOC(tmp, int32_t, n);
+                int64_t* cpos = ALLOC(tmp, int64_t, n);
+                int32_t* crows = ALLOC(tmp, int32_t, n);
+                void* cst = ALLOC(tmp, char, scan_tmp_bytes(n));
+                if (!cflag || !cpos || !crows || !cst) FAIL(SRW_E_NOMEM);
+                const int classes[2][2] = {{256, 2048}, {2048, 8192}};
+                for (const auto& c : classes) {
+                    if (P <= c[0]) break;
+                    k_budget_class<<<g, BLOCK, 0, s>>>(n, budget, c[0], c[1], cflag);
+                    CHECK_HIP(exclusive_scan_i32_to_i64(cflag, cpos, n, cst, s));
+                    k_scatter_rows<<<g, BLOCK, 0, s>>>(n, cflag, cpos, crows);
+                    k_read_last<<<1, 1, 0, s>>>(cpos, cflag, n, tot + 3);
+                    CHECK_HIP(hipMemcpyAsync(&pinned[4], tot + 3, sizeof(int64_t),
+                                             hipMemcpyDeviceToHost, s));
+                    CHECK_HIP(hipStreamSynchronize(s));
+                    const int64_t nc = pinned[4];
+                    if (nc == 0) continue;
+                    const int Pc = std::min(P, c[1]);
+                    if (c[1] <= 2048) {
+                        const size_t lds = (size_t)Pc * sizeof(uint64_t) +
+                                           (size_t)(4 * Pc) * sizeof(uint32_t);
+                        k_tally_hash<<<(unsigned)nc, 64, lds, s>>>(
+                            nc, crows, budget, rec_off, rec_end, rec_vis, rec_len, Pc, tJ, tG,
+                            tsteps, tvsq, hlen, h_end, h_cnt);
+                    } else {
+                        const size_t lds = (size_t)(2 * Pc) * sizeof(uint32_t);
+                        if (lds > 64 * 1024) FAIL(SRW_E_ARG);  // budgets above 8192 walks per row
+                        k_tally<<<(unsigned)nc, 64, lds, s>>>(nc, crows, budget, rec_off, rec_end,
+                                                             rec_vis, rec_len, Pc, tJ, tG, tsteps,
+                                                             tvsq, hlen, h_end, h_cnt);
+                    }
+                    CHECK_HIP(hipGetLastError());
+                }
+            }
         } else {
             CHECK_HIP(hipMemsetAsync(tJ, 0, n * sizeof(uint64_t), s));
             CHECK_HIP(hipMemsetAsync(tG, 0, n * sizeof(uint32_t), s));
@@ -1777,7 +1855,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         }
 
         // the solves' dense head (single builds): the lowest-ranked rows
-        const int64_t head =
+        int64_t head =
             (batch || asym || rule || opt.head_rows < 0)
                 ? 0
                 : std::min<int64_t>(n, head_rows_fit(opt.head_rows == 0 ? HEAD_DEFAULT
@@ -1817,6 +1895,17 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             k_copy_i32<<<g, BLOCK, 0, s>>>(n, F->by_rank, F->slot_node);
             k_copy_i32<<<g, BLOCK, 0, s>>>(n, F->rank, F->node_slot);
             CHECK_HIP(relabel(F->yptr, F->ycol, F->yval, F->fptr, F->fcol, F->fval));
+            if (head > 0) {
+                // the head's inverse costs about head x (its entries) / 4 entry reads:
+                // keep that within HEAD_COST (long rows, e.g. from large per-row
+                // budgets, shorten the head)
+                int64_t* hb = ALLOC(tmp, int64_t, 1);
+                if (!hb) FAIL(SRW_E_NOMEM);
+                k_head_bound<<<1, 1, 0, s>>>(F->fptr, head, HEAD_COST, hb);
+                CHECK_HIP(hipMemcpyAsync(&pinned[0], hb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+                CHECK_HIP(hipStreamSynchronize(s));
+                head = pinned[0];
+            }
         } else {
             CHECK_HIP(hipMemsetAsync(F->fptr, 0, sizeof(int64_t), s));
             CHECK_HIP(hipMemsetAsync(F->bptr, 0, sizeof(int64_t), s));

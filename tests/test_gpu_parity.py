@@ -438,6 +438,21 @@ def test_maximum_budget_row(srw):
     compare_walks(srw, A, 5, 3, budget=budget)
 
 
+def test_budget_classes_bit_exact(srw):
+    # budgets on both sides of every tally class boundary (256, 2048), rows of every
+    # class scattered over the matrix, so that each class runs over a row list
+    A = W.config_grid2d_32(2)
+    rng = np.random.default_rng(11)
+    budget = rng.integers(1, 64, A.n).astype(np.int32)
+    picks = rng.choice(A.n, 24, replace=False)
+    budget[picks] = [255, 256, 257, 258, 511, 1000, 2047, 2048, 2049, 2050, 3000, 4095,
+                     4096, 4097, 6000, 8191, 8192, 300, 700, 1500, 1999, 2500, 5000, 7777]
+    compare_walks(srw, A, 5, 6, budget=budget)
+    # the middle class alone (no row above 2048)
+    budget[budget > 2048] = 2048
+    compare_walks(srw, A, 5, 6, budget=budget)
+
+
 @pytest.mark.parametrize("name,delta,max_walks", [("grid2d_32", 0.2, 8192), ("random_3000", 0.3, 8192),
                                                   ("grid2d_37x29", 0.02, 100)])
 def test_adaptive_budgets_bit_exact(srw, name, delta, max_walks):

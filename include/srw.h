@@ -128,7 +128,9 @@ typedef struct {
                                   0 (default) = min(n, 4096); -1 = none; 1..16384 =
                                   min(n, that), lowered in steps of 64 rows where a
                                   workgroup's LDS cannot hold one column of the
-                                  head's values (8 B per row).  Single builds only
+                                  head's values (8 B per row), and where the head's
+                                  rows times its entries pass 2^33 (long rows, e.g.
+                                  from large per-row budgets).  Single builds only
                                   (batched and two-game builds take none).  Results
                                   agree with the substitution to rounding            */
 } srw_options;
@@ -216,6 +218,7 @@ typedef struct {
     int32_t reuse;         /* srw_options.reuse of the build                        */
     int32_t two_game;      /* 1 for a factor of srw_build_factor_ldu                */
     int32_t walk_waves;    /* waves per CU the walk kernel ran (0: no walks)        */
+    int64_t head_rows;     /* rows of the solves' dense head (0: none)              */
 } srw_stats;
 
 /* Counters and (if profiled) phase times of a factor; host output. */

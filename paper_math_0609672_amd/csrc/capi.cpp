@@ -254,6 +254,7 @@ int srw_factor_stats(const srw_factor* F, srw_stats* out)
     out->reuse = F->reuse;
     out->two_game = F->tgame ? 1 : 0;
     out->walk_waves = F->walk_waves;
+    out->head_rows = F->head;
     return SRW_OK;
 }
 

@@ -97,6 +97,9 @@ namespace srw {
 
 // rows of the triangular solves' dense head when srw_options.head_rows is 0
 constexpr int64_t HEAD_DEFAULT = 4096;
+// bound on head rows x head entries (the inverse's work grows with it): about six
+// times that of the 128^3 grid's default head (4,096 rows, 0.32M entries, 1.6 ms)
+constexpr int64_t HEAD_COST = (int64_t)8 << 30;
 
 // Device allocation tracked by an owner list (freed together).  With a stream the
 // blocks come from the stream-ordered pool (hipMallocAsync / hipFreeAsync), so the

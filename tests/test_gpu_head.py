@@ -112,6 +112,27 @@ def test_head_with_ic0_and_noalloc(srw):
     G.free()
 
 
+def test_head_shortened_by_its_cost(srw):
+    """The head's inverse costs about (head rows) x (head entries); a head that would
+    pass the bound is shortened (to a multiple of 64 rows), and the preconditioner
+    still agrees with the head-less one.  A plain build reports the default head."""
+    A = grid3d(40, 7)  # 64,000 rows; 16,384 head rows would hold about 1.4M entries
+    M = srw.Matrix.from_host(A, DEV)
+    F0 = srw.build_factor(M, 256, 1e-4, 5)
+    assert F0.stats()["head_rows"] == 4096
+    F = srw.build_factor(M, 256, 1e-4, 5, head_rows=16384)
+    G = srw.build_factor(M, 256, 1e-4, 5, head_rows=-1)
+    h = F.stats()["head_rows"]
+    assert 4096 <= h < 16384 and h % 64 == 0, h
+    assert G.stats()["head_rows"] == 0
+    r = torch.as_tensor(W.rhs(A.n, seed=6), device=DEV)
+    z, zg = np_(srw.apply(F, r)), np_(srw.apply(G, r))
+    assert np.linalg.norm(z - zg) <= 1e-13 * np.linalg.norm(zg)
+    assert np.linalg.norm(np_(srw.apply(F0, r)) - zg) <= 1e-13 * np.linalg.norm(zg)
+    for X in (F0, F, G):
+        X.free()
+
+
 def test_head_rows_out_of_range_refused(srw):
     A, walks = SMALL["grid3d_12"]
     M = srw.Matrix.from_host(A, DEV)

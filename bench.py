@@ -91,9 +91,11 @@ def parse():
     ap.add_argument("--ic0", action="store_true",
                     help="time IC(0)-PCG (natural ordering) against the random-walk factor on "
                          "the workload and report the paper's Table 1 figures (C, M1, I, M2, R1)")
-    ap.add_argument("--rule", default="equal", choices=["equal", "neyman"],
+    ap.add_argument("--rule", default="sqrt", choices=["equal", "sqrt", "neyman"],
                     help="learned_128: the budget rule the network learns (equal: every row "
-                         "variance eps; neyman: least summed variance per walk step)")
+                         "variance eps; sqrt: walks in proportion to the root of the per-walk "
+                         "variance, the least summed variance per walk; neyman: least summed "
+                         "variance per walk step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, copy a buffer of this many MiB three times with an "
                          "elementwise kernel (known traffic, for scaling hardware byte counters)")

@@ -451,10 +451,11 @@ int srw_mlp_train_step_rows(float* params, float* adam_m, float* adam_v, int32_t
 /* Training set of the budget network from one matrix: the rows whose label (from
  * srw_budget_labels, float64[n], device) is finite and positive, in row order.
  * x_out float32 [count][8] = their features (srw_row_features), y_out float32[count] =
- * log(label), halved when per_step = 1 (labels per walk step: the budgets then follow
- * the square root of the label, the least summed variance per step).  x_out and y_out
- * hold n rows; *count (host) receives the rows kept.  Synchronises the stream. */
-int srw_budget_targets(const double* label, const float* features, int64_t n, int32_t per_step,
+ * log(label), halved when half = 1 (the budgets exp(prediction) / eps then follow the
+ * square root of the label: with labels per walk step, the least summed variance per
+ * step).  x_out and y_out hold n rows; *count (host) receives the rows kept.
+ * Synchronises the stream. */
+int srw_budget_targets(const double* label, const float* features, int64_t n, int32_t half,
                        float* x_out, float* y_out, int64_t* count, void* stream);
 
 /* Statistics of a training set of n >= 1 rows: mu_sd float32[16] = per-feature mean of

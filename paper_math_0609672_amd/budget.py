@@ -5,8 +5,10 @@ arithmetic runs in the library's kernels.
 A row's label is the per-walk variance of its estimates measured on a pilot factor
 (srw_budget_labels); the network learns a target from the row's features
 (srw_row_features) and a row's budget is exp(prediction) / eps (srw_mlp_budgets).
-Two rules:
+Three rules:
   "equal"   target log V_k: every row gets variance about eps;
+  "sqrt"    target (1/2) log V_k: budgets proportional to sqrt(V_k), the least summed
+            variance for a given number of walks;
   "neyman"  target (1/2) log(V_k / L_k), L_k the mean walk length: budgets
             proportional to sqrt(V_k / L_k), the least summed variance for a given
             number of walk steps.
@@ -32,7 +34,7 @@ class Model:
         return srw.mlp_forward(self.params, self.mu_sd, features)
 
 
-RULES = ("equal", "neyman")
+RULES = ("equal", "sqrt", "neyman")
 
 
 def pilot_rows(M: srw.Matrix, seed: int, walks: int, drop_tol: float, rule: str = "neyman"):
@@ -40,12 +42,11 @@ def pilot_rows(M: srw.Matrix, seed: int, walks: int, drop_tol: float, rule: str 
     from a pilot factor with `walks` walks per row."""
     if rule not in RULES:
         raise ValueError(rule)
-    per_step = rule == "neyman"
     F = srw.build_factor(M, walks, drop_tol, seed, keep=1)
-    lab = srw.budget_labels(F, per_step=per_step)
+    lab = srw.budget_labels(F, per_step=rule == "neyman")
     F.free()
     feat = srw.row_features(M, srw.ordering(M.n, seed, M.rowptr.device))
-    return srw.budget_targets(lab, feat, per_step)
+    return srw.budget_targets(lab, feat, rule != "equal")
 
 
 def init_params(seed: int, device) -> torch.Tensor:

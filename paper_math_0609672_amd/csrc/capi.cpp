@@ -463,12 +463,12 @@ int srw_mlp_train_step_rows(float* params, float* adam_m, float* adam_v, int32_t
                                n_rows, n, grad, loss, as_stream(stream));
 }
 
-int srw_budget_targets(const double* label, const float* features, int64_t n, int32_t per_step,
+int srw_budget_targets(const double* label, const float* features, int64_t n, int32_t half,
                        float* x_out, float* y_out, int64_t* count, void* stream)
 {
-    if (n < 0 || !count || (per_step != 0 && per_step != 1)) return SRW_E_ARG;
+    if (n < 0 || !count || (half != 0 && half != 1)) return SRW_E_ARG;
     if (n > 0 && (!label || !features || !x_out || !y_out)) return SRW_E_ARG;
-    return srw::budget_targets_impl(label, features, n, per_step, x_out, y_out, count,
+    return srw::budget_targets_impl(label, features, n, half, x_out, y_out, count,
                                     as_stream(stream));
 }
 

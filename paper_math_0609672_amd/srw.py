@@ -490,14 +490,14 @@ def mlp_train_step_rows(params: torch.Tensor, mu_sd: torch.Tensor, features: tor
            "srw_mlp_train_step_rows")
 
 
-def budget_targets(label: torch.Tensor, features: torch.Tensor, per_step: bool, stream=None):
+def budget_targets(label: torch.Tensor, features: torch.Tensor, half: bool, stream=None):
     """srw_budget_targets: (features, targets) of the rows with a finite positive
-    label, in row order; targets log(label), halved with per_step."""
+    label, in row order; targets log(label), halved with half."""
     n = label.shape[0]
     x = torch.empty((n, NUM_FEATURES), dtype=torch.float32, device=label.device)
     y = torch.empty(n, dtype=torch.float32, device=label.device)
     cnt = _I64(0)
-    _check(_lib.srw_budget_targets(_ptr(label), _ptr(features), int(n), 1 if per_step else 0,
+    _check(_lib.srw_budget_targets(_ptr(label), _ptr(features), int(n), 1 if half else 0,
                                    _ptr(x), _ptr(y), ctypes.byref(cnt), _stream(stream)),
            "srw_budget_targets")
     return x[:cnt.value], y[:cnt.value]

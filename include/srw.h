@@ -219,6 +219,10 @@ typedef struct {
     int32_t two_game;      /* 1 for a factor of srw_build_factor_ldu                */
     int32_t walk_waves;    /* waves per CU the walk kernel ran (0: no walks)        */
     int64_t head_rows;     /* rows of the solves' dense head (0: none)              */
+    int32_t walk_lds;      /* 1 if the walk kernel read its records from a copy in
+                              each workgroup's LDS (tables of at most the LDS one
+                              workgroup can hold, the default refill period), 0
+                              if from memory                                      */
 } srw_stats;
 
 /* Counters and (if profiled) phase times of a factor; host output. */

@@ -1544,6 +1544,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         if (n_chunks > 0) {
             WalkArgs wa{};
             wa.recs = recs;
+            wa.lds_lines = (uint32_t)(2 * n_lines);
             wa.chunks = cdesc;
             wa.bounds = bounds;
             wa.max_steps = opt.max_steps;
@@ -1557,7 +1558,21 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipGetDevice(&dev));
             CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             void (*kern)(WalkArgs) = nullptr;
-            if (reuse) {
+            // a table that fits in one workgroup's LDS is staged there (the default
+            // refill period only)
+            int lds_max = 0;
+            CHECK_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            const size_t table_bytes = (size_t)(2 * n_lines) * 64;
+            const bool lds_table = !reuse && opt.refill_period == 8 && table_bytes <= (size_t)lds_max;
+            size_t dyn_lds = 0;
+            if (lds_table) {
+                kern = bucketing ? k_walk_lds<true> : k_walk_lds<false>;
+                dyn_lds = table_bytes;
+                F->walk_lds = 1;
+                CHECK_HIP(hipFuncSetAttribute((const void*)kern,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)dyn_lds));
+            } else if (reuse) {
                 kern = bucketing ? k_walk_reuse<true> : k_walk_reuse<false>;
             } else if (bucketing) {
                 switch (opt.refill_period) {
@@ -1576,14 +1591,14 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             }
             // persistent grid of walk_waves waves per CU (at most what fits)
             int per_cu = 0;
-            CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
+            CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, dyn_lds));
             const int want = (opt.walk_waves > 0 ? opt.walk_waves : WALK_WAVES_PER_CU) / (BLOCK / 64);
             int64_t blocks = (int64_t)cus * std::max(1, std::min(per_cu, want));
             F->walk_waves = std::max(1, std::min(per_cu, want)) * (BLOCK / 64);
             blocks = std::min<int64_t>(blocks, (n_chunks + BLOCK / 64 - 1) / (BLOCK / 64));
             if (blocks < 1) blocks = 1;
             if (!reuse) {
-                hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, wa);
+                hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), dyn_lds, s, wa);
                 CHECK_HIP(hipGetLastError());
             } else {
                 wa.stack_depth = REUSE_STACK;

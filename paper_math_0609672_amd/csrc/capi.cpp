@@ -255,6 +255,7 @@ int srw_factor_stats(const srw_factor* F, srw_stats* out)
     out->two_game = F->tgame ? 1 : 0;
     out->walk_waves = F->walk_waves;
     out->head_rows = F->head;
+    out->walk_lds = F->walk_lds;
     return SRW_OK;
 }
 

@@ -21,6 +21,7 @@ struct srw_factor {
                                    // walks plus those extracted from them)
     int32_t reuse = 0;
     int32_t walk_waves = 0;  // waves per CU of the walk launch
+    int32_t walk_lds = 0;    // 1: the walk kernel read the records from LDS
     int64_t deg_sum = 0;
     double phase_ms[SRW_NUM_PHASES] = {-1, -1, -1, -1, -1, -1, -1, -1};
 

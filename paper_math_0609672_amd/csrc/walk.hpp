@@ -291,6 +291,7 @@ __global__ void k_chunks(int64_t norder, int64_t nlong, const int32_t* __restric
 
 struct WalkArgs {
     const uint4* recs;         // walk and start records, 4 x 16 bytes per line
+    uint32_t lds_lines;        // lines of recs (k_walk_lds copies them all to LDS)
     const ChunkDesc* chunks;
     const int64_t* bounds;     // NSEG + 1 segment starts
     uint64_t max_steps;
@@ -391,8 +392,9 @@ __device__ __forceinline__ void emit_walks(const WalkArgs& a, bool em, uint32_t 
 #ifndef SRW_WALK_WAVES
 #define SRW_WALK_WAVES 4  // waves per SIMD the register budget is cut for (the grid runs 2)
 #endif
+// recs: the records (a.recs, or the workgroup's copy of them in LDS)
 template <int R, bool REUSE, bool BUCKETS>
-__device__ __forceinline__ void walk_body(const WalkArgs& a)
+__device__ __forceinline__ void walk_body(const WalkArgs& a, const uint4* recs)
 {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
@@ -471,7 +473,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
                         top_vis = 1;
                         depth = 0;
                     }
-                    const uint4* lp = a.recs + (size_t)cline * 4;
+                    const uint4* lp = recs + (size_t)cline * 4;
                     r0 = lp[0];
                     r1 = lp[1];
                     r2 = lp[2];
@@ -547,7 +549,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
                 lh = h ? (uint32_t)(i + 1) : lh;
             }
             for (uint32_t l = lh ? lh : (L > 12 ? 13u : 0u); l != 0 && l <= L && !found; ++l) {
-                const uint4* lp = a.recs + ((size_t)(cline + l) * 4);
+                const uint4* lp = recs + ((size_t)(cline + l) * 4);
                 const uint4 x0 = lp[0], x1 = lp[1], x2 = lp[2], x3 = lp[3];
                 const uint32_t f[16] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w,
                                         x2.x, x2.y, x2.z, x2.w, x3.x, x3.y, x3.z, x3.w};
@@ -576,7 +578,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
             next_line = kb == 0u ? base : base + (q0 >> (32u - kb));
         }
         if (LOCK && !active) next_line = 0;
-        const uint4* lp = a.recs + (size_t)next_line * 4;
+        const uint4* lp = recs + (size_t)next_line * 4;
         r0 = lp[0];
         r1 = lp[1];
         r2 = lp[2];
@@ -679,12 +681,25 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a)
 template <int R, bool BUCKETS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_WAVES))) void k_walk(WalkArgs a)
 {
-    walk_body<R, false, BUCKETS>(a);
+    walk_body<R, false, BUCKETS>(a, a.recs);
+}
+
+// The same walks with the records staged in LDS: for a table of at most the LDS a
+// workgroup can hold (a.lds_lines lines of 64 bytes, walk and start records), every
+// workgroup first copies it, and each step then reads LDS instead of the caches.
+template <bool BUCKETS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRW_WALK_WAVES))) void k_walk_lds(WalkArgs a)
+{
+    extern __shared__ uint4 table[];
+    const int64_t words = (int64_t)a.lds_lines * 4;
+    for (int64_t i = threadIdx.x; i < words; i += BLOCK) table[i] = a.recs[i];
+    __syncthreads();
+    walk_body<8, false, BUCKETS>(a, table);
 }
 
 // walk reuse keeps the stack top in registers as well: a larger register budget
 template <bool BUCKETS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_reuse(WalkArgs a)
 {
-    walk_body<8, true, BUCKETS>(a);
+    walk_body<8, true, BUCKETS>(a, a.recs);
 }

@@ -55,7 +55,8 @@ class _Stats(ctypes.Structure):
                 ("levels_bwd", ctypes.c_int32), ("precision", ctypes.c_int32), ("keep", ctypes.c_int32),
                 ("phase_ms", ctypes.c_double * NUM_PHASES), ("tallied_walks", ctypes.c_int64),
                 ("reuse", ctypes.c_int32), ("two_game", ctypes.c_int32),
-                ("walk_waves", ctypes.c_int32), ("head_rows", ctypes.c_int64)]
+                ("walk_waves", ctypes.c_int32), ("head_rows", ctypes.c_int64),
+                ("walk_lds", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

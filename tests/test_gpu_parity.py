@@ -524,3 +524,28 @@ def test_factor_bit_exact_with_wide_rows(srw, drop):
     assert np.array_equal(got["ycol"], ref.ycol)
     assert np.array_equal(got["yval"], ref.yval)
     assert np.array_equal(got["d"], ref.d)
+
+
+@pytest.mark.parametrize("name,A,walks", [
+    ("grid2d_32", None, None),
+    ("random_50_wide", W.random_graph(50, 400, seed=5, ground_frac=0.05), 40),
+])
+def test_lds_staged_walks_bit_exact(srw, name, A, walks):
+    """Tables that fit in one workgroup's LDS are walked from an LDS copy (narrow
+    records, and wide ones with bucket lines): the records and tallies are the
+    oracle's, bit for bit."""
+    if A is None:
+        A, walks = CASES[name]
+    assert int(np.diff(A.rowptr).max()) > 7 or name == "grid2d_32"
+    F, t = compare_walks(srw, A, walks, 13)
+    assert F.stats()["walk_lds"] == 1
+
+
+def test_large_table_walks_from_memory(srw):
+    """A table larger than a workgroup's LDS is read from memory (the 12^3 grid's 3,456
+    lines of 64 bytes are 216 KiB)."""
+    A, walks = CASES["grid3d_12"]
+    M = srw.Matrix.from_host(A, DEV)
+    F = srw.build_factor(M, walks, 1e-3, 1)
+    assert F.stats()["walk_lds"] == 0
+    F.free()

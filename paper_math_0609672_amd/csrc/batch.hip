@@ -43,10 +43,65 @@ __global__ void k_stack_col(int64_t nnz, const int32_t* __restrict__ src, int32_
     if (q < nnz) dst[q] = src[q] + row_off;
 }
 
-__global__ void k_offset_i32(int64_t n, int32_t* __restrict__ x, int32_t add)
+// The batch's orderings, all at once.  Stacked row v of matrix i = node_mat[v] is node
+// v - off_i of A[i]; its sort key is the one a single-matrix build of A[i] with seed
+// seeds[i] gives that node (Philox of the node id, ties by node id).
+__global__ void k_batch_rank_keys(int64_t n, const int32_t* __restrict__ node_mat,
+                                  const int64_t* __restrict__ off,
+                                  const uint64_t* __restrict__ seed, uint64_t* __restrict__ keys,
+                                  uint32_t* __restrict__ vals)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t i = node_mat[v];
+    const u64x4 b = philox4x64_10(0, 0, (uint64_t)(v - off[i]), STREAM_ORDER, seed[i], 0);
+    keys[v] = b.x0;
+    vals[v] = (uint32_t)v;
+}
+
+// rows sorted by their key, keyed again by their matrix (a stable sort on it gives the
+// rows of every matrix in its own order)
+__global__ void k_batch_mat_keys(int64_t n, const uint32_t* __restrict__ rows,
+                                 const int32_t* __restrict__ node_mat, uint32_t* __restrict__ keys,
+                                 uint32_t* __restrict__ vals)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    keys[p] = (uint32_t)node_mat[rows[p]];
+    vals[p] = rows[p];
+}
+
+// Position p of the (matrix, own order) list holds the row of local rank r = p - off_i,
+// whose stacked rank is p.  For the dependency-level pass the matrices are
+// interleaved: that row's key is floor(r 2^32 / n_i), then the matrix, so every
+// matrix's rows keep their order and the passes over all matrices advance together
+// (in stacked rank order one matrix's chain would hold up the next one's).
+__global__ void k_batch_mix_keys(int64_t n, const uint32_t* __restrict__ rows,
+                                 const int32_t* __restrict__ node_mat,
+                                 const int64_t* __restrict__ off, uint64_t* __restrict__ keys,
+                                 uint32_t* __restrict__ vals)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t v = rows[p];
+    const int32_t i = node_mat[v];
+    const uint64_t r = (uint64_t)(p - off[i]);
+    const uint64_t ni = (uint64_t)(off[i + 1] - off[i]);
+    keys[p] = ((r << 32) / ni) << 32 | (uint32_t)i;
+    vals[p] = (uint32_t)p;  // the row's stacked rank, i.e. its slot in the rank order
+}
+
+__global__ void k_batch_rank_scatter(int64_t n, const uint32_t* __restrict__ rows,
+                                     int32_t* __restrict__ rank)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) rank[rows[p]] = (int32_t)p;
+}
+
+__global__ void k_copy_u32_i32(int64_t n, const uint32_t* __restrict__ a, int32_t* __restrict__ b)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] += add;
+    if (i < n) b[i] = (int32_t)a[i];
 }
 
 // matrix of every stacked row: the last matrix whose first row is <= the row
@@ -504,23 +559,71 @@ int build_batched_impl(int32_t nmat, const srw_csr* A, int32_t walks_per_row, do
         e = hipGetLastError();
     }
     if (e != hipSuccess) return fail(hip_fail(e, "batched stacking"));
-    // one random ordering per matrix (its own seed), shifted into the stacked order
-    for (int32_t i = 0; i < nmat; ++i) {
-        const int64_t n = A[i].n;
-        if (n == 0) continue;
-        int st = ordering_impl(n, seeds[i], rank + off[i], s);
-        if (st) return fail(st);
-        k_offset_i32<<<grid_for(n, BLOCK), BLOCK, 0, s>>>(n, rank + off[i], (int32_t)off[i]);
+    // one random ordering per matrix (its own seed), shifted into the stacked order:
+    // all rows sorted by their key, then stably by their matrix; then the matrices
+    // interleaved for the dependency-level pass
+    int32_t* level_order = nullptr;
+    if (N > 0) {
+        char* ws = nullptr;
+        const size_t rt = radix_tmp_bytes(N);
+        const size_t bytes = (size_t)N * (2 * sizeof(uint64_t) + 4 * sizeof(uint32_t)) + rt + 256;
+        if ((e = hipMallocAsync((void**)&ws, bytes, s)) != hipSuccess)
+            return fail(hip_fail(e, "batched ordering"));
+        if ((e = hipMallocAsync((void**)&level_order, (size_t)N * sizeof(int32_t), s)) != hipSuccess) {
+            (void)hipFreeAsync(ws, s);
+            return fail(hip_fail(e, "batched ordering"));
+        }
+        uint64_t* k64 = (uint64_t*)ws;
+        uint64_t* k64b = k64 + N;
+        uint32_t* v1 = (uint32_t*)(k64b + N);
+        uint32_t* v2 = v1 + N;
+        uint32_t* k32 = v2 + N;
+        uint32_t* k32b = k32 + N;
+        void* tmp = (void*)(((uintptr_t)(k32b + N) + 255) & ~(uintptr_t)255);
+        uint64_t* ko = nullptr;
+        uint32_t* ko32 = nullptr;
+        uint32_t* vo = nullptr;
+        const int g = grid_for(N, BLOCK);
+        int mbits = 1;
+        while (mbits < 32 && ((int64_t)1 << mbits) < nmat) ++mbits;
+        k_batch_rank_keys<<<g, BLOCK, 0, s>>>(N, node_mat, mat_off, mat_seed, k64, v1);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = radix_sort_u64(k64, v1, k64b, v2, N, 64, tmp, &ko, &vo, s);
+        if (e == hipSuccess) {
+            uint32_t* rows = vo;
+            uint32_t* other = rows == v1 ? v2 : v1;
+            k_batch_mat_keys<<<g, BLOCK, 0, s>>>(N, rows, node_mat, k32, other);
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = radix_sort_u32(k32, other, k32b, rows, N, mbits, tmp, &ko32, &vo, s);
+        }
+        if (e == hipSuccess) {
+            uint32_t* rows = vo;  // rows by (matrix, own order): position = stacked rank
+            uint32_t* other = rows == v1 ? v2 : v1;
+            k_batch_rank_scatter<<<g, BLOCK, 0, s>>>(N, rows, rank);
+            k_batch_mix_keys<<<g, BLOCK, 0, s>>>(N, rows, node_mat, mat_off, k64, other);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = radix_sort_u64(k64, other, k64b, rows, N, 64, tmp, &ko, &vo, s);
+        }
+        if (e == hipSuccess) {
+            k_copy_u32_i32<<<g, BLOCK, 0, s>>>(N, vo, level_order);
+            e = hipGetLastError();
+        }
+        (void)hipFreeAsync(ws, s);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(level_order, s);
+            return fail(hip_fail(e, "batched ordering"));
+        }
     }
-    if ((e = hipGetLastError()) != hipSuccess) return fail(hip_fail(e, "batched ordering"));
     srw_options opt = *opt_in;
     opt.ordering = SRW_ORDER_GIVEN;
     opt.rank = rank;
     if (opt.solve_order == 2) opt.solve_order = 1;  // the batched solves need the levels
     srw_csr cat{N, NNZ, rowptr, col, val};
-    BatchKeys keys{node_mat, mat_off, mat_seed};
+    BatchKeys keys{node_mat, mat_off, mat_seed, level_order};
     srw_factor* F = nullptr;
     const int st = build_factor_impl(&cat, walks_per_row, drop_tol, 0, &opt, &F, s, &keys);
+    if (level_order) (void)hipFreeAsync(level_order, s);
     if (st != SRW_OK) return fail(st);
     F->nmat = nmat;
     F->mat_off_host = off;

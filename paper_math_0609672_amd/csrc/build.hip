@@ -1935,7 +1935,7 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             void* rt = ALLOC(tmp, char, radix_tmp_bytes(n));
             if (!lev || !lkey || !lkey2 || !lval || !lval2 || !rt) FAIL(SRW_E_NOMEM);
             int32_t depth = 0;
-            status = dag_levels(F, lev, &depth, s);
+            status = dag_levels(F, lev, &depth, s, batch ? batch->level_order : nullptr);
             if (status) goto done;
             F->depth = depth;
             k_level_keys<<<g, BLOCK, 0, s>>>(n, head, F->slot_node, lev, lkey, lval);

@@ -160,6 +160,9 @@ struct BatchKeys {
     const int32_t* node_mat;
     const int64_t* mat_off;
     const uint64_t* mat_seed;
+    // the slots in the order the dependency-level pass takes them: the matrices
+    // interleaved (each in its own order), so that their chains advance together
+    const int32_t* level_order;
 };
 
 // Walks-only build: apply the Section 5.1 stopping rule to every row's walks and
@@ -203,7 +206,10 @@ int64_t head_rows_fit(int64_t h);
 int apply_noalloc_impl(const srw_factor* F, const double* r, double* z, hipStream_t s);
 int dag_depth(srw_factor* F, int32_t* depth_out, hipStream_t s);
 // Dependency level of every slot of the plan (lev, caller-allocated [n]) and the depth.
-int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s);
+// order: the slots in the order the pass takes them (NULL: slot order); every slot's
+// columns must precede it in that order
+int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s,
+               const int32_t* order = nullptr);
 void free_factor(srw_factor* F);
 int ordering_impl(int64_t n, uint64_t seed, int32_t* rank, hipStream_t s);
 int build_batched_impl(int32_t nmat, const srw_csr* A, int32_t walks_per_row, double drop_tol,

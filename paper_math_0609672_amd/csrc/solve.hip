@@ -335,9 +335,12 @@ __global__ __launch_bounds__(BLOCK) void k_trsv(int64_t n, int64_t h, const int6
 }
 
 // Dependency level of every slot over the forward plan: lev_s = 1 + the largest
-// level among the row's columns, 0 for an empty row; the same scheme as k_trsv.
+// level among the row's columns, 0 for an empty row; the same scheme as k_trsv.  The
+// waves take the slots order[0], order[1], ... in turn (slot order when order is
+// NULL); every slot's columns precede it in that sequence.
 // Each wave keeps the largest level it met; one atomic per wave gives the depth.
-__global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int64_t* __restrict__ ptr,
+__global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int32_t* __restrict__ order,
+                                                  const int64_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ col, int32_t* lev,
                                                   int* depth, int* err, int64_t ticks)
 {
@@ -347,7 +350,8 @@ __global__ __launch_bounds__(BLOCK) void k_levels(int64_t n, const int64_t* __re
     const int64_t wid =
         (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int wmax = 0;
-    for (int64_t s = wid; s < n; s += nw) {
+    for (int64_t i = wid; i < n; i += nw) {
+        const int64_t s = order ? (int64_t)order[i] : i;
         int m = -1;
         for (int64_t qb = ptr[s]; qb < ptr[s + 1]; qb += 64) {
             const int64_t q = qb + lane;
@@ -847,7 +851,8 @@ int apply_noalloc_impl(const srw_factor* F, const double* r, double* z, hipStrea
     return SRW_OK;
 }
 
-int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s)
+int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s,
+               const int32_t* order)
 {
     int64_t n = F->n;
     *depth_out = 0;
@@ -865,7 +870,7 @@ int dag_levels(srw_factor* F, int32_t* lev, int32_t* depth_out, hipStream_t s)
         const int64_t* ptr = F->fptr;
         const int32_t* col = F->fcol;
         int64_t ticks = wait_ticks(5.0);
-        void* args[] = {&n, &ptr, &col, &lev, &depth, &err, &ticks};
+        void* args[] = {&n, &order, &ptr, &col, &lev, &depth, &err, &ticks};
         e = coop_launch(k_levels, n, args, s);
     }
     int host[2] = {0, 0};

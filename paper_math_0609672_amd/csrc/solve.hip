@@ -549,8 +549,8 @@ hipError_t coop_launch(K kernel, int64_t rows, void** args, hipStream_t s)
     if (e != hipSuccess) return e;
     // The waits need every wave resident at once.  The runtime's occupancy is not
     // always met in full (a kernel reported at 8 workgroups per CU was measured running
-    // 7 together), so the grid takes three quarters of it.
-    int64_t blocks = (int64_t)cus * std::max(1, per_cu * 3 / 4);
+    // 7 together), so the grid leaves one workgroup in eight unused.
+    int64_t blocks = (int64_t)cus * std::max(1, per_cu * 7 / 8);
     blocks = std::min<int64_t>(blocks, (rows + BLOCK / 64 - 1) / (BLOCK / 64));
     if (blocks < 1) blocks = 1;
     return hipLaunchCooperativeKernel((const void*)kernel, dim3((unsigned)blocks), dim3(BLOCK),

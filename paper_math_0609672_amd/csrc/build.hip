@@ -824,8 +824,11 @@ __global__ void k_desc_lens(int64_t n, const int32_t* __restrict__ by_rank,
 }
 
 // Sixteen lanes per row (rows of Y hold about twenty entries), entries strided by 16.
+// The column field is the column's node, or its rank when col_rank is given (the rows
+// of Y^T then come out in rank order, the solve slots of a rank-ordered plan).
 __global__ void k_entry_keys(int64_t n, const int32_t* __restrict__ by_rank,
                              const int64_t* __restrict__ yptr, const int32_t* __restrict__ ycol,
+                             const int32_t* __restrict__ col_rank,
                              const int64_t* __restrict__ doff, uint32_t* idx, uint64_t* key)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -835,7 +838,8 @@ __global__ void k_entry_keys(int64_t n, const int32_t* __restrict__ by_rank,
     const int64_t b = yptr[k], e = yptr[k + 1], o = doff[r] - b;
     for (int64_t q = b + (t & 15); q < e; q += 16) {
         idx[o + q] = (uint32_t)q;
-        key[o + q] = ((uint64_t)r << 32) | (uint32_t)ycol[q];
+        const int32_t c = col_rank ? col_rank[ycol[q]] : ycol[q];
+        key[o + q] = ((uint64_t)r << 32) | (uint32_t)c;
     }
 }
 
@@ -852,6 +856,22 @@ __global__ void k_transpose_fill(int64_t nnz, int64_t n, const uint64_t* __restr
     const int64_t r = (int64_t)(sorted_key[j] >> 32);
     ytcol[j] = by_rank[n - 1 - r];
     ytval[j] = yval[sorted_idx[j]];
+}
+
+// The same for a rank-ordered plan, sorted on the column's rank: the entries land in
+// the rows of Y^T by slot, the source row's slot (its rank) being n - 1 minus the
+// key's position field.
+template <typename T>
+__global__ void k_transpose_fill_slots(int64_t nnz, int64_t n,
+                                       const uint64_t* __restrict__ sorted_key,
+                                       const uint32_t* __restrict__ sorted_idx,
+                                       const T* __restrict__ yval, int32_t* __restrict__ bcol,
+                                       T* __restrict__ bval)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nnz) return;
+    bcol[j] = (int32_t)(n - 1 - (int64_t)(sorted_key[j] >> 32));
+    bval[j] = yval[sorted_idx[j]];
 }
 
 __global__ void k_set_last(int64_t* ptr, int64_t n, int64_t v) { ptr[n] = v; }
@@ -1829,12 +1849,23 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             if (herr) FAIL(map_err(herr));
         }
 
-        // ---- 7. Y^T by a stable sort of the entries on their column, then the plan
+        // ---- 7. Y^T by a stable sort of the entries on their column, then the plan.
+        // A rank-ordered plan (no level sort) sorts on the column's rank and fills its
+        // rows of Y^T by slot straight from the sorted entries; the level order sorts
+        // on the column's node, and the rows are relabelled once the slots are known.
         mark(7);
-        int64_t* ytptr = ALLOC(tmp, int64_t, n + 1);
-        int32_t* ytcol = ALLOC(tmp, int32_t, nnz_y);
-        void* ytval = ALLOC(tmp, char, nnz_y * vbytes);
-        if (!ytptr || !ytcol || !ytval) FAIL(SRW_E_NOMEM);
+        const bool bt_direct = opt.solve_order != 1;
+        int64_t* ytptr = nullptr;
+        int32_t* ytcol = nullptr;
+        void* ytval = nullptr;
+        if (!bt_direct) {
+            ytptr = ALLOC(tmp, int64_t, n + 1);
+            ytcol = ALLOC(tmp, int32_t, nnz_y);
+            ytval = ALLOC(tmp, char, nnz_y * vbytes);
+            if (!ytptr || !ytcol || !ytval) FAIL(SRW_E_NOMEM);
+        }
+        uint64_t* yt_key = nullptr;  // sorted (listing position << 32 | column field)
+        uint32_t* yt_idx = nullptr;  // and the entry each came from
         {
             uint32_t* idx = ALLOC(tmp, uint32_t, nnz_y);
             uint32_t* idx2 = ALLOC(tmp, uint32_t, nnz_y);
@@ -1849,23 +1880,27 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             if (!dlen || !doff) FAIL(SRW_E_NOMEM);
             k_desc_lens<<<g, BLOCK, 0, s>>>(n, F->by_rank, F->yptr, dlen);
             CHECK_HIP(exclusive_scan_i32_to_i64(dlen, doff, n, st, s));
-            k_entry_keys<<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(n, F->by_rank, F->yptr, F->ycol,
-                                                                   doff, idx, key);
+            k_entry_keys<<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(
+                n, F->by_rank, F->yptr, F->ycol, bt_direct ? F->rank : nullptr, doff, idx, key);
             uint64_t* ko;
             uint32_t* vo;
             // stable on the column bits only: the listing order supplies the rank order
             CHECK_HIP(radix_sort_u64(key, idx, key2, idx2, nnz_y, rbits, rt, &ko, &vo, s));
-            // rows of Y^T: where each column's run of sorted keys begins
-            k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, nnz_y, ytptr, 0,
-                                                                 (1ull << 32) - 1ull);
-            if (fp32)
-                k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, n, ko, vo, F->by_rank, (const float*)F->yval, ytcol,
-                    (float*)ytval);
-            else
-                k_transpose_fill<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
-                    nnz_y, n, ko, vo, F->by_rank, (const double*)F->yval, ytcol,
-                    (double*)ytval);
+            yt_key = ko;
+            yt_idx = vo;
+            if (!bt_direct) {
+                // rows of Y^T: where each column's run of sorted keys begins
+                k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, nnz_y, ytptr, 0,
+                                                                     (1ull << 32) - 1ull);
+                if (fp32)
+                    k_transpose_fill<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
+                        nnz_y, n, ko, vo, F->by_rank, (const float*)F->yval, ytcol,
+                        (float*)ytval);
+                else
+                    k_transpose_fill<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
+                        nnz_y, n, ko, vo, F->by_rank, (const double*)F->yval, ytcol,
+                        (double*)ytval);
+            }
             CHECK_HIP(hipGetLastError());
         }
 
@@ -1949,7 +1984,21 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(relabel(F->yptr, F->ycol, F->yval, F->fptr, F->fcol, F->fval));
         }
         if (n > 0) {
-            CHECK_HIP(relabel(ytptr, ytcol, ytval, F->bptr, F->bcol, F->bval));
+            if (bt_direct) {
+                // slots are ranks: the sorted entries are already the rows of Y^T by slot
+                k_row_begin<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, yt_key, nnz_y, F->bptr, 0,
+                                                                     (1ull << 32) - 1ull);
+                if (fp32)
+                    k_transpose_fill_slots<float><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
+                        nnz_y, n, yt_key, yt_idx, (const float*)F->yval, F->bcol,
+                        (float*)F->bval);
+                else
+                    k_transpose_fill_slots<double><<<grid_for(nnz_y, BLOCK), BLOCK, 0, s>>>(
+                        nnz_y, n, yt_key, yt_idx, (const double*)F->yval, F->bcol,
+                        (double*)F->bval);
+            } else {
+                CHECK_HIP(relabel(ytptr, ytcol, ytval, F->bptr, F->bcol, F->bval));
+            }
             if (fp32)
                 k_gather_slots<float><<<g, BLOCK, 0, s>>>(n, F->slot_node, (const float*)F->d,
                                                           (float*)F->dslot);

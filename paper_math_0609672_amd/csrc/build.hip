@@ -766,7 +766,7 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
             }
         }
         if (FILL) dout[k] = (T)(((double)M * a) / (double)J[k]);
-        else ynnz[k] = (int32_t)kept;
+        if (ynnz) ynnz[k] = (int32_t)kept;
         return;
     }
     for (;;) {
@@ -802,8 +802,36 @@ __global__ void k_factor(int64_t n, const int64_t* __restrict__ rowptr,
             dk = a / (1.0 + tk * (mbar - 1.0));
         }
         dout[k] = (T)dk;
-    } else {
-        ynnz[k] = (int32_t)kept;
+    }
+    if (ynnz) ynnz[k] = (int32_t)kept;
+}
+
+// Room for row k of Y before the drop: its neighbours other than itself (the
+// lower-ranked ones are a subset) plus the distinct end nodes of its walks.
+__global__ void k_factor_caps(int64_t n, const int64_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ budget, const int32_t* __restrict__ hlen,
+                              int32_t* __restrict__ cap)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    cap[k] = (int32_t)(rowptr[k + 1] - rowptr[k] - 1) + (budget[k] ? hlen[k] : 0);
+}
+
+// The rows written at their padded offsets, packed into the factor's CSR; sixteen
+// lanes per row.
+template <typename T>
+__global__ void k_pack_rows(int64_t n, const int64_t* __restrict__ pad_off,
+                            const int64_t* __restrict__ yptr, const int32_t* __restrict__ ynnz,
+                            const int32_t* __restrict__ pcol, const T* __restrict__ pval,
+                            int32_t* __restrict__ ycol, T* __restrict__ yval)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = t >> 4;
+    if (k >= n) return;
+    const int64_t a = pad_off[k], b = yptr[k];
+    for (int32_t j = (int32_t)(t & 15); j < ynnz[k]; j += 16) {
+        ycol[b + j] = pcol[a + j];
+        yval[b + j] = pval[a + j];
     }
 }
 
@@ -1794,14 +1822,33 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             CHECK_HIP(hipMemcpyAsync(&pinned[4], ssum, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         }
 
-        // ---- 6. factor
+        // ---- 6. factor: one pass writes every row at an offset padded to an upper
+        // bound of its length (and the row's length), then the rows are packed
         int32_t* ynnz = ALLOC(tmp, int32_t, n);
-        if (!ynnz) FAIL(SRW_E_NOMEM);
+        int32_t* pcap = ALLOC(tmp, int32_t, n);
+        int64_t* pad_off = ALLOC(tmp, int64_t, n + 1);
+        if (!ynnz || !pcap || !pad_off) FAIL(SRW_E_NOMEM);
         mark(6);
-        k_factor<double, false><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
-                                                    budget, tJ, h_off, hlen, h_end, h_cnt,
-                                                    drop_tol, plain ? 1 : 0, ynnz, nullptr,
-                                                    nullptr, nullptr, nullptr);
+        k_factor_caps<<<g, BLOCK, 0, s>>>(n, A->rowptr, budget, hlen, pcap);
+        CHECK_HIP(exclusive_scan_i32_to_i64(pcap, pad_off, n, st, s));
+        k_read_last<<<1, 1, 0, s>>>(pad_off, pcap, n, tot + 2);
+        CHECK_HIP(hipMemcpyAsync(&pinned[2], tot + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        const int64_t cap_total = pinned[2];
+        F->d = ALLOC(keep, char, n * vbytes);
+        int32_t* pcol = ALLOC(tmp, int32_t, std::max<int64_t>(cap_total, 1));
+        void* pval = ALLOC(tmp, char, std::max<int64_t>(cap_total, 1) * vbytes);
+        if (!F->d || !pcol || !pval) FAIL(SRW_E_NOMEM);
+        if (fp32)
+            k_factor<float, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
+                                                     budget, tJ, h_off, hlen, h_end, h_cnt,
+                                                     drop_tol, plain ? 1 : 0, ynnz, pad_off, pcol,
+                                                     (float*)pval, (float*)F->d);
+        else
+            k_factor<double, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
+                                                      budget, tJ, h_off, hlen, h_end, h_cnt,
+                                                      drop_tol, plain ? 1 : 0, ynnz, pad_off, pcol,
+                                                      (double*)pval, (double*)F->d);
         CHECK_HIP(exclusive_scan_i32_to_i64(ynnz, F->yptr, n, st, s));
         k_read_last<<<1, 1, 0, s>>>(F->yptr, ynnz, n, tot + 0);
         CHECK_HIP(hipMemcpyAsync(&pinned[0], tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1813,18 +1860,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
         k_set_last<<<1, 1, 0, s>>>(F->yptr, n, nnz_y);
         F->ycol = ALLOC(keep, int32_t, nnz_y);
         F->yval = ALLOC(keep, char, nnz_y * vbytes);
-        F->d = ALLOC(keep, char, n * vbytes);
-        if (!F->ycol || !F->yval || !F->d) FAIL(SRW_E_NOMEM);
+        if (!F->ycol || !F->yval) FAIL(SRW_E_NOMEM);
         if (fp32)
-            k_factor<float, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
-                                                     budget, tJ, h_off, hlen, h_end, h_cnt,
-                                                     drop_tol, plain ? 1 : 0, nullptr, F->yptr,
-                                                     F->ycol, (float*)F->yval, (float*)F->d);
+            k_pack_rows<float><<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(
+                n, pad_off, F->yptr, ynnz, pcol, (const float*)pval, F->ycol, (float*)F->yval);
         else
-            k_factor<double, true><<<g, BLOCK, 0, s>>>(n, A->rowptr, A->col, A->val, F->rank, tau,
-                                                      budget, tJ, h_off, hlen, h_end, h_cnt,
-                                                      drop_tol, plain ? 1 : 0, nullptr, F->yptr,
-                                                      F->ycol, (double*)F->yval, (double*)F->d);
+            k_pack_rows<double><<<grid_for(16 * n, BLOCK), BLOCK, 0, s>>>(
+                n, pad_off, F->yptr, ynnz, pcol, (const double*)pval, F->ycol, (double*)F->yval);
         CHECK_HIP(hipGetLastError());
 
         if (ic0 && n > 0) {

@@ -385,14 +385,29 @@ int srw_batch_info(const srw_factor* F, int32_t* nmat, int64_t* row_off);
  * tolerance restarts from it (at most 3 restarts).  Dot products are reduced per
  * system in a fixed order; the triangular solves carry the nrhs values of a row
  * together.  use_graph = 1 captures one iteration in a HIP graph and replays it.  On
- * first use for a problem shape the solve schedule is picked by timing 2 and 1 blocks
- * per CU with 16, 32 and 64 rows per work claim, and kept for the process.
+ * first use for a problem shape the solve schedule is picked by timing the
+ * level-by-level substitutions (one launch per dependency level; batched factors are
+ * level-ordered) and the sync-free ones at 2 and 1 blocks per CU with 16, 32 and 64
+ * rows per work claim, and kept for the process.
  * Host outputs (may be NULL): iters int32[nmat * nrhs] and rel_residual
  * float64[nmat * nrhs] (true residuals), system (i, j) at i * nrhs + j.  Returns SRW_OK
  * or SRW_NOT_CONVERGED (some system missed tol within max_iter). */
 int srw_pcg_solve_batched(srw_factor* F, int32_t nrhs, const double* B, double tol,
                           int32_t max_iter, double* X, int32_t* iters, double* rel_residual,
                           int32_t use_graph, void* stream);
+
+/* One application of the preconditioner to every system of a batched factor: for each
+ * matrix i and right-hand side j, z = (Y^T D Y)^{-1} r (Algorithm 1's M applied by a
+ * backward then a forward substitution, Section 2.2.2).  R, Z: device float64
+ * [N][nrhs] row-major over the stacked rows (1 <= nrhs <= 8), caller-owned; R is read,
+ * Z written.  schedule: 0 = the one srw_pcg_solve_batched tuned for this shape (else
+ * level by level), 1 = the sync-free substitutions (2 blocks per CU, 16-row claims),
+ * 2 = level by level.  Every schedule sums a row's entries in the same order, so all
+ * give the same bits.  Allocates a workspace of 2 N nrhs factor values on the stream
+ * and synchronises the stream.  Returns SRW_OK, SRW_E_ARG (not a batched factor, nrhs
+ * or schedule out of range), or SRW_E_HIP (a sync-free solve gave up waiting). */
+int srw_apply_batched(srw_factor* F, int32_t nrhs, const double* R, double* Z, int32_t schedule,
+                      void* stream);
 
 /* ---- learned walk budgets (an extension: the paper sets walks per row by a
  * stopping rule on walk lengths, Section 5.1) ------------------------------------ */

@@ -508,6 +508,62 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs, int32
     }
 }
 
+// Level-by-level substitution: one launch per dependency level of a level-ordered
+// plan, over the level's slots [a, b).  Every value a row reads was written by an
+// earlier launch, so there is no waiting and no flag.  A row takes RG lanes and its
+// entries and partial sums go exactly as in k_trsv_multi (lane j: entries j, j + RG,
+// ..., a zero product where a round runs past the row; then the butterfly), so both
+// kernels give the same bits.  Lane j of a row writes right-hand side j.
+template <typename T, bool FWD>
+__global__ __launch_bounds__(BLOCK) void k_trsv_level(int64_t a, int64_t b, int nrhs,
+                                                      const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const T* __restrict__ val,
+                                                      const T* __restrict__ dslot,
+                                                      const int32_t* __restrict__ slot_node,
+                                                      const double* __restrict__ rhs,
+                                                      const T* __restrict__ w, T* __restrict__ sol,
+                                                      double* __restrict__ out)
+{
+    const int64_t s = a + ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / RG;
+    const int j = (int)(threadIdx.x % RG);
+    const bool row = s < b;
+    T acc[MAXR];
+#pragma unroll
+    for (int jr = 0; jr < MAXR; ++jr) acc[jr] = T(0);
+    if (row) {
+        const int64_t q0 = ptr[s], q1 = ptr[s + 1];
+        for (int64_t qb = q0; qb < q1; qb += RG) {
+            const int64_t q = qb + j;
+            const bool ok = q < q1;
+            const int32_t c = ok ? col[q] : 0;
+            const T av = ok ? val[q] : T(0);
+            const T* src = sol + (int64_t)c * nrhs;
+#pragma unroll
+            for (int jr = 0; jr < MAXR; ++jr) {
+                const T x = (ok && jr < nrhs) ? src[jr] : T(0);
+                acc[jr] += av * x;
+            }
+        }
+    }
+    T v = T(0);
+#pragma unroll
+    for (int jr = 0; jr < MAXR; ++jr) {
+        T t = acc[jr];
+        t += __shfl_xor(t, 4, 64);
+        t += __shfl_xor(t, 2, 64);
+        t += __shfl_xor(t, 1, 64);
+        v = jr == j ? t : v;
+    }
+    if (row && j < nrhs) {
+        const int32_t node = slot_node[s];
+        const T base_v = FWD ? w[s * nrhs + j] / dslot[s] : (T)rhs[(int64_t)node * nrhs + j];
+        const T x = base_v - v;
+        sol[s * nrhs + j] = x;
+        if (out) out[(int64_t)node * nrhs + j] = (double)x;
+    }
+}
+
 int fill_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(grid_for(n, BLOCK), 1), 2048); }
 
 }  // namespace
@@ -653,10 +709,12 @@ struct BatchWork {
     int64_t* mat_tile = nullptr;
 };
 
-// Solve schedule: blocks per CU of the launch grid and slots per claim.
+// Solve schedule: blocks per CU of the launch grid and slots per claim, or (level)
+// one launch per dependency level.
 struct Sched {
     int per_cu = 0;  // 0: not tuned
     int chunk = 0;
+    int level = 0;
 };
 
 // Stream-ordered launch of a persistent grid of up to per_cu_cap blocks per CU (the
@@ -687,6 +745,26 @@ hipError_t batch_apply(const srw_factor* F, BatchWork& W, const Sched& sc, hipSt
     int64_t ticks = W.wait_ticks;
     T* work = (T*)W.work;
     T* sol = work + n * nrhs;
+    if (sc.level) {
+        const std::vector<int64_t>& lp = F->level_ptr;
+        const int L = (int)lp.size() - 1;
+        const int64_t per_block = BLOCK / RG;
+        for (int l = L - 1; l >= 0; --l) {  // backward: the levels in reverse
+            const int64_t a = lp[l], b = lp[l + 1];
+            if (b <= a) continue;
+            k_trsv_level<T, false><<<(unsigned)((b - a + per_block - 1) / per_block), BLOCK, 0, s>>>(
+                a, b, nrhs, F->bptr, F->bcol, (const T*)F->bval, nullptr, F->slot_node, W.r,
+                nullptr, work, nullptr);
+        }
+        for (int l = 0; l < L; ++l) {
+            const int64_t a = lp[l], b = lp[l + 1];
+            if (b <= a) continue;
+            k_trsv_level<T, true><<<(unsigned)((b - a + per_block - 1) / per_block), BLOCK, 0, s>>>(
+                a, b, nrhs, F->fptr, F->fcol, (const T*)F->fval, (const T*)F->dslot, F->slot_node,
+                nullptr, work, sol, W.z);
+        }
+        return hipGetLastError();
+    }
     k_mfill<T><<<fill_grid(n * nrhs), BLOCK, 0, s>>>(n * nrhs, work);
     k_mfill<T><<<fill_grid(n * nrhs), BLOCK, 0, s>>>(n * nrhs, sol);
     k_zero_u64<<<1, 64, 0, s>>>(W.claim, 2);
@@ -790,6 +868,60 @@ void remember_schedule(const TuneKey& k, const Sched& sc, float ms)
 
 }  // namespace
 
+// One application z = M^{-1} r to every system of a batched factor, on the schedule
+// asked for (0: the one tuned for this shape, else level by level where the plan has
+// levels, else the sync-free kernel; 1: the sync-free kernel, 2 blocks per CU and
+// claims of 16 slots; 2: level by level).
+int apply_batched_impl(srw_factor* F, int32_t nrhs, const double* R, double* Z, int32_t schedule,
+                       hipStream_t s)
+{
+    const bool has_levels = !F->level_ptr.empty() && F->head == 0;
+    if (schedule == 2 && !has_levels) {
+        set_last_error("srw_apply_batched: the factor's plan has no dependency levels");
+        return SRW_E_ARG;
+    }
+    BatchWork W;
+    W.N = F->n;
+    W.nrhs = nrhs;
+    const int64_t nv = W.N * nrhs;
+    const size_t vb = F->precision == SRW_FP32 ? sizeof(float) : sizeof(double);
+    const size_t o_flag = ((2 * nv * vb) + 255) & ~(size_t)255;
+    char* ws = nullptr;
+    SRW_HIP(hipMallocAsync((void**)&ws, o_flag + 128, s));
+    W.r = const_cast<double*>(R);
+    W.z = Z;
+    W.work = ws;
+    W.active = (int*)(ws + o_flag);
+    W.err = W.active + 1;
+    W.claim = (unsigned long long*)(ws + o_flag + 64);
+    W.wait_ticks = wait_ticks(5.0);
+    Sched sc{2, RPW * 2, 0};
+    if (schedule == 2) {
+        sc = Sched{1, RPW, 1};
+    } else if (schedule == 0) {
+        const Sched t = tuned_schedule(TuneKey{F->n, F->nnz_y, nrhs, F->precision});
+        if (t.per_cu) sc = t;
+        else if (has_levels) sc = Sched{1, RPW, 1};
+    }
+    k_zero_n<<<1, 64, 0, s>>>(W.err, 8);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = apply_b(F, W, sc, s);
+    int herr[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(herr, W.active, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const hipError_t fe = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = fe;
+    if (e != hipSuccess) {
+        set_last_error(hipGetErrorString(e));
+        return SRW_E_HIP;
+    }
+    if (herr[1] != 0) {
+        set_last_error("srw_apply_batched: a triangular solve gave up waiting");
+        return SRW_E_HIP;
+    }
+    return SRW_OK;
+}
+
 int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, int32_t max_iter,
                      double* X, int32_t* iters, double* rel, int32_t use_graph, hipStream_t s)
 {
@@ -887,6 +1019,20 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
         CK(apply_b(F, W, best_s, s));  // warm
+        if (!F->level_ptr.empty() && F->head == 0 && e == hipSuccess) {
+            const Sched cand{1, RPW, 1};
+            CK(apply_b(F, W, cand, s));  // warm
+            CK(hipEventRecord(e0, s));
+            CK(apply_b(F, W, cand, s));
+            CK(hipEventRecord(e1, s));
+            CK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) {
+                best = ms;
+                best_s = cand;
+            }
+        }
         for (int cap : {2, 1}) {
             for (int chunk : {RPW * 2, RPW * 4, RPW * 8}) {
                 if (e != hipSuccess) break;

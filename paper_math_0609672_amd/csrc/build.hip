@@ -986,6 +986,18 @@ __global__ void k_level_keys(int64_t n, int64_t h, const int32_t* __restrict__ s
     val[s] = (uint32_t)slot_node[s];
 }
 
+// ptr[k] = the first position of the sorted keys (head 0, level + 1 past it) holding
+// a key >= k, for k = 0 .. kmax + 1; every key up to kmax occurs
+__global__ void k_key_ptr(int64_t n, const uint32_t* __restrict__ key, uint32_t kmax,
+                          int64_t* __restrict__ ptr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const uint32_t lo = i == 0 ? 0u : key[i - 1] + 1u;
+    const uint32_t hi = i == n ? kmax + 1u : min(key[i], kmax + 1u);
+    for (uint32_t k = lo; k <= hi; ++k) ptr[k] = i;
+}
+
 __global__ void k_sum_u64(int64_t n, const uint64_t* __restrict__ x, unsigned long long* out)
 {
     uint64_t s = 0;
@@ -2021,6 +2033,13 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             uint32_t* ko;
             uint32_t* vo;
             CHECK_HIP(radix_sort_u32(lkey, lval, lkey2, lval2, n, bits, rt, &ko, &vo, s));
+            // the levels' slot ranges, for level-by-level substitutions
+            int64_t* kptr = ALLOC(tmp, int64_t, (size_t)depth + 2);
+            if (!kptr) FAIL(SRW_E_NOMEM);
+            k_key_ptr<<<grid_for(n + 1, BLOCK), BLOCK, 0, s>>>(n, ko, (uint32_t)depth, kptr);
+            F->level_ptr.assign((size_t)depth + 1, 0);
+            CHECK_HIP(hipMemcpyAsync(F->level_ptr.data(), kptr + 1, ((size_t)depth + 1) * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, s));
             k_copy_i32<<<g, BLOCK, 0, s>>>(n, (const int32_t*)vo, F->slot_node);
             k_invert<<<g, BLOCK, 0, s>>>(n, F->slot_node, F->node_slot);
             CHECK_HIP(relabel(F->yptr, F->ycol, F->yval, F->fptr, F->fcol, F->fval));

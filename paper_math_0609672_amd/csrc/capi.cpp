@@ -135,6 +135,19 @@ int srw_pcg_solve_batched(srw_factor* F, int32_t nrhs, const double* B, double t
     }
 }
 
+int srw_apply_batched(srw_factor* F, int32_t nrhs, const double* R, double* Z, int32_t schedule,
+                      void* stream)
+{
+    if (!F || F->nmat < 1 || nrhs < 1 || nrhs > 8 || schedule < 0 || schedule > 2) return SRW_E_ARG;
+    if (F->n == 0) return SRW_OK;
+    if (!R || !Z) return SRW_E_ARG;
+    try {
+        return srw::apply_batched_impl(F, nrhs, R, Z, schedule, as_stream(stream));
+    } catch (...) {
+        return SRW_E_HIP;
+    }
+}
+
 int srw_build_factor(const srw_csr* A, int32_t walks_per_row, double drop_tol, uint64_t seed,
                      const srw_options* opt, srw_factor** out, void* stream)
 {

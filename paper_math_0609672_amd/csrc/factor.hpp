@@ -52,6 +52,9 @@ struct srw_factor {
 
     // longest dependency chain of the triangular solves, -1 until srw_factor_depth
     int32_t depth = -1;
+    // level order: first slot of every dependency level past the head, and the end
+    // ([depth + 1]; empty for the rank order)
+    std::vector<int64_t> level_ptr;
 
     // asymmetric A (Section 7.1): the factor of the game of A^T with the same ordering
     // (owned); the preconditioner is then (Y_T^T D Y)^{-1}
@@ -217,6 +220,8 @@ int build_batched_impl(int32_t nmat, const srw_csr* A, int32_t walks_per_row, do
                        hipStream_t s);
 int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, int32_t max_iter,
                      double* X, int32_t* iters, double* rel, int32_t use_graph, hipStream_t s);
+int apply_batched_impl(srw_factor* F, int32_t nrhs, const double* R, double* Z, int32_t schedule,
+                       hipStream_t s);
 int features_impl(const srw_csr* A, const int32_t* rank, float* feat, hipStream_t s);
 int labels_impl(const srw_factor* F, int per_step, double* label, hipStream_t s);
 int walk_stats_impl(const srw_factor* F, double* var, double* mean_len, hipStream_t s);

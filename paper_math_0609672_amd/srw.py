@@ -97,6 +97,7 @@ _lib.srw_build_factor_batched.argtypes = [_I32, _P, _I32, _D, _P, ctypes.POINTER
                                           ctypes.POINTER(_P), _P]
 _lib.srw_batch_info.argtypes = [_P, ctypes.POINTER(_I32), _P]
 _lib.srw_pcg_solve_batched.argtypes = [_P, _I32, _P, _D, _I32, _P, _P, _P, _I32, _P]
+_lib.srw_apply_batched.argtypes = [_P, _I32, _P, _P, _I32, _P]
 _lib.srw_build_factor_ldu.argtypes = [ctypes.POINTER(_Csr), _I32, _D, _U64, ctypes.POINTER(_Options),
                                       ctypes.POINTER(_P), _P]
 _lib.srw_factor_transpose_game.argtypes = [_P, ctypes.POINTER(_P)]
@@ -113,7 +114,8 @@ EXPORTED = ["srw_default_options", "srw_build_factor", "srw_build_ic0", "srw_fac
             "srw_pcg_solve", "srw_apply", "srw_apply_noalloc", "srw_walk_stats", "srw_adaptive_budgets", "srw_ordering", "srw_row_features", "srw_budget_labels",
             "srw_mlp_forward", "srw_mlp_train_step", "srw_mlp_train_step_rows", "srw_budget_targets",
             "srw_mlp_standardize", "srw_mlp_budgets", "srw_build_factor_batched",
-            "srw_batch_info", "srw_pcg_solve_batched", "srw_last_error", "srw_status_string"]
+            "srw_batch_info", "srw_pcg_solve_batched", "srw_apply_batched", "srw_last_error",
+            "srw_status_string"]
 
 NOALLOC_MAX_N = 1 << 21  # SRW_NOALLOC_MAX_N
 MLP_PARAMS = 4801
@@ -560,6 +562,16 @@ def batch_info(F: Factor):
     _check(_lib.srw_batch_info(F.handle, ctypes.byref(nm), off.ctypes.data_as(ctypes.c_void_p)),
            "srw_batch_info")
     return nm.value, off.tolist()
+
+
+def apply_batched(F: Factor, R: torch.Tensor, Z=None, schedule: int = 0, stream=None):
+    """srw_apply_batched: Z = M^{-1} R for every system of a batched factor, R [N, nrhs]."""
+    if Z is None:
+        Z = torch.empty_like(R)
+    st = _lib.srw_apply_batched(F.handle, int(R.shape[1]), _ptr(R), _ptr(Z), int(schedule),
+                                _stream(stream))
+    _check(st, "srw_apply_batched")
+    return Z
 
 
 def pcg_solve_batched(F: Factor, B: torch.Tensor, tol: float, max_iter: int = 10000, X=None,

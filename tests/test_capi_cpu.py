@@ -43,6 +43,9 @@ def test_status_strings_and_argument_checks_without_gpu():
     assert lib.srw_build_factor(None, 64, ctypes.c_double(0.0), ctypes.c_uint64(0), None,
                                 ctypes.byref(out), None) == -1
     assert lib.srw_factor_info(None, None, None, None, None, None, None, None, None) == -1
+    # batched apply: null factor, nrhs and schedule out of range
+    for nrhs, sched in ((1, 0), (9, 0), (1, 3)):
+        assert lib.srw_apply_batched(None, nrhs, None, None, sched, None) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libsrw.so not built")

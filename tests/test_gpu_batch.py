@@ -215,3 +215,52 @@ def test_batched_rejects_given_ordering_and_bad_nrhs(srw):
         srw.pcg_solve_batched(single, B[: mats[0].n, :2], 1e-8)
     single.free()
     F.free()
+
+
+@pytest.mark.parametrize("precision,nrhs", [("fp64", 8), ("fp64", 3), ("fp32", 8)])
+def test_batched_apply_schedules_agree(srw, precision, nrhs):
+    """One preconditioner application (Section 2.2.2: a backward then a forward
+    substitution) on every system: the level-by-level and the sync-free substitutions
+    sum each row in the same order, so they agree bit for bit, and the tuned default
+    is one of them; in FP64 each system's z is the oracle's M^{-1} r within 1e-10."""
+    mats = batch_mats()
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    F = srw.build_factor_batched(Ms, 64, 1e-3, SEEDS, precision=precision)
+    _, off = srw.batch_info(F)
+    N = off[-1]
+    Rh = np.random.default_rng(40 + nrhs).standard_normal((N, nrhs))
+    Rh[off[1]:off[2], 0] = 0.0  # one system with r = 0
+    R = torch.as_tensor(Rh, device=DEV)
+    Z1 = np_(srw.apply_batched(F, R, schedule=1))
+    Z2 = np_(srw.apply_batched(F, R, schedule=2))
+    Z0 = np_(srw.apply_batched(F, R, schedule=0))
+    assert np.array_equal(Z1, Z2) and np.array_equal(Z0, Z2)
+    assert not np.any(Z2[off[1]:off[2], 0])
+    if precision == "fp64":
+        for i, A in enumerate(mats):
+            a, b = off[i], off[i + 1]
+            Fo = O.build_factor(A, 64, 1e-3, SEEDS[i])
+            for j in range(nrhs):
+                zo = O.apply(Fo, Rh[a:b, j])
+                if not np.any(zo):
+                    assert not np.any(Z2[a:b, j])
+                    continue
+                err = np.linalg.norm(Z2[a:b, j] - zo) / np.linalg.norm(zo)
+                assert err <= 1e-10, (i, j, err)
+    F.free()
+
+
+def test_batched_apply_rejects_bad_arguments(srw):
+    mats = batch_mats()[:2]
+    Ms = [srw.Matrix.from_host(A, DEV) for A in mats]
+    F = srw.build_factor_batched(Ms, 16, 0.0, SEEDS[:2])
+    N = sum(A.n for A in mats)
+    with pytest.raises(srw.SrwError):
+        srw.apply_batched(F, torch.zeros((N, 9), dtype=torch.float64, device=DEV))
+    with pytest.raises(srw.SrwError):
+        srw.apply_batched(F, torch.zeros((N, 2), dtype=torch.float64, device=DEV), schedule=3)
+    single = srw.build_factor(Ms[0], 16, 0.0, 1)
+    with pytest.raises(srw.SrwError):
+        srw.apply_batched(single, torch.zeros((mats[0].n, 2), dtype=torch.float64, device=DEV))
+    single.free()
+    F.free()

@@ -169,49 +169,43 @@ __global__ __launch_bounds__(BLOCK) void k_tile(Tiles tl, int nrhs, const int64_
     double acc[MAXR];
 #pragma unroll
     for (int j = 0; j < MAXR; ++j) acc[j] = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+    // one thread per (row, right-hand side): the tile's nrhs-wide rows are contiguous,
+    // so neighbouring threads touch neighbouring values
+    const int64_t f0 = r0 * nrhs;
+    const int nf = (int)((r1 - r0) * nrhs);  // <= TILE_ROWS * MAXR
+    for (int fr = threadIdx.x; fr < nf; fr += BLOCK) {
+        const int64_t f = f0 + fr;
+        const int j = fr % nrhs;
+        double add;
         if (OP == T_PQ || OP == T_RES) {
-            double s[MAXR];
-#pragma unroll
-            for (int j = 0; j < MAXR; ++j) s[j] = 0.0;
+            const int64_t i = r0 + fr / nrhs;
             const double* src = OP == T_PQ ? u : v;  // p, or x
-            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-                const double a = val[e];
-                const double* pc = src + (int64_t)col[e] * nrhs;
-#pragma unroll
-                for (int j = 0; j < MAXR; ++j)
-                    if (j < nrhs) s[j] += a * pc[j];
-            }
-#pragma unroll
-            for (int j = 0; j < MAXR; ++j) {
-                if (j >= nrhs) continue;
-                if (OP == T_PQ) {
-                    w[i * nrhs + j] = s[j];
-                    acc[j] += u[i * nrhs + j] * s[j];
-                } else {
-                    const double rv = u[i * nrhs + j] - s[j];  // b - A x
-                    w[i * nrhs + j] = rv;
-                    acc[j] += rv * rv;
-                }
+            double sum = 0.0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                sum += val[e] * src[(int64_t)col[e] * nrhs + j];
+            if (OP == T_PQ) {
+                w[f] = sum;
+                add = u[f] * sum;
+            } else {
+                const double rv = u[f] - sum;  // b - A x
+                w[f] = rv;
+                add = rv * rv;
             }
         } else if (OP == T_DOT || OP == T_BB) {
-#pragma unroll
-            for (int j = 0; j < MAXR; ++j)
-                if (j < nrhs) acc[j] += u[i * nrhs + j] * (OP == T_BB ? u[i * nrhs + j] : v[i * nrhs + j]);
+            add = u[f] * (OP == T_BB ? u[f] : v[f]);
         } else {  // T_UPD: x += alpha p, r -= alpha q (active systems)
-#pragma unroll
-            for (int j = 0; j < MAXR; ++j) {
-                if (j >= nrhs) continue;
-                const Sys& S = sys[(int64_t)m * nrhs + j];
-                double rv = r2[i * nrhs + j];
-                if (S.active) {
-                    w[i * nrhs + j] = w[i * nrhs + j] + S.alpha * u[i * nrhs + j];
-                    rv = rv - S.alpha * v[i * nrhs + j];
-                    r2[i * nrhs + j] = rv;
-                }
-                acc[j] += rv * rv;
+            const Sys& S = sys[(int64_t)m * nrhs + j];
+            double rv = r2[f];
+            if (S.active) {
+                w[f] = w[f] + S.alpha * u[f];
+                rv = rv - S.alpha * v[f];
+                r2[f] = rv;
             }
+            add = rv * rv;
         }
+#pragma unroll
+        for (int jj = 0; jj < MAXR; ++jj)
+            if (jj == j) acc[jj] += add;
     }
 #pragma unroll
     for (int j = 0; j < MAXR; ++j) {
@@ -508,6 +502,30 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_multi(int64_t n, int nrhs, int32
     }
 }
 
+// The MAXR = 8 values of a row (64 or 32 bytes, aligned to their size) in 16-byte loads.
+__device__ __forceinline__ void load_row8(const double* p, double (&x)[MAXR])
+{
+    const double2* q = (const double2*)p;
+#pragma unroll
+    for (int k = 0; k < MAXR / 2; ++k) {
+        const double2 v = q[k];
+        x[2 * k] = v.x;
+        x[2 * k + 1] = v.y;
+    }
+}
+__device__ __forceinline__ void load_row8(const float* p, float (&x)[MAXR])
+{
+    const float4* q = (const float4*)p;
+#pragma unroll
+    for (int k = 0; k < MAXR / 4; ++k) {
+        const float4 v = q[k];
+        x[4 * k] = v.x;
+        x[4 * k + 1] = v.y;
+        x[4 * k + 2] = v.z;
+        x[4 * k + 3] = v.w;
+    }
+}
+
 // Level-by-level substitution: one launch per dependency level of a level-ordered
 // plan, over the level's slots [a, b).  Every value a row reads was written by an
 // earlier launch, so there is no waiting and no flag.  A row takes RG lanes and its
@@ -539,9 +557,16 @@ __global__ __launch_bounds__(BLOCK) void k_trsv_level(int64_t a, int64_t b, int 
             const int32_t c = ok ? col[q] : 0;
             const T av = ok ? val[q] : T(0);
             const T* src = sol + (int64_t)c * nrhs;
+            T xv[MAXR];
+            if (nrhs == MAXR) {
+                load_row8(src, xv);  // a whole row of values in 16-byte loads
+            } else {
+#pragma unroll
+                for (int jr = 0; jr < MAXR; ++jr) xv[jr] = jr < nrhs ? src[jr] : T(0);
+            }
 #pragma unroll
             for (int jr = 0; jr < MAXR; ++jr) {
-                const T x = (ok && jr < nrhs) ? src[jr] : T(0);
+                const T x = ok ? xv[jr] : T(0);
                 acc[jr] += av * x;
             }
         }

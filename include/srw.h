@@ -385,10 +385,11 @@ int srw_batch_info(const srw_factor* F, int32_t* nmat, int64_t* row_off);
  * tolerance restarts from it (at most 3 restarts).  Dot products are reduced per
  * system in a fixed order; the triangular solves carry the nrhs values of a row
  * together.  use_graph = 1 captures one iteration in a HIP graph and replays it.  On
- * first use for a problem shape the solve schedule is picked by timing the
- * level-by-level substitutions (one launch per dependency level; batched factors are
- * level-ordered) and the sync-free ones at 2 and 1 blocks per CU with 16, 32 and 64
- * rows per work claim, and kept for the process.
+ * first use for a problem shape the solve schedule is picked by timing, and kept for
+ * the process: the level-by-level substitutions (one launch per dependency level;
+ * batched factors are level-ordered), then the sync-free ones at 2 and 1 blocks per CU
+ * with 16, 32 and 64 rows per work claim, the sweep ending as soon as a sync-free
+ * schedule is slower than the level-by-level one.
  * Host outputs (may be NULL): iters int32[nmat * nrhs] and rel_residual
  * float64[nmat * nrhs] (true residuals), system (i, j) at i * nrhs + j.  Returns SRW_OK
  * or SRW_NOT_CONVERGED (some system missed tol within max_iter). */

@@ -1039,12 +1039,17 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
     Sched sched = tuned_schedule(key);
     if (e == hipSuccess && sched.per_cu == 0) {
         float best = 1e30f;
-        Sched best_s{2, RPW * 4};
+        Sched best_s{2, RPW * 2};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
+        // level by level first, where the plan has levels; then the sync-free schedules,
+        // from the one that was fastest on every batch measured (2 blocks per CU, 16-slot
+        // claims): if even that one loses to the level-by-level solve, the rest are not
+        // timed
+        const bool levels = !F->level_ptr.empty() && F->head == 0;
         CK(apply_b(F, W, best_s, s));  // warm
-        if (!F->level_ptr.empty() && F->head == 0 && e == hipSuccess) {
+        if (levels && e == hipSuccess) {
             const Sched cand{1, RPW, 1};
             CK(apply_b(F, W, cand, s));  // warm
             CK(hipEventRecord(e0, s));
@@ -1077,8 +1082,9 @@ int pcg_batched_impl(srw_factor* F, int32_t nrhs, const double* B, double tol, i
                     best = ms;
                     best_s = cand;
                 }
+                if (best_s.level) break;
             }
-            if (tuning.per_cu) break;
+            if (tuning.per_cu || best_s.level) break;
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);

@@ -566,8 +566,12 @@ def batch_info(F: Factor):
 
 def apply_batched(F: Factor, R: torch.Tensor, Z=None, schedule: int = 0, stream=None):
     """srw_apply_batched: Z = M^{-1} R for every system of a batched factor, R [N, nrhs]."""
+    if R.dim() != 2 or R.dtype != torch.float64 or not R.is_contiguous():
+        raise ValueError("R must be a contiguous float64 [N, nrhs] tensor")
     if Z is None:
         Z = torch.empty_like(R)
+    elif Z.shape != R.shape or Z.dtype != torch.float64 or not Z.is_contiguous():
+        raise ValueError("Z must be a contiguous float64 tensor shaped like R")
     st = _lib.srw_apply_batched(F.handle, int(R.shape[1]), _ptr(R), _ptr(Z), int(schedule),
                                 _stream(stream))
     _check(st, "srw_apply_batched")

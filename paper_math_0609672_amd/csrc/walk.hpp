@@ -299,6 +299,7 @@ struct WalkArgs {
     uint32_t* rec_vis;
     uint32_t* rec_len;
     unsigned long long* queue;
+    uint32_t slab_claim;       // chunks a wave claims at once from a slab queue (>= 1)
     unsigned long long* deg_sum;
     int* err;
     // walk reuse: per-lane stacks of stack_depth entries {rank, node, position,
@@ -401,6 +402,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a, const uint4* recs)
     // wave-uniform chunk state
     ChunkDesc cd{};
     uint32_t c_next = 0, c_end = 0;
+    uint64_t c_cur = 0, c_lim = 0;  // the chunk held and the end of the range claimed
     bool done = false;
     const int home = 1 + (int)(blockIdx.x % NSLAB);
     int seg = 0, tried = 0;
@@ -431,17 +433,22 @@ __device__ __forceinline__ void walk_body(const WalkArgs& a, const uint4* recs)
             while (idle != 0) {
                 if (c_next >= c_end) {
                     // next chunk: long segment, then home slab, then the other slabs
-                    bool got = false;
-                    unsigned long long cidx = 0;
+                    // the next chunk of the range already claimed, else a new claim:
+                    // one chunk from the long segment, slab_claim from a slab
+                    bool got = c_cur + 1 < c_lim;
+                    unsigned long long cidx = got ? ++c_cur : 0ull;
                     while (!done && !got) {
                         const int sq = seg == 0 ? 0 : 1 + (home - 1 + tried) % NSLAB;
                         const unsigned long long size =
                             (unsigned long long)(a.bounds[sq + 1] - a.bounds[sq]);
+                        const unsigned long long k = sq == 0 ? 1ull : (unsigned long long)a.slab_claim;
                         const unsigned long long c =
-                            lane0_u64(atomicAdd(&a.queue[sq], lane == 0 ? 1ull : 0ull));
+                            lane0_u64(atomicAdd(&a.queue[sq], lane == 0 ? k : 0ull));
                         if (c < size) {
                             got = true;
                             cidx = (unsigned long long)a.bounds[sq] + c;
+                            c_cur = cidx;
+                            c_lim = (unsigned long long)a.bounds[sq] + (c + k < size ? c + k : size);
                         } else if (seg == 0) {
                             seg = 1;
                         } else if (++tried >= NSLAB) {

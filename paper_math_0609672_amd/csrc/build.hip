@@ -1612,10 +1612,10 @@ int build_factor_impl(const srw_csr* A, int32_t walks_per_row, double drop_tol, 
             wa.rec_vis = rec_vis;
             wa.rec_len = rec_len;
             wa.queue = queue;
-            // rows of small budgets: several slab chunks per claim, about CHUNK_WALKS
-            // walks (the walks do not depend on which wave runs them)
+            // several slab chunks per claim, about 4 CHUNK_WALKS walks (the walks do not
+            // depend on which wave runs them)
             wa.slab_claim = (uint32_t)std::min<int64_t>(
-                16, std::max<int64_t>(1, (int64_t)CHUNK_WALKS / std::max<int32_t>(1, max_budget)));
+                16, std::max<int64_t>(1, 4 * (int64_t)CHUNK_WALKS / std::max<int32_t>(1, max_budget)));
             wa.deg_sum = queue + NSEG;
             wa.err = err;
             int dev = 0, cus = 0;
